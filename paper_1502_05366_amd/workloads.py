@@ -1,0 +1,136 @@
+"""Seeded synthetic test matrices shaped like the paper's workloads.
+
+This module holds input generators only; it contains none of the
+factorization arithmetic.  The paper's experiments (Sec. 5) use
+A = U D V^* with U, V random matrices with orthonormal columns and a
+prescribed diagonal D (log-spaced spectra, "types I, II, III"); every
+generator below follows that recipe with an exactly known spectrum.
+
+Randomness comes from numpy's PCG64 generator seeded by the caller.  Haar
+(uniformly distributed) orthonormal factors come from the QR factorization of
+a Gaussian matrix with the column signs fixed by sign(diag(R)) (Mezzadri,
+"How to generate random matrices from the classical compact groups", 2007).
+"""
+
+import numpy as np
+
+C1_SHAPE = (2000, 1000)
+C2_SHAPE = (20000, 10000)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def haar(g, m, r):
+    """m x r matrix with orthonormal columns, Haar distributed."""
+    G = g.standard_normal((m, r))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def from_factors(U, s, V):
+    """U diag(s) V^T."""
+    return (U * s[None, :]) @ V.T
+
+
+def spectrum_matrix(m, n, s, seed):
+    """A = U diag(s) V^T with Haar U (m x r), V (n x r), r = len(s)."""
+    g = rng(seed)
+    r = len(s)
+    U = haar(g, m, r)
+    V = haar(g, n, r)
+    return from_factors(U, np.asarray(s, dtype=np.float64), V), U, V
+
+
+def logspace_type(m, n, kind, seed):
+    """Sec. 5 test matrices: sigma = logspace(0, -e, min(m,n)) with
+    e = 0.5 (type I), 2 (type II), 3.5 (type III)."""
+    e = {1: 0.5, 2: 2.0, 3: 3.5}[kind]
+    r = min(m, n)
+    s = np.logspace(0.0, -e, r)
+    A, U, V = spectrum_matrix(m, n, s, seed)
+    return A, s
+
+
+def c1_matrix(seed=0xC0FFEE00):
+    """2000 x 1000, sigma_j = 10^(-j/10) (j = 1..1000), Haar U and V."""
+    m, n = C1_SHAPE
+    s = 10.0 ** (-np.arange(1, n + 1) / 10.0)
+    A, _, _ = spectrum_matrix(m, n, s, seed)
+    return A, s
+
+
+def kron_haar_matrix(m1, r1, m2, n1, n2, s, seed):
+    """A = (U1[:, :r1] kron U2) diag(s) (V1 kron V2)^T.
+
+    U1 is m1 x m1 Haar, U2 is m2 x m2 Haar, V1 n1 x n1 Haar, V2 n2 x n2 Haar;
+    r1 * m2 = n1 * n2 = len(s).  Singular vector j of A is column j of each
+    Kronecker factor, so the spectrum is exactly s while A is dense and its
+    singular vectors are delocalized.  Assembled without forming the
+    Kronecker factors: rows (a, b) of W = diag(s) V^T are mapped by
+    U1[:, :r1] on a and by U2 on b.
+    """
+    g = rng(seed)
+    U1 = haar(g, m1, m1)[:, :r1]
+    U2 = haar(g, m2, m2)
+    V1 = haar(g, n1, n1)
+    V2 = haar(g, n2, n2)
+    r = r1 * m2
+    n = n1 * n2
+    assert r == len(s) and r == n
+    W = np.kron(V1.T, V2.T)                      # (V1 kron V2)^T, n x n
+    W *= np.asarray(s, dtype=np.float64)[:, None]
+    W = W.reshape(r1, m2, n)
+    T1 = np.matmul(U2[None, :, :], W)            # (r1, m2, n): U2 on index b
+    A = np.tensordot(U1, T1, axes=([1], [0]))    # (m1, m2, n): U1 on index a
+    return A.reshape(m1 * m2, n)
+
+
+def c2_matrix(seed=0xC0FFEE01, noise_std=1e-6):
+    """20000 x 10000, sigma_j = 1/j (j = 1..10000) plus i.i.d. N(0, noise_std^2).
+
+    Kronecker-Haar factors U = U1[:, :80] kron U2 (U1 160^2, U2 125^2) and
+    V = V1 kron V2 (100^2 each).  The noise E has ||E||_2 ~ noise_std *
+    (sqrt(m) + sqrt(n)) ~ 2.4e-4, so sigma_j(A) = 1/j +- 2.5e-4 (Weyl)."""
+    m, n = C2_SHAPE
+    s = 1.0 / np.arange(1, n + 1)
+    A = kron_haar_matrix(160, 80, 125, 100, 100, s, seed)
+    if noise_std:
+        g = rng(seed ^ 0x5A5A5A5A)
+        A += noise_std * g.standard_normal(A.shape)
+    return A, s
+
+
+def exact_rank_matrix(m, n, r, seed, decay=0.5):
+    """Rank-r A = U diag(s) V^T with s_j = decay^j (j = 0..r-1)."""
+    s = decay ** np.arange(r)
+    A, U, V = spectrum_matrix(m, n, s, seed)
+    return A, s, U, V
+
+
+def separated_skeleton_matrix(m, n, r, seed):
+    """A = U_r diag(d) E_pi^T with d_j = 2^(-j/4) (j = 0..r-1).
+
+    U_r is m x r Haar, pi an injective map of 0..r-1 into 0..n-1, and every
+    other column of A is zero.  A has rank r and orthogonal nonzero columns
+    of norms d_j, so any B with the same row space relation (B = Q^T A with
+    Q Q^T A = A) has orthogonal columns of the same norms: k steps of the
+    column-pivoted QR must return pi(0), .., pi(k-1) in that order, with a
+    16% norm margin between consecutive pivots.  Returns (A, pi, d)."""
+    g = rng(seed)
+    U = haar(g, m, r)
+    pi = g.permutation(n)[:r]
+    d = 2.0 ** (-np.arange(r) / 4.0)
+    A = np.zeros((m, n))
+    A[:, pi] = U * d[None, :]
+    return A, pi, d
+
+
+def integer_matrix(m, n, seed, lo=-8, hi=8):
+    """Small-integer entries: every product and sum of a GEMM is exact in
+    FP64 (and in FP32 for short enough reductions)."""
+    g = rng(seed)
+    return g.integers(lo, hi + 1, size=(m, n)).astype(np.float64)
