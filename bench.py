@@ -1,0 +1,200 @@
+"""Throughput of the randomized SVD + ID + CUR path on one MI355X.
+
+One step = one rsvd_decompose call on the 20000 x 10000 FP64 matrix with
+sigma_j = 1/j plus N(0, (1e-6)^2) noise, k = 200, p = 20, q = 2: the Gaussian
+sketch, 6 passes over A with CholeskyQR2 between them, the Jacobi SVD of the
+small factor with U, V, the k-step pivoted QR of B with T, and the CUR
+post-processing.  A is resident in HBM before timing starts.
+
+GFLOP/s counts the algorithmic work of the RSVD only:
+  F = 2(2q+2) m n l + (q+1)(2 m l^2 - 2/3 l^3) + (q+1)(2 n l^2 - 2/3 l^3)
+      + 2 (m + n) l k
+(passes, Householder-count orthonormalization, U and V); the ID and CUR work
+is timed but not credited.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RSVD GFLOP/s + % HBM roofline; BF16 vs FP64 speedup at stated σ error"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_flops(m, n, k, p, q):
+    l = min(k + p, m, n)
+    return (2 * (2 * q + 2) * m * n * l + (q + 1) * (2 * m * l * l - 2 * l ** 3 / 3)
+            + (q + 1) * (2 * n * l * l - 2 * l ** 3 / 3) + 2 * (m + n) * l * k)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(A, k, p, q, seed, budget_s=20.0):
+    """The FP64 oracle (RSVD + ID + CUR) on the first rows of the same A."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import rsvd as O
+
+    m, n = A.shape
+    ms = 2000
+    t = 0.0
+    while True:
+        As = np.ascontiguousarray(A[:ms])
+        t0 = time.perf_counter()
+        O.rsvd(As, k, p, q, seed)
+        O.cur(As, k, p, q, seed)
+        t = time.perf_counter() - t0
+        if t > budget_s / 3 or ms >= m:
+            break
+        ms = min(m, int(ms * min(4.0, max(1.5, budget_s / 3 / max(t, 1e-3)))))
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    f = alg_flops(ms, n, k, p, q)
+    return {"value": round(f / t / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "oracle RSVD+ID+CUR on the first %d of %d rows (%d x %d), k=%d p=%d q=%d, "
+                      "%.1f s; GFLOP/s with the same RSVD flop count" % (ms, m, ms, n, k, p, q, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pass-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1502_05366_amd import _lib, api, workloads as W
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m, n = W.C2_SHAPE
+    k, p, q, seed = 200, 20, 2, 0x5EED0001
+    l = min(k + p, m, n)
+    log("generating A %dx%d" % (m, n))
+    t0 = time.perf_counter()
+    A_np, _ = W.c2_matrix()
+    A = torch.from_numpy(A_np).to(dev)
+    torch.cuda.synchronize()
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+
+    h = api.handle(dev)
+    ops = api.OP_SVD | api.OP_ID | api.OP_CUR
+    wb = lib.rsvd_workspace_bytes(ops, api.F64, m, n, k, p, q)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    U = torch.empty((m, k), dtype=torch.float64, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty((n, k), dtype=torch.float64, device=dev)
+    J = torch.empty(n, dtype=torch.int64, device=dev)
+    T = torch.empty((k, n - k), dtype=torch.float64, device=dev)
+    Jr = torch.empty(k, dtype=torch.int64, device=dev)
+    Uc = torch.empty((k, k), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+
+    def step():
+        rc = lib.rsvd_decompose(h, api.F64, m, n, k, p, q, seed, P(A), n, P(U), k, P(S), P(V), k,
+                                P(J), P(T), n - k, P(Jr), P(Uc), k, P(work), wb, P(info), sp)
+        if rc != 0:
+            raise RuntimeError("rsvd_decompose returned %d" % rc)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    log("timed %d steps: %.3f ms/step (wall %.3f s)" % (args.steps, ms, wall))
+    flops = alg_flops(m, n, k, p, q)
+    gflops = flops / (ms * 1e-3) / 1e9
+    st = info.cpu().numpy()
+
+    # dominant kernel: one pass over A (Y = A X and Z = A^T X on the matrix
+    # cores), timed with events on the stream it runs on
+    X = torch.randn((n, l), dtype=torch.float64, device=dev)
+    Xm = torch.randn((m, l), dtype=torch.float64, device=dev)
+    Y = torch.empty((m, l), dtype=torch.float64, device=dev)
+    Z = torch.empty((n, l), dtype=torch.float64, device=dev)
+    pw = max(lib.rsvd_pass_workspace_bytes(api.F64, 0, m, n, l),
+             lib.rsvd_pass_workspace_bytes(api.F64, 1, m, n, l))
+    pwork = torch.empty(pw, dtype=torch.uint8, device=dev)
+    pass_ms = {}
+    for trans, Xt, Yt, name in ((0, X, Y, "A_X"), (1, Xm, Z, "At_X")):
+        for _ in range(3):
+            lib.rsvd_pass(h, api.F64, trans, m, n, l, P(A), n, P(Xt), l, P(Yt), l, P(pwork), pw, sp)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.pass_reps):
+            lib.rsvd_pass(h, api.F64, trans, m, n, l, P(A), n, P(Xt), l, P(Yt), l, P(pwork), pw, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pass_ms[name] = e0.elapsed_time(e1) / args.pass_reps
+    pass_flops = 2.0 * m * n * l
+    t_pass = 0.5 * (pass_ms["A_X"] + pass_ms["At_X"])
+    achieved = pass_flops / (t_pass * 1e-3) / 1e12
+    a_bytes = 8.0 * m * n
+    log("pass A X %.3f ms, A^T X %.3f ms" % (pass_ms["A_X"], pass_ms["At_X"]))
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "RSVD+ID+CUR, FP64 A 20000x10000, sigma_j=1/j + N(0,1e-12) noise, "
+                               "k=200 p=20 q=2, one rsvd_decompose call per step",
+                   "m": m, "n": n, "k": k, "p": p, "q": q, "l": l},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "pass over A (gemm_sk_kernel + fix-up), FP64 MFMA 16x16x4",
+                     "pass_ms": {kk: round(v, 4) for kk, v in pass_ms.items()},
+                     "pass_hbm_GBs": round(a_bytes / (t_pass * 1e-3) / 1e9, 1)},
+        "end_to_end_frac_of_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS, 4),
+        "info": [int(st[0]), int(st[1])],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

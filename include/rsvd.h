@@ -1,0 +1,172 @@
+/* rsvd.h -- randomized SVD, interpolative (ID) and CUR decompositions on one
+ * AMD Instinct MI355X (gfx950), after Voronin & Martinsson, "RSVDPACK:
+ * Implementations of randomized algorithms for computing the singular value,
+ * interpolative, and CUR decompositions of matrices on multi-core and GPU
+ * architectures" (arXiv:1502.05366).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix pointers are DEVICE pointers; the caller allocates every
+ *   input, output and workspace buffer.  The library allocates nothing per
+ *   call; the handle holds only immutable per-device facts.
+ * - Matrices are row-major: element (i, j) of an r x c matrix X with leading
+ *   dimension ldx (>= c) is X[i * ldx + j].  Index outputs are 0-based int64.
+ * - `dtype` selects the storage and pass precision of A (and of the
+ *   range-finder matrices): RSVD_F64 or RSVD_F32.  Gram matrices, Cholesky
+ *   factors, the small SVD and the pivoted QR always run in FP64.
+ * - All work is enqueued on `stream` (a hipStream_t, may be NULL for the null
+ *   stream); nothing synchronizes with the host.  Buffers must stay valid
+ *   until the stream has passed the call.
+ * - Return value (synchronous): RSVD_OK, -i when the i-th argument is invalid
+ *   (1-based, LAPACK convention), or a positive RSVD_ERR_* code.
+ * - Numerical status (asynchronous) goes to the device words info[0..1]:
+ *   info[0] is a bit set of RSVD_INFO_*, info[1] the numerical rank found by
+ *   the pivoted QR when RSVD_INFO_RANK is set.  Each call resets both words.
+ * - l = min(k + p, m, n) is the sample size; this build supports l <= 256 and
+ *   k <= l.  p >= 0, q >= 0, 1 <= k <= min(m, n).
+ * - The Gaussian test matrix is drawn from Philox4x32-10 (key = seed) with
+ *   Box-Muller normals: sketch entry (i, j) is normal number j*n + i of
+ *   stream 0 (see rsvd_sketch).
+ */
+#ifndef RSVD_H_
+#define RSVD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { RSVD_F64 = 0, RSVD_F32 = 1 } rsvd_dtype_t;
+
+enum {
+  RSVD_OK = 0,
+  RSVD_ERR_HIP = 1,         /* a HIP call failed (launch or device query)       */
+  RSVD_ERR_WORKSPACE = 2,   /* work_bytes smaller than the workspace query      */
+  RSVD_ERR_UNSUPPORTED = 3, /* valid arguments outside what this build supports */
+  RSVD_ERR_NO_DEVICE = 4    /* no HIP device with the requested index           */
+};
+
+enum {
+  RSVD_INFO_ORTH_FALLBACK = 1, /* orth met a numerically dependent column and
+                                  replaced it by a random one (rank-deficient Y) */
+  RSVD_INFO_JACOBI_CAP = 2,    /* the Jacobi SVD stopped at its sweep cap        */
+  RSVD_INFO_RANK = 4,          /* pivoted QR residual fell below the rank
+                                  tolerance before step k; info[1] = that step   */
+  RSVD_INFO_NONFINITE = 8,     /* NaN or Inf met in a Gram matrix                */
+  RSVD_INFO_BARRIER = 16       /* internal: a grid barrier hit its spin cap      */
+};
+
+typedef struct rsvd_handle_s* rsvd_handle_t;
+
+/* Operation selector of rsvd_workspace_bytes. */
+enum { RSVD_OP_SVD = 1, RSVD_OP_ID = 2, RSVD_OP_CUR = 4 };
+
+/* Create a handle for HIP device `device` (queries its compute-unit count).
+ * Returns RSVD_ERR_NO_DEVICE if it does not exist. */
+int rsvd_create(rsvd_handle_t* handle, int device);
+int rsvd_destroy(rsvd_handle_t handle);
+const char* rsvd_status_string(int code);
+
+/* Bytes of device workspace needed by rsvd_decompose (and rsvd_svd, rsvd_id,
+ * rsvd_cur) for the outputs selected by `ops` (a bit set of RSVD_OP_*).
+ * Pure host function of its arguments; 0 for invalid arguments. */
+size_t rsvd_workspace_bytes(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q);
+
+/* Rank-k randomized SVD, Alg. 5 of the paper (RSVD Version II) with the
+ * power scheme of Sec. 3.2 re-orthonormalized after every product (s = 1):
+ *   Y = A Omega;  q times { Q = orth(Y); Z = A^T Q; Z = orth(Z); Y = A Z };
+ *   Q = orth(Y);  B^T = A^T Q;  [Qh, Rh] = qr(B^T);  Rh = Uh diag(S) Vh^T;
+ *   U = Q Vh(:, 1:k),  V = Qh Uh(:, 1:k).
+ * A: m x n (lda >= n).  U: m x k (ldu >= k), V: n x k (ldv >= k), both of the
+ * type of A.  S: k FP64 values, descending.  A ~ U diag(S) V^T. */
+int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+             uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
+             void* V, int64_t ldv, void* work, size_t work_bytes, int32_t* info,
+             void* stream);
+
+/* Rank-k column ID computed from B = Q^T A (Sec. 3.5, last part; Alg. 1 on B):
+ * k steps of column-pivoted QR of B give the skeleton J[0..k) (pivot order)
+ * and T = S11^{-1} S12 (Sec. 2.4).  J: n int64, J[k..n) are the remaining
+ * columns in ascending order.  T: k x (n-k) FP64 (ldt >= n-k), its column j
+ * belongs to column J[k+j] of A.  With V = P [I_k; T^T] (V[J[i], :] = e_i,
+ * V[J[k+j], :] = T(:, j)^T), A ~ A(:, J[0..k)) V^T. */
+int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+            uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
+            void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/* Rank-k CUR from the two-sided ID (Sec. 2.5, Alg. 3; Sec. 3.6): Jc = skeleton
+ * columns of the ID above, Jr = the k rows chosen by k steps of column-pivoted
+ * QR of C^T (C = A(:, Jc)), and Ucur = V^T R^dagger (k x k FP64, lduc >= k),
+ * the least-squares solution of Ucur R = V^T with R = A(Jr, :):
+ * A ~ A(:, Jc) Ucur A(Jr, :). */
+int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+             uint64_t seed, const void* A, int64_t lda, int64_t* Jc, int64_t* Jr,
+             double* Ucur, int64_t lduc, void* work, size_t work_bytes, int32_t* info,
+             void* stream);
+
+/* One range finder, then any of the three decompositions of the same B.
+ * Output groups may be NULL to skip them: (U, S, V) for the SVD, (J, T) for
+ * the ID, (Jr, Ucur) for the CUR (the CUR needs the ID, which is then computed
+ * into the workspace when J/T are NULL; Jc = J[0..k)).  The workspace query
+ * must be made with the same set of ops. */
+int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                   uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu,
+                   double* S, void* V, int64_t ldv, int64_t* J, double* T, int64_t ldt,
+                   int64_t* Jr, double* Ucur, int64_t lduc, void* work, size_t work_bytes,
+                   int32_t* info, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Single steps of the path, exposed so that each can be checked on its own.
+ * ------------------------------------------------------------------------ */
+
+/* The n x l Gaussian test matrix (Fig. 1 step 1): Omega[i * ldo + j] = normal
+ * number j*n + i of stream 0, rounded to dtype; columns l..ldo-1 are zeroed. */
+int rsvd_sketch(rsvd_handle_t h, int dtype, uint64_t seed, int64_t n, int64_t l, void* Omega,
+                int64_t ldo, void* stream);
+
+/* Raw Philox4x32-10 words: out[4*i + r] = word r for counter
+ * (first + i, stream_id, batch) under key = seed.  out: 4*count uint32. */
+int rsvd_philox(rsvd_handle_t h, uint64_t seed, uint32_t stream_id, uint32_t batch,
+                uint64_t first, int64_t count, uint32_t* out, void* stream);
+
+/* One pass over A on the matrix cores: Y = A X (trans = 0; X n x l, Y m x l)
+ * or Y = A^T X (trans = 1; X m x l, Y n x l).  A, X, Y of type dtype. */
+size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int64_t l);
+int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64_t l,
+              const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy,
+              void* work, size_t work_bytes, void* stream);
+
+/* orth (Sec. 2.1): Q (rows x l, type dtype) with orthonormal columns and
+ * Y = Q R, by CholeskyQR2 in FP64; R (l x l FP64, upper triangular with a
+ * positive diagonal, zero below; may be NULL).  Dependent columns of Y are
+ * replaced by random vectors (RSVD_INFO_ORTH_FALLBACK); then Y = Q R holds
+ * only on the range of Y.  rows >= l, l <= 256. */
+size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l);
+int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
+              void* Q, int64_t ldq, double* R, int64_t ldr, uint64_t seed, void* work,
+              size_t work_bytes, int32_t* info, void* stream);
+
+/* Small SVD of Alg. 5: one-sided Jacobi on an l x l FP64 matrix Rh,
+ * Rh = Uh diag(S) Vh^T; the k largest singular values (descending) and the
+ * matching columns Uh (l x k, lduh >= k) and Vh (l x k, ldvh >= k). */
+size_t rsvd_small_svd_workspace_bytes(int64_t l);
+int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t ldr, double* S,
+                   double* Uh, int64_t lduh, double* Vh, int64_t ldvh, void* work,
+                   size_t work_bytes, int32_t* info, void* stream);
+
+/* k steps of column-pivoted QR of an r x c matrix B given by columns:
+ * column j of B is Bcols[j * ldb .. j * ldb + r) (type dtype), i.e. B^T in
+ * row-major.  Outputs as in rsvd_id: J (c), T (k x (c-k), ldt), and the pivot
+ * norms pivn (k FP64, may be NULL).  k <= min(r, c, 256). */
+size_t rsvd_cpqr_workspace_bytes(int64_t r, int64_t c, int k);
+int rsvd_cpqr(rsvd_handle_t h, int dtype, int64_t r, int64_t c, int k, const void* Bcols,
+              int64_t ldb, int64_t* J, double* T, int64_t ldt, double* pivn, void* work,
+              size_t work_bytes, int32_t* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H_ */

@@ -1,0 +1,19 @@
+"""Randomized SVD, interpolative (ID) and CUR decompositions on AMD MI355X.
+
+Python binding of librsvd.so (include/rsvd.h): argument marshalling only.
+Every step of the computation runs in the library's HIP kernels; PyTorch is
+used for device memory and streams.  Names follow the C entry points:
+
+    svd(A, k, p, q, seed)        -> U, S, V, info      (Alg. 5, s = 1)
+    id(A, k, p, q, seed)         -> J, T, info         (ID from B = Q^T A)
+    cur(A, k, p, q, seed)        -> Jc, Jr, U, info    (CUR from the two-sided ID)
+    decompose(A, k, p, q, seed)  -> dict with all three from one range finder
+
+and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
+"""
+
+from .api import (  # noqa: F401
+    RsvdError, handle, svd, id, cur, decompose, workspace_bytes, sketch, philox, pass_, orth,
+    small_svd, cpqr, INFO_ORTH_FALLBACK, INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER,
+    F64, F32,
+)

@@ -1,0 +1,280 @@
+"""Thin torch-facing wrappers of the C entry points in include/rsvd.h.
+
+Inputs and outputs are torch tensors on a HIP device; each wrapper allocates
+the outputs and the workspace with torch, passes raw device pointers and the
+current torch stream to the library, and raises RsvdError on a non-zero
+return code.  The numerical status words are returned as a 2-element int32
+device tensor (read it with .cpu() when needed).
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+F64 = 0
+F32 = 1
+
+INFO_ORTH_FALLBACK = 1
+INFO_JACOBI_CAP = 2
+INFO_RANK = 4
+INFO_NONFINITE = 8
+INFO_BARRIER = 16
+
+OP_SVD, OP_ID, OP_CUR = 1, 2, 4
+
+
+class RsvdError(RuntimeError):
+    pass
+
+
+_handles = {}
+
+
+def _dev_index(device):
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise RsvdError("tensors must be on a HIP device, got %s" % d)
+    return d.index if d.index is not None else torch.cuda.current_device()
+
+
+def handle(device=None):
+    """Per-device library handle (created once)."""
+    lib = _lib.load()
+    idx = _dev_index(device if device is not None else "cuda")
+    h = _handles.get(idx)
+    if h is None:
+        p = ctypes.c_void_p()
+        rc = lib.rsvd_create(ctypes.byref(p), idx)
+        _check(rc, "rsvd_create")
+        h = p
+        _handles[idx] = h
+    return h
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = _lib.load().rsvd_status_string(rc).decode()
+        raise RsvdError("%s failed: %s (code %d)" % (what, msg, rc))
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise RsvdError("A must be float64 or float32, got %s" % t.dtype)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _row_major(A):
+    if A.dim() != 2:
+        raise RsvdError("expected a matrix")
+    if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        A = A.contiguous()
+    return A
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def workspace_bytes(ops, dtype, m, n, k, p, q):
+    return int(_lib.load().rsvd_workspace_bytes(ops, dtype, m, n, k, p, q))
+
+
+def decompose(A, k, p, q, seed, svd=True, id=True, cur=True):
+    """One range finder, then the selected decompositions of the same B."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    ops = (OP_SVD if svd else 0) | (OP_ID if id else 0) | (OP_CUR if cur else 0)
+    wb = workspace_bytes(ops, dt, m, n, k, p, q)
+    if wb == 0:
+        raise RsvdError("invalid sizes")
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    out = {}
+    U = S = V = J = T = Jr = Uc = None
+    if svd:
+        U = torch.empty((m, k), dtype=A.dtype, device=dev)
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        V = torch.empty((n, k), dtype=A.dtype, device=dev)
+    if id or cur:
+        J = torch.empty(n, dtype=torch.int64, device=dev)
+        T = torch.empty((k, max(n - k, 1)), dtype=torch.float64, device=dev)
+    if cur:
+        Jr = torch.empty(k, dtype=torch.int64, device=dev)
+        Uc = torch.empty((k, k), dtype=torch.float64, device=dev)
+    rc = lib.rsvd_decompose(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0),
+                            _ptr(U), k if svd else 0, _ptr(S), _ptr(V), k if svd else 0,
+                            _ptr(J), _ptr(T), max(n - k, 1) if J is not None else 0,
+                            _ptr(Jr), _ptr(Uc), k if cur else 0,
+                            _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_decompose")
+    out["info"] = info
+    if svd:
+        out.update(U=U, S=S, V=V)
+    if id or cur:
+        out.update(J=J, T=T[:, :n - k])
+    if cur:
+        out.update(Jc=J[:k], Jr=Jr, Ucur=Uc)
+    out["workspace"] = work
+    return out
+
+
+def svd(A, k, p, q, seed):
+    """Rank-k randomized SVD: U (m x k), S (k, FP64, descending), V (n x k)."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    wb = workspace_bytes(OP_SVD, dt, m, n, k, p, q)
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    U = torch.empty((m, k), dtype=A.dtype, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty((n, k), dtype=A.dtype, device=dev)
+    rc = lib.rsvd_svd(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(U), k,
+                      _ptr(S), _ptr(V), k, _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_svd")
+    return U, S, V, info
+
+
+def id(A, k, p, q, seed):  # noqa: A001  (named after the C entry point)
+    """Rank-k column ID: J (n; skeleton J[:k]), T (k x (n-k)), info."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    work = _workspace(workspace_bytes(OP_ID, dt, m, n, k, p, q), dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    J = torch.empty(n, dtype=torch.int64, device=dev)
+    ldt = max(n - k, 1)
+    T = torch.empty((k, ldt), dtype=torch.float64, device=dev)
+    rc = lib.rsvd_id(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(J), _ptr(T),
+                     ldt, _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_id")
+    return J, T[:, :n - k], info
+
+
+def cur(A, k, p, q, seed):
+    """Rank-k CUR: Jc (k), Jr (k), U (k x k FP64), info; A ~ A[:, Jc] U A[Jr, :]."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    work = _workspace(workspace_bytes(OP_CUR, dt, m, n, k, p, q), dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    Jc = torch.empty(k, dtype=torch.int64, device=dev)
+    Jr = torch.empty(k, dtype=torch.int64, device=dev)
+    U = torch.empty((k, k), dtype=torch.float64, device=dev)
+    rc = lib.rsvd_cur(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(Jc),
+                      _ptr(Jr), _ptr(U), k, _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_cur")
+    return Jc, Jr, U, info
+
+
+# ------------------------------------------------------------------ steps --
+
+def sketch(n, l, seed, dtype=torch.float64, device="cuda", ldo=None):
+    lib = _lib.load()
+    ldo = l if ldo is None else ldo
+    om = torch.empty((n, ldo), dtype=dtype, device=device)
+    dt = F64 if dtype == torch.float64 else F32
+    rc = lib.rsvd_sketch(handle(om.device), dt, seed, n, l, _ptr(om), ldo, _stream(om.device))
+    _check(rc, "rsvd_sketch")
+    return om
+
+
+def philox(seed, stream_id, batch, first, count, device="cuda"):
+    """Raw Philox words as an int32 tensor of shape (count, 4) (bit patterns)."""
+    lib = _lib.load()
+    out = torch.empty((count, 4), dtype=torch.int32, device=device)
+    rc = lib.rsvd_philox(handle(out.device), seed, stream_id, batch, first, count, _ptr(out),
+                         _stream(out.device))
+    _check(rc, "rsvd_philox")
+    return out
+
+
+def pass_(A, X, trans=False):
+    """Y = A X (trans=False) or Y = A^T X (trans=True) on the matrix cores."""
+    lib = _lib.load()
+    A = _row_major(A)
+    X = _row_major(X)
+    m, n = A.shape
+    l = X.shape[1]
+    dt = _dtype_code(A)
+    rows = n if trans else m
+    Y = torch.empty((rows, l), dtype=A.dtype, device=A.device)
+    wb = lib.rsvd_pass_workspace_bytes(dt, int(trans), m, n, l)
+    work = _workspace(wb, A.device)
+    rc = lib.rsvd_pass(handle(A.device), dt, int(trans), m, n, l, _ptr(A), A.stride(0), _ptr(X),
+                       X.stride(0), _ptr(Y), l, _ptr(work), work.numel(), _stream(A.device))
+    _check(rc, "rsvd_pass")
+    return Y
+
+
+def orth(Y, seed=0, want_R=True):
+    """Q, R, info with Y = Q R, Q orthonormal (CholeskyQR2, FP64 Gram)."""
+    lib = _lib.load()
+    Y = _row_major(Y)
+    rows, l = Y.shape
+    dt = _dtype_code(Y)
+    Q = torch.empty((rows, l), dtype=Y.dtype, device=Y.device)
+    R = torch.empty((l, l), dtype=torch.float64, device=Y.device) if want_R else None
+    work = _workspace(lib.rsvd_orth_workspace_bytes(dt, rows, l), Y.device)
+    info = torch.zeros(2, dtype=torch.int32, device=Y.device)
+    rc = lib.rsvd_orth(handle(Y.device), dt, rows, l, _ptr(Y), Y.stride(0), _ptr(Q), l, _ptr(R),
+                       l, seed, _ptr(work), work.numel(), _ptr(info), _stream(Y.device))
+    _check(rc, "rsvd_orth")
+    return Q, R, info
+
+
+def small_svd(Rh, k):
+    """S (k), Uh (l x k), Vh (l x k), info with Rh = Uh diag(S) Vh^T (top k)."""
+    lib = _lib.load()
+    Rh = _row_major(Rh)
+    l = Rh.shape[0]
+    S = torch.empty(k, dtype=torch.float64, device=Rh.device)
+    Uh = torch.empty((l, k), dtype=torch.float64, device=Rh.device)
+    Vh = torch.empty((l, k), dtype=torch.float64, device=Rh.device)
+    work = _workspace(lib.rsvd_small_svd_workspace_bytes(l), Rh.device)
+    info = torch.zeros(2, dtype=torch.int32, device=Rh.device)
+    rc = lib.rsvd_small_svd(handle(Rh.device), l, k, _ptr(Rh), Rh.stride(0), _ptr(S), _ptr(Uh), k,
+                            _ptr(Vh), k, _ptr(work), work.numel(), _ptr(info), _stream(Rh.device))
+    _check(rc, "rsvd_small_svd")
+    return S, Uh, Vh, info
+
+
+def cpqr(Bcols, r, k):
+    """k-step column-pivoted QR of the r x c matrix whose column j is row j of
+    Bcols (c x >= r).  Returns J (c), T (k x (c-k)), pivot norms (k), info."""
+    lib = _lib.load()
+    Bcols = _row_major(Bcols)
+    c = Bcols.shape[0]
+    dt = _dtype_code(Bcols)
+    dev = Bcols.device
+    J = torch.empty(c, dtype=torch.int64, device=dev)
+    ldt = max(c - k, 1)
+    T = torch.empty((k, ldt), dtype=torch.float64, device=dev)
+    pv = torch.empty(k, dtype=torch.float64, device=dev)
+    work = _workspace(lib.rsvd_cpqr_workspace_bytes(r, c, k), dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    rc = lib.rsvd_cpqr(handle(dev), dt, r, c, k, _ptr(Bcols), Bcols.stride(0), _ptr(J), _ptr(T),
+                       ldt, _ptr(pv), _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_cpqr")
+    return J, T[:, :c - k], pv, info

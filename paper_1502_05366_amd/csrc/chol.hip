@@ -1,0 +1,393 @@
+// orth(Y) by CholeskyQR (the unpivoted QR `[Q, ~] = qr(Y, 0)` of Sec. 2.1,
+// used between the products of the power scheme of Sec. 3.2 and in Alg. 5):
+//   G = Y^T Y (FP64),  G = R^T R (Cholesky),  Q = Y R^{-1}  (triangular solve),
+// applied twice (CholeskyQR2) so that Q is orthonormal to working precision.
+//
+// Kernels here:
+//  * chol_kernel: one workgroup of 16 waves factors an lp x lp Gram matrix
+//    (lp <= 256) held in 16x16 matrix-core accumulator tiles (right-looking,
+//    block size 16).  It writes R (upper triangular, zero below), the inverses
+//    of its 16x16 diagonal blocks, and a flag per column.  A column whose
+//    Schur pivot is not above eta * G_jj (numerically dependent on the
+//    columns before it) gets a unit row in R, so it is removed from the
+//    factorization of the later columns and can be replaced afterwards.
+//  * trsm_kernel: Q = Y R^{-1} for a tall Y, one wave per 16 rows, column
+//    block by column block (Q_c = (Y_c - sum_{b<c} Q_b R_bc) R_cc^{-1}).
+//  * replace_kernel: overwrites flagged columns of Q with fresh Gaussian
+//    vectors (Philox stream 7) scaled to unit expected norm.
+//  * trmm_kernel: R = R2 R1 for the two passes.
+#include "common.h"
+#include "internal.h"
+
+namespace rsvd {
+namespace {
+
+constexpr int CH_NT = 1024;
+constexpr int CH_NW = CH_NT / 64;  // waves
+constexpr int MAXNB = 16;          // lp <= 256
+constexpr int MAXT = MAXNB * (MAXNB + 1) / 2;
+
+// Tile t of the row-major enumeration of the upper triangle of an nb x nb
+// tile grid: row a starts at t = a*nb - a*(a-1)/2.  Arguments are uniform.
+__device__ __forceinline__ int tile_row(int t, int nb) {
+  int a = 0;
+  while (a + 1 < nb && (a + 1) * nb - (a + 1) * a / 2 <= t) ++a;
+  return a;
+}
+__device__ __forceinline__ int tile_col(int t, int nb) {
+  const int a = tile_row(t, nb);
+  return a + (t - (a * nb - a * (a - 1) / 2));
+}
+
+// Load tile (a, b) of the symmetric G (upper triangle read; padding rows and
+// columns >= l are those of the identity) in accumulator layout.
+__device__ __forceinline__ d4 load_gtile(const double* G, int64_t ldg, int l, int a, int b,
+                                         int lane) {
+  d4 t;
+  const int col = b * 16 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = a * 16 + drow(lane >> 4, v);
+    double x;
+    if (row < l && col < l) {
+      x = (row <= col) ? G[(int64_t)row * ldg + col] : G[(int64_t)col * ldg + row];
+    } else {
+      x = (row == col) ? 1.0 : 0.0;
+    }
+    t[v] = x;
+  }
+  return t;
+}
+
+template <int TPW>   // tiles per wave: ceil(nb (nb + 1) / 2 / 16)
+__global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ G, int64_t ldg,
+                                                     int l, int lp, double eta,
+                                                     double* __restrict__ R, int64_t ldr,
+                                                     double* __restrict__ Rdinv,
+                                                     int32_t* __restrict__ dep, int32_t* info,
+                                                     int32_t* __restrict__ anomaly,
+                                                     const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int nb = lp / 16;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+
+  __shared__ double Dss[16 * 17];        // diagonal block being factored
+  __shared__ double Xss[16 * 16];        // its inverse
+  __shared__ double P[16 * 256];         // row panel of R (rows s*16 .. s*16+15)
+  __shared__ double Tw[CH_NW][16 * 16]; // per-wave transpose scratch
+  __shared__ int depblk[16];
+  __shared__ double diag0[256];
+
+  for (int j = tid; j < lp; j += CH_NT) diag0[j] = (j < l) ? G[(int64_t)j * ldg + j] : 1.0;
+  // zero the strictly lower part of R
+  for (int64_t e = tid; e < (int64_t)lp * lp; e += CH_NT) {
+    const int r = (int)(e / lp), c = (int)(e % lp);
+    if (r > c) R[(int64_t)r * ldr + c] = 0.0;
+  }
+  __syncthreads();
+  const int ntiles = nb * (nb + 1) / 2;
+
+  d4 acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + CH_NW * q;
+    if (t < ntiles) acc[q] = load_gtile(G, ldg, l, tile_row(t, nb), tile_col(t, nb), lane);
+    else acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  for (int s = 0; s < nb; ++s) {
+    // (a) the owner of tile (s, s) hands it to LDS
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + CH_NW * q;
+      if (t < ntiles && tile_row(t, nb) == s && tile_col(t, nb) == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dss[drow(lk, v) * 17 + li] = acc[q][v];
+      }
+    }
+    __syncthreads();
+    // (b) wave 0 factors the 16x16 block in LDS; lane c < 16 owns column c
+    if (wave == 0) {
+      const int c = lane;
+      for (int j = 0; j < 16; ++j) {
+        const double d = Dss[j * 17 + j];
+        const int gj = s * 16 + j;
+        const bool finite = isfinite(d);
+        const bool ok = finite && d > eta * diag0[gj];
+        const double rjj = ok ? sqrt(d) : 1.0;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (c < 16) {
+          if (c == j) Dss[j * 17 + j] = rjj;
+          else if (c > j) Dss[j * 17 + c] = ok ? Dss[j * 17 + c] / rjj : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (c < 16 && c > j) {
+          const double rjc = Dss[j * 17 + c];
+          for (int a = j + 1; a <= c; ++a) Dss[a * 17 + c] -= Dss[j * 17 + a] * rjc;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane == 0) {
+          depblk[j] = ok ? 0 : 1;
+          if (!ok && gj < l) {
+            dep[gj] = 1;
+            info_or(info, finite ? INFO_ORTH_FALLBACK : INFO_NONFINITE);
+          } else if (gj < l) {
+            dep[gj] = 0;
+          }
+          if (anomaly && gj < l && (!ok || d < 0.25 * diag0[gj] || d > 4.0 * diag0[gj]))
+            atomicOr(anomaly, 1);
+        }
+      }
+      // R_ss (zero below the diagonal) to LDS and to R
+      if (c < 16) {
+        for (int a = 0; a < 16; ++a) {
+          const double v = (a <= c) ? Dss[a * 17 + c] : 0.0;
+          Dss[a * 17 + c] = v;
+          R[(int64_t)(s * 16 + a) * ldr + s * 16 + c] = v;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // inverse of R_ss, column c by back substitution (x_i stored in Xss[i][c])
+      if (c < 16) {
+        for (int i = 15; i >= 0; --i) {
+          double acc_i = (i == c) ? 1.0 : 0.0;
+          for (int j = i + 1; j <= c; ++j) acc_i -= Dss[i * 17 + j] * Xss[j * 16 + c];
+          const double xi = (i <= c) ? acc_i / Dss[i * 17 + i] : 0.0;
+          Xss[i * 16 + c] = xi;
+          Rdinv[(int64_t)s * 256 + i * 16 + c] = xi;
+        }
+      }
+    }
+    __syncthreads();
+    // (c) panel: R_sb = R_ss^{-T} G_sb for b > s, zero rows of dependent columns
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + CH_NW * q;
+      if (t < ntiles && tile_row(t, nb) == s && tile_col(t, nb) > s) {
+        const int b = tile_col(t, nb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tw[wave][drow(lk, v) * 16 + li] = acc[q][v];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        d4 r = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lk;
+          const double av = Xss[k * 16 + li];          // (R_ss^{-T})[li][k]
+          const double bv = Tw[wave][k * 16 + li];     // G_sb[k][li]
+          r = Mfma<double>::mma(av, bv, r);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = drow(lk, v);
+          const double x = depblk[row] ? 0.0 : r[v];
+          r[v] = x;
+          P[row * 256 + b * 16 + li] = x;
+          R[(int64_t)(s * 16 + row) * ldr + b * 16 + li] = x;
+        }
+        acc[q] = r;
+      }
+    }
+    __syncthreads();
+    // (d) trailing update: G_ab -= R_sa^T R_sb for s < a <= b
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + CH_NW * q;
+      if (t < ntiles && tile_row(t, nb) > s) {
+        const int a = tile_row(t, nb), b = tile_col(t, nb);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lk;
+          const double av = -P[k * 256 + a * 16 + li];
+          const double bv = P[k * 256 + b * 16 + li];
+          acc[q] = Mfma<double>::mma(av, bv, acc[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Q = Y R^{-1}: one wave per 16 rows of Y.  Q_c = (Y_c - sum_{b<c} Q_b R_bc) Rinv_cc.
+template <typename TY, typename TQ>
+__global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int64_t ldy,
+                                                   int64_t M, int l, int lp,
+                                                   const double* __restrict__ R, int64_t ldr,
+                                                   const double* __restrict__ Rdinv,
+                                                   TQ* __restrict__ Q, int64_t ldq,
+                                                   const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ double Qs[4][16 * 257];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (row0 >= M) return;
+  double* qs = Qs[wave];
+  const int nb = lp / 16;
+  for (int c = 0; c < nb; ++c) {
+    d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = row0 + drow(lk, v);
+      const int col = c * 16 + li;
+      acc[v] = (r < M && col < l) ? (double)Y[r * ldy + col] : 0.0;
+    }
+    for (int b = 0; b < c; ++b) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + lk;
+        const double av = -qs[li * 257 + b * 16 + k];                       // Q_b[li][k]
+        const double bv = R[(int64_t)(b * 16 + k) * ldr + c * 16 + li];     // R_bc[k][li]
+        acc = Mfma<double>::mma(av, bv, acc);
+      }
+    }
+    // stage (Y_c - ...) to LDS, then multiply by Rinv_cc
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qs[drow(lk, v) * 257 + c * 16 + li] = acc[v];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kk + lk;
+      const double av = qs[li * 257 + c * 16 + k];
+      const double bv = Rdinv[(int64_t)c * 256 + k * 16 + li];
+      out = Mfma<double>::mma(av, bv, out);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = drow(lk, v);
+      qs[rr * 257 + c * 16 + li] = out[v];
+      const int64_t r = row0 + rr;
+      const int col = c * 16 + li;
+      if (r < M && col < l) Q[r * ldq + col] = (TQ)out[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
+// Replace every flagged column j of Q (M rows) by N(0, 1/M) entries from
+// Philox stream 7, counter pair index = j*M + i for normal (i, j), batch = call.
+__device__ __forceinline__ double normal_at(uint32_t k0, uint32_t k1, uint32_t sid, uint32_t batch,
+                                            uint64_t t) {
+  uint32_t c0 = (uint32_t)(t >> 1), c1 = (uint32_t)(t >> 33), c2 = sid, c3 = batch;
+  const uint32_t PM0 = 0xD2511F53u, PM1 = 0xCD9E8D57u, PW0 = 0x9E3779B9u, PW1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += PW0; k1 += PW1; }
+    const uint32_t hi0 = __umulhi(PM0, c0), lo0 = PM0 * c0;
+    const uint32_t hi1 = __umulhi(PM1, c2), lo1 = PM1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  const double a = (double)(c0 >> 5) * 67108864.0 + (double)(c1 >> 6);
+  const double b = (double)(c2 >> 5) * 67108864.0 + (double)(c3 >> 6);
+  const double u1 = (a + 1.0) * 0x1.0p-53, u2 = b * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1)), th = 6.283185307179586 * u2;
+  return (t & 1) ? r * sin(th) : r * cos(th);
+}
+
+template <typename TQ>
+__global__ __launch_bounds__(256) void replace_kernel(TQ* __restrict__ Q, int64_t ldq, int64_t M,
+                                                      int l, const int32_t* __restrict__ dep,
+                                                      uint64_t seed, uint32_t call) {
+  const double scale = 1.0 / sqrt((double)M);
+  for (int j = 0; j < l; ++j) {
+    if (!dep[j]) continue;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const double z = normal_at((uint32_t)seed, (uint32_t)(seed >> 32), 7u, call,
+                                 (uint64_t)j * (uint64_t)M + (uint64_t)i);
+      Q[i * ldq + j] = (TQ)(z * scale);
+    }
+  }
+}
+
+// C = A B for upper-triangular lp x lp A, B (C upper triangular, zero below).
+__global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am, int64_t lda,
+                                                   const double* __restrict__ Bm, int64_t ldb,
+                                                   double* __restrict__ C, int64_t ldc, int lp) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)lp * lp) return;
+  const int i = (int)(e / lp), j = (int)(e % lp);
+  double s = 0.0;
+  for (int k = i; k <= j; ++k) s += Am[(int64_t)i * lda + k] * Bm[(int64_t)k * ldb + j];
+  C[(int64_t)i * ldc + j] = (i <= j) ? s : 0.0;
+}
+
+__global__ void set_word_kernel(int32_t* w, int32_t v) { *w = v; }
+
+}  // namespace
+
+hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
+                       const int32_t* gate, hipStream_t s) {
+  if (lp > 256 || lp % 16) return hipErrorInvalidValue;
+  const int nb = lp / 16;
+  const int tpw = (int)cdiv(nb * (nb + 1) / 2, CH_NW);
+#define RSVD_CHOL(T)                                                                          \
+  hipLaunchKernelGGL(chol_kernel<T>, dim3(1), dim3(CH_NT), 0, s, G, ldg, l, lp, eta, R, ldr, \
+                     Rdinv, dep, info, anomaly, gate)
+  if (tpw <= 1) RSVD_CHOL(1);
+  else if (tpw <= 2) RSVD_CHOL(2);
+  else if (tpw <= 4) RSVD_CHOL(4);
+  else if (tpw <= 7) RSVD_CHOL(7);
+  else RSVD_CHOL(9);
+#undef RSVD_CHOL
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
+                       int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
+                       int64_t ldq, const int32_t* gate, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  const dim3 grid((unsigned)cdiv(M, 64));
+  if (!y_f32 && !q_f32)
+    hipLaunchKernelGGL((trsm_kernel<double, double>), grid, dim3(256), 0, s,
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, gate);
+  else if (y_f32 && q_f32)
+    hipLaunchKernelGGL((trsm_kernel<float, float>), grid, dim3(256), 0, s,
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, gate);
+  else if (y_f32 && !q_f32)
+    hipLaunchKernelGGL((trsm_kernel<float, double>), grid, dim3(256), 0, s,
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, gate);
+  else
+    hipLaunchKernelGGL((trsm_kernel<double, float>), grid, dim3(256), 0, s,
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
+                          uint64_t seed, uint32_t call, hipStream_t s) {
+  const int grid = (int)(cdiv(M, 256) < 1024 ? cdiv(M, 256) : 1024);
+  if (q_f32)
+    hipLaunchKernelGGL(replace_kernel<float>, dim3(grid), dim3(256), 0, s, (float*)Q, ldq, M, l,
+                       dep, seed, call);
+  else
+    hipLaunchKernelGGL(replace_kernel<double>, dim3(grid), dim3(256), 0, s, (double*)Q, ldq, M, l,
+                       dep, seed, call);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                             int64_t ldc, int lp, hipStream_t s) {
+  hipLaunchKernelGGL(trmm_kernel, dim3((unsigned)cdiv((int64_t)lp * lp, 256)), dim3(256), 0, s, A,
+                     lda, B, ldb, C, ldc, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(set_word_kernel, dim3(1), dim3(1), 0, s, w, v);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,389 @@
+// k steps of the column-pivoted QR (Sec. 2.3) of the short, wide B = Q^T A
+// (l x n), which selects the skeleton columns of the ID computed from B
+// (Sec. 3.5, last part) and, applied to C^T, the rows of the CUR (Sec. 2.5,
+// Sec. 3.6).  Then T = S11^{-1} S12 (Sec. 2.4) by back substitution.
+//
+// One cooperative launch of G workgroups; workgroup g keeps columns
+// [g*cs, (g+1)*cs) of B in LDS for the whole factorization.  Step s:
+//   1. each workgroup finds its unchosen column with the largest residual
+//      norm ||B(s:, j)|| (FP64, lowest column index on ties) and publishes
+//      the norm, the index and rows s.. of that column;
+//   2. grid barrier;
+//   3. every workgroup reads the G candidates, picks the global pivot the
+//      same way, builds the Householder reflector H = I - beta v v^T of the
+//      pivot column (v = x + sign(x_0)||x|| e_1, beta = 2 / v^T v) from the
+//      published values, and applies it to rows s.. of its unchosen columns;
+//   4. residual norms are recomputed exactly over rows s+1.. .
+// Chosen columns keep their place; the remaining columns are listed in
+// ascending index order.  The rank tolerance is max(r, c) * eps * ||B||_F.
+#include "common.h"
+#include "internal.h"
+
+namespace rsvd {
+namespace {
+
+constexpr int CQ_NT = 256;
+constexpr double DEPS = 2.220446049250313e-16;
+
+struct CpqrArgs {
+  const void* Bt; int64_t ldb;     // column j of B at Bt + j * ldb
+  int r; int64_t c; int k;
+  int G; int64_t cs; int rp;
+  double* slots;                   // [2][G][slot_len]
+  int64_t slot_len;
+  double* fro;                     // [G] partial ||B||_F^2
+  uint32_t* bar;                   // [3] barrier count, generation, abort flag
+  int64_t* J;                      // [c]
+  double* S11t;                    // column t = top k rows of pivot column t (ld = lds)
+  double* S12t;                    // column rho = top k rows of residual column rho
+  int64_t lds;
+  double* pivn;                    // [k] pivot norms
+  int32_t* info;                   // [2]
+};
+
+// Sense-free grid barrier: bar[0] counts arrivals, bar[1] is the generation,
+// bar[2] an abort flag.  A wait that exceeds its spin cap raises the abort
+// flag and INFO_BARRIER; every later barrier then returns at once, so the
+// kernel always runs to its end (results are then invalid and flagged).
+__device__ void grid_barrier(uint32_t* bar, uint32_t G, int32_t* info) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t* count = bar;
+    uint32_t* gen = bar + 1;
+    uint32_t* abort_flag = bar + 2;
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      const uint32_t my = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      const uint32_t old =
+          __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == G - 1) {
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
+          if (++spins > (1u << 22) ||
+              __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            info_or(info, INFO_BARRIER);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// block-wide reductions (CQ_NT threads)
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < CQ_NT / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// argmax of (val, idx): larger val wins, lower idx on equal val
+__device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t i2) {
+  return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+__device__ void block_argmax(double& v, int64_t& i, int& g, double* redv, int64_t* redi,
+                             int* redg) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int64_t oi = __shfl_xor(i, off, 64);
+    const int og = __shfl_xor(g, off, 64);
+    if (better(ov, oi, v, i)) { v = ov; i = oi; g = og; }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) { redv[wave] = v; redi[wave] = i; redg[wave] = g; }
+  __syncthreads();
+  v = redv[0]; i = redi[0]; g = redg[0];
+  for (int w = 1; w < CQ_NT / 64; ++w)
+    if (better(redv[w], redi[w], v, i)) { v = redv[w]; i = redi[w]; g = redg[w]; }
+  __syncthreads();
+}
+
+template <typename TB>
+__global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x;
+  const int64_t j0 = (int64_t)g * a.cs;
+  int64_t ncols = a.c - j0;
+  if (ncols > a.cs) ncols = a.cs;
+  if (ncols < 0) ncols = 0;
+  const int r = a.r, rp = a.rp;
+
+  double* slab = smem;                         // [cs][rp]
+  double* nrm = slab + a.cs * rp;              // [cs]
+  double* v = nrm + a.cs;                      // [rp]
+  int* chosen_at = (int*)(v + rp);             // [cs] step at which chosen, -1 if not
+  int64_t* piv = (int64_t*)(chosen_at + a.cs + (a.cs & 1));  // [k]
+  __shared__ double redv[CQ_NT / 64];
+  __shared__ int64_t redi[CQ_NT / 64];
+  __shared__ int redg[CQ_NT / 64];
+  __shared__ double red[CQ_NT / 64];
+  __shared__ double sh_beta, sh_alpha;
+
+  const TB* Bt = static_cast<const TB*>(a.Bt);
+  for (int64_t e = tid; e < ncols * rp; e += CQ_NT) {
+    const int64_t jj = e / rp;
+    const int i = (int)(e - jj * rp);
+    slab[e] = (i < r) ? (double)Bt[(j0 + jj) * a.ldb + i] : 0.0;
+  }
+  __syncthreads();
+  // initial norms and ||B||_F^2
+  double fpart = 0.0;
+  for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+    double s2 = 0.0;
+    for (int i = lane; i < r; i += 64) { const double x = slab[jj * rp + i]; s2 += x * x; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+    if (lane == 0) { nrm[jj] = s2; chosen_at[jj] = -1; }
+    fpart += (lane == 0) ? s2 : 0.0;
+  }
+  fpart = block_sum(fpart, red);
+  if (tid == 0) st_agent(a.fro + g, fpart);
+  __threadfence();
+  grid_barrier(a.bar, (uint32_t)a.G, a.info);
+  double fro2 = 0.0;
+  for (int w = 0; w < a.G; ++w) fro2 += ld_agent(a.fro + w);
+  const double tol = (double)(r > a.c ? r : a.c) * DEPS * sqrt(fro2);
+  int frank = a.k;
+
+  for (int s = 0; s < a.k; ++s) {
+    const int par = s & 1;
+    // 1. local candidate
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+    int bg = g;
+    for (int64_t jj = tid; jj < ncols; jj += CQ_NT) {
+      if (chosen_at[jj] >= 0) continue;
+      if (better(nrm[jj], j0 + jj, bv, bi)) { bv = nrm[jj]; bi = j0 + jj; }
+    }
+    block_argmax(bv, bi, bg, redv, redi, redg);
+    double* myslot = a.slots + ((int64_t)par * a.G + g) * a.slot_len;
+    if (tid == 0) {
+      st_agent(myslot + 0, bv);
+      st_agent(myslot + 1, (double)(bi == INT64_MAX ? -1 : bi));
+    }
+    if (bi != INT64_MAX) {
+      const int64_t jj = bi - j0;
+      for (int i = s + tid; i < r; i += CQ_NT) st_agent(myslot + 2 + i, slab[jj * rp + i]);
+    }
+    __threadfence();
+    grid_barrier(a.bar, (uint32_t)a.G, a.info);
+    // 3. global pivot
+    double gv = -1.0;
+    int64_t gi = INT64_MAX;
+    int gg = 0;
+    for (int w = tid; w < a.G; w += CQ_NT) {
+      const double* sl = a.slots + ((int64_t)par * a.G + w) * a.slot_len;
+      const double vv = ld_agent(sl + 0);
+      const double iv = ld_agent(sl + 1);
+      if (iv < 0.0) continue;
+      const int64_t ii = (int64_t)iv;
+      if (better(vv, ii, gv, gi)) { gv = vv; gi = ii; gg = w; }
+    }
+    block_argmax(gv, gi, gg, redv, redi, redg);
+    if (gi < 0 || gi >= a.c) { gi = 0; gg = 0; }     // only after an aborted barrier
+    const double pnorm = sqrt(gv > 0.0 ? gv : 0.0);
+    if (frank == a.k && pnorm <= tol) frank = s;
+    const double* psl = a.slots + ((int64_t)par * a.G + gg) * a.slot_len;
+    double xs2 = 0.0;
+    for (int i = s + tid; i < r; i += CQ_NT) {
+      const double x = ld_agent(psl + 2 + i);
+      v[i] = x;
+      xs2 += x * x;
+    }
+    xs2 = block_sum(xs2, red);           // also orders the writes of v
+    if (tid == 0) {
+      const double normx = sqrt(xs2);
+      const double x0 = v[s];
+      if (normx == 0.0) {
+        sh_beta = 0.0;
+        sh_alpha = 0.0;
+      } else {
+        const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+        v[s] = x0 + sg * normx;
+        sh_alpha = -sg * normx;
+        // v^T v = 2 ||x|| (||x|| + |x_0|)
+        sh_beta = 1.0 / (normx * (normx + fabs(x0)));
+      }
+      if (g == 0) {
+        a.J[s] = gi;
+        a.pivn[s] = pnorm;
+      }
+    }
+    __syncthreads();
+    const double beta = sh_beta, alpha = sh_alpha;
+    // apply H to the unchosen owned columns (one wave per column)
+    for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+      if (chosen_at[jj] >= 0) continue;
+      double* col = slab + jj * rp;
+      if (j0 + jj == gi) {
+        for (int i = s + lane; i < r; i += 64) col[i] = (i == s) ? alpha : 0.0;
+        if (lane == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
+        continue;
+      }
+      if (beta != 0.0) {
+        double w = 0.0;
+        for (int i = s + lane; i < r; i += 64) w += v[i] * col[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        w *= beta;
+        for (int i = s + lane; i < r; i += 64) col[i] -= w * v[i];
+      }
+      double s2 = 0.0;
+      for (int i = s + 1 + lane; i < r; i += 64) { const double x = col[i]; s2 += x * x; }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+      if (lane == 0) nrm[jj] = s2;
+    }
+    if (tid == 0) piv[s] = gi;
+    __syncthreads();
+  }
+  if (g == 0 && tid == 0 && frank < a.k) {
+    info_or(a.info, INFO_RANK);
+    a.info[1] = frank;
+  }
+  // outputs: top k rows of every owned column
+  for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+    const int64_t j = j0 + jj;
+    const int t = chosen_at[jj];
+    double* dst;
+    if (t >= 0) {
+      dst = a.S11t + (int64_t)t * a.lds;
+    } else {
+      int64_t before = 0;
+      for (int q = lane; q < a.k; q += 64) before += (piv[q] < j) ? 1 : 0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
+      const int64_t rho = j - before;
+      dst = a.S12t + rho * a.lds;
+      if (lane == 0) a.J[a.k + rho] = j;
+    }
+    for (int i = lane; i < a.k; i += 64) dst[i] = (i < r) ? slab[jj * rp + i] : 0.0;
+  }
+}
+
+// Upper-triangular solve with many right-hand sides, by back substitution
+// (x_i = (b_i - sum_{j>i} S_ij x_j) / S_ii, i = k-1 .. 0); one wave per
+// right-hand side.  Strided access: S(i, j) = S[i*s_r + j*s_c],
+// right-hand side `col` element i = Bm[col*b_c + i*b_r],
+// solution X(i, col) = X[i*x_r + col*x_c].  k <= 256.
+__global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__ S, int64_t s_r,
+                                                      int64_t s_c, const double* __restrict__ Bm,
+                                                      int64_t b_r, int64_t b_c, int k,
+                                                      int64_t nrhs, double* __restrict__ X,
+                                                      int64_t x_r, int64_t x_c) {
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= nrhs) return;
+  double x[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 64 * q + lane;
+    x[q] = (i < k) ? Bm[col * b_c + (int64_t)i * b_r] : 0.0;
+  }
+#pragma unroll
+  for (int q = 3; q >= 0; --q) {
+    for (int ll = 63; ll >= 0; --ll) {
+      const int i = 64 * q + ll;
+      if (i >= k) continue;
+      const double xi = __shfl(x[q], ll, 64) / S[(int64_t)i * s_r + (int64_t)i * s_c];
+      if (lane == ll) x[q] = xi;
+#pragma unroll
+      for (int q2 = 0; q2 <= q; ++q2) {
+        const int i2 = 64 * q2 + lane;
+        if (i2 < i) x[q2] -= S[(int64_t)i2 * s_r + (int64_t)i * s_c] * xi;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 64 * q + lane;
+    if (i < k) X[(int64_t)i * x_r + col * x_c] = x[q];
+  }
+}
+
+}  // namespace
+
+size_t cpqr_lds_bytes(int64_t cs, int rp, int k) {
+  return (size_t)(cs * rp + cs + rp) * sizeof(double) + (size_t)(cs + (cs & 1)) * sizeof(int) +
+         (size_t)k * sizeof(int64_t);
+}
+
+CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
+  CpqrPlan p;
+  p.rp = (int)rup(r, 2);
+  int64_t G = cdiv(c, 32);
+  if (G > ncu) G = ncu;
+  if (G < 1) G = 1;
+  p.G = (int)G;
+  p.cs = cdiv(c, G);
+  p.lds = cpqr_lds_bytes(p.cs, p.rp, k);
+  p.slot_len = 2 + p.rp;
+  p.ok = p.lds <= 150 * 1024 && k <= 256 && k <= r && k <= c;
+  return p;
+}
+
+size_t cpqr_work_bytes(const CpqrPlan& p) {
+  return (size_t)(2 * p.G * p.slot_len + p.G) * sizeof(double) + 64;
+}
+
+hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
+                       const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
+                       int64_t lds, double* pivn, int32_t* info, hipStream_t s) {
+  if (!p.ok) return hipErrorInvalidValue;
+  CpqrArgs a;
+  a.Bt = Bt; a.ldb = ldb; a.r = r; a.c = c; a.k = k;
+  a.G = p.G; a.cs = p.cs; a.rp = p.rp;
+  double* w = static_cast<double*>(work);
+  a.slots = w;
+  a.slot_len = p.slot_len;
+  a.fro = w + 2 * p.G * p.slot_len;
+  a.bar = reinterpret_cast<uint32_t*>(a.fro + p.G);
+  a.J = J; a.S11t = S11t; a.S12t = S12t; a.lds = lds; a.pivn = pivn; a.info = info;
+  hipError_t e = launch_set_word(reinterpret_cast<int32_t*>(a.bar), 0, s);
+  if (e == hipSuccess) e = launch_set_word(reinterpret_cast<int32_t*>(a.bar) + 2, 0, s);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
+  if (e != hipSuccess) return e;
+  e = hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const double* Bm,
+                          int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,
+                          int64_t x_c, hipStream_t s) {
+  if (nrhs <= 0 || k <= 0) return hipSuccess;
+  if (k > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)cdiv(nrhs, 4)), dim3(256), 0, s, S, s_r, s_c,
+                     Bm, b_r, b_c, k, nrhs, X, x_r, x_c);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

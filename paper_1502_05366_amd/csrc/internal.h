@@ -1,0 +1,99 @@
+// Internal launcher API shared by the kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace rsvd {
+
+// ---------------------------------------------------------------- sketch --
+// Omega[i * ldo + j] = normal number j*n + i of Philox stream `sid`
+// (rows i < n, columns j < l); columns l..ldo-1 are set to zero.
+hipError_t launch_sketch(bool f32, uint64_t seed, uint32_t sid, uint32_t batch, int64_t n,
+                         int64_t l, void* Omega, int64_t ldo, hipStream_t s);
+// raw Philox words: out[4*i + r] = word r of counter first+i of stream sid
+hipError_t launch_philox_words(uint64_t seed, uint32_t sid, uint32_t batch, uint64_t first,
+                               int64_t count, uint32_t* out, hipStream_t s);
+
+// ------------------------------------------------------------------ gemm --
+enum GemmTypes {      // element types A, X, compute, C
+  GEMM_DDDD = 0,
+  GEMM_FFFF = 1,
+  GEMM_FFDD = 2,
+  GEMM_FDDF = 3,
+  GEMM_DDDF = 4,
+};
+struct GemmPlan {
+  int64_t nrt, nct, KI, U, G;
+  int cbw, bm, bn;
+};
+GemmPlan plan_gemm(int64_t M, int64_t K, int64_t L, int ncu, int force_G);
+size_t gemm_part_bytes(const GemmPlan& p, size_t tc_size);
+hipError_t launch_gemm(GemmTypes ty, bool trans, const void* A, int64_t lda, const void* X,
+                       int64_t ldx, void* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
+                       const GemmPlan& p, void* part, size_t part_cap, hipStream_t s);
+
+}  // namespace rsvd
+
+namespace rsvd {
+
+// ------------------------------------------------------------------ orth --
+// One Cholesky factorization of an lp x lp Gram matrix (lp <= 256, lp % 16 == 0,
+// only rows/columns < l are read).  R upper triangular (zero below), Rdinv the
+// inverses of its 16x16 diagonal blocks (lp/16 blocks of 256 doubles), dep[j]
+// = 1 for columns declared dependent (pivot <= eta * G_jj).  `anomaly` (may be
+// null) is set when a pivot leaves [0.25, 4] * G_jj.  Kernels return at once
+// when `gate` is non-null and *gate == 0.
+hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
+                       const int32_t* gate, hipStream_t s);
+// Q = Y R^{-1} (M x l); Y and Q may be FP32 or FP64; arithmetic in FP64.
+hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
+                       int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
+                       int64_t ldq, const int32_t* gate, hipStream_t s);
+// overwrite the columns j with dep[j] != 0 of Q (M rows) by N(0, 1/M) values
+hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
+                          uint64_t seed, uint32_t call, hipStream_t s);
+// C = A B for upper-triangular lp x lp matrices
+hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                             int64_t ldc, int lp, hipStream_t s);
+hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s);
+
+// ---------------------------------------------------------------- jacobi --
+hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* Wwork, double* Vwork,
+                         int64_t ldw, double* S, double* Uh, int64_t lduh, double* Vh,
+                         int64_t ldvh, int max_sweeps, int32_t* info, hipStream_t s);
+
+// ------------------------------------------------------------------ cpqr --
+struct CpqrPlan {
+  int G;
+  int64_t cs;
+  int rp;
+  size_t lds;
+  int64_t slot_len;
+  bool ok;
+};
+CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu);
+size_t cpqr_work_bytes(const CpqrPlan& p);
+hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
+                       const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
+                       int64_t lds, double* pivn, int32_t* info, hipStream_t s);
+hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const double* Bm,
+                          int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,
+                          int64_t x_c, hipStream_t s);
+
+// ------------------------------------------------------------------- cur --
+hipError_t launch_gather_cols(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+                              const int64_t* J, int k, double* Crow, int64_t ldc, hipStream_t s);
+hipError_t launch_gather_rows_t(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+                                const int64_t* Jr, int k, double* Rt, int64_t ldr, hipStream_t s);
+// indices outside [0, in_rows) give zero rows (defensive; they never occur
+// when the pivoted QR succeeded)
+hipError_t launch_pick_rows(const double* In, int64_t ldi, int64_t in_rows, const int64_t* J,
+                            int64_t rows, int cols, double* Out, int64_t ldo, bool add,
+                            hipStream_t s);
+hipError_t launch_convert(const float* in, int64_t ldi, int64_t rows, int cols, double* out,
+                          int64_t ldo, hipStream_t s);
+
+}  // namespace rsvd

@@ -1,0 +1,677 @@
+// C-ABI of the randomized SVD / ID / CUR library: argument checks, workspace
+// layout and the order of kernel launches on the caller's stream.
+//
+// The path (Alg. 5 of the paper with s = 1, then the ID from B of Sec. 3.5 and
+// the CUR of Sec. 2.5 / 3.6):
+//   Omega = sketch(seed)                      Philox4x32-10 + Box-Muller
+//   Y = A Omega                               pass over A
+//   q times: Q = orth(Y); Z = A^T Q;          orth = CholeskyQR2 in FP64
+//            Zq = orth(Z); Y = A Zq
+//   Q = orth(Y); B^T = A^T Q
+//   SVD:  [Qh, Rh] = orth(B^T) (keep R); Jacobi: Rh = Uh S Vh^T;
+//         U = Q Vh_k, V = Qh Uh_k
+//   ID:   k-step CPQR of B -> J, S11, S12; T = S11^{-1} S12
+//   CUR:  C = A(:, J_k); k-step CPQR of C^T -> Jr; R = A(Jr, :);
+//         R^T = Qt Rt; U = (Qt(J_k, :) + T Qt(J_res, :)) Rt^{-T}
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "rsvd.h"
+#include "common.h"
+#include "internal.h"
+
+struct rsvd_handle_s {
+  int device;
+  int ncu;
+};
+
+namespace rsvd {
+namespace {
+
+constexpr int MAX_L = 256;
+constexpr int NCU_CAP = 256;          // workspace is sized for at most this many CUs
+constexpr double ETA_ORTH = 1e-13;    // Cholesky pivot / G_jj below which a column is dependent
+constexpr int JACOBI_MAX_SWEEPS = 40;
+
+struct Arena {
+  char* base;
+  size_t off;
+  explicit Arena(void* b) : base(static_cast<char*>(b)), off(0) {}
+  template <typename T> T* take(size_t count) {
+    const size_t o = (off + 255) & ~(size_t)255;
+    off = o + count * sizeof(T) + 256;
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+struct Shape {
+  int64_t m, n;
+  int k, p, q, l, lp, kp;
+  bool f32;
+  size_t dsz;
+  int ops;
+};
+
+Shape make_shape(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  Shape s;
+  s.m = m; s.n = n; s.k = k; s.p = p; s.q = q;
+  int64_t l = (int64_t)k + p;
+  l = std::min<int64_t>(l, std::min(m, n));
+  s.l = (int)l;
+  s.lp = (int)rup(l, 16);
+  s.kp = (int)rup(k, 16);
+  s.f32 = dtype == RSVD_F32;
+  s.dsz = s.f32 ? 4 : 8;
+  s.ops = ops;
+  return s;
+}
+
+// buffers of one orth (CholeskyQR2) call
+struct OrthBufs {
+  double *G, *R1, *R2, *Rd1, *Rd2, *Qa;
+  int32_t *dep, *dep2;
+  void* part;
+  size_t part_bytes;
+};
+
+struct Bufs {
+  void *Om, *Y, *Q, *Z, *Zq;
+  double *Qh, *Rh, *Wj, *Vj, *Uh, *Vh;
+  OrthBufs ob;
+  // ID
+  void* cq_work;
+  int64_t* J;
+  double *S11t, *S12t, *pivn, *T;
+  // CUR
+  double* Crow;
+  void* cq2_work;
+  int64_t* J2;
+  double *S11t2, *S12t2, *pivn2, *Rt, *Qt, *Rtt, *Qres, *Mb;
+};
+
+size_t max_part(const Shape& s) {
+  const int ncu = NCU_CAP;
+  size_t b = 0;
+  auto upd = [&](int64_t M, int64_t K, int64_t L) {
+    if (M <= 0 || K <= 0 || L <= 0) return;
+    b = std::max(b, gemm_part_bytes(plan_gemm(M, K, L, ncu, 0), 8));
+  };
+  upd(s.m, s.n, s.l);
+  upd(s.n, s.m, s.l);
+  upd(s.l, s.m, s.l);
+  upd(s.l, s.n, s.l);
+  upd(s.m, s.l, s.k);
+  upd(s.n, s.l, s.k);
+  upd(s.k, s.n, s.k);
+  upd(s.k, s.n - s.k, s.k);
+  return b;
+}
+
+size_t layout(const Shape& s, void* base, Bufs* out) {
+  Arena a(base);
+  Bufs b;
+  std::memset(&b, 0, sizeof(b));
+  const int64_t rmax = std::max(s.m, s.n);
+  b.Om = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  b.Y = a.take<char>((size_t)s.m * s.lp * s.dsz);
+  b.Q = a.take<char>((size_t)s.m * s.lp * s.dsz);
+  b.Z = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  b.Zq = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  b.ob.G = a.take<double>((size_t)s.lp * s.lp);
+  b.ob.R1 = a.take<double>((size_t)s.lp * s.lp);
+  b.ob.R2 = a.take<double>((size_t)s.lp * s.lp);
+  b.ob.Rd1 = a.take<double>((size_t)s.lp * 16);
+  b.ob.Rd2 = a.take<double>((size_t)s.lp * 16);
+  b.ob.Qa = a.take<double>((size_t)rmax * s.lp);
+  b.ob.dep = a.take<int32_t>(s.lp);
+  b.ob.dep2 = a.take<int32_t>(s.lp);
+  b.ob.part_bytes = max_part(s);
+  b.ob.part = a.take<char>(b.ob.part_bytes);
+  if (s.ops & RSVD_OP_SVD) {
+    b.Qh = a.take<double>((size_t)s.n * s.lp);
+    b.Rh = a.take<double>((size_t)s.lp * s.lp);
+    b.Wj = a.take<double>((size_t)s.lp * s.lp);
+    b.Vj = a.take<double>((size_t)s.lp * s.lp);
+    b.Uh = a.take<double>((size_t)s.lp * s.kp);
+    b.Vh = a.take<double>((size_t)s.lp * s.kp);
+  }
+  if (s.ops & (RSVD_OP_ID | RSVD_OP_CUR)) {
+    const CpqrPlan cp = plan_cpqr(s.l, s.n, s.k, NCU_CAP);
+    b.cq_work = a.take<char>(cpqr_work_bytes(cp));
+    b.J = a.take<int64_t>(s.n);
+    b.S11t = a.take<double>((size_t)s.k * s.kp);
+    b.S12t = a.take<double>((size_t)(s.n - s.k + 1) * s.kp);
+    b.pivn = a.take<double>(s.k);
+    b.T = a.take<double>((size_t)s.k * (s.n - s.k + 1));
+  }
+  if (s.ops & RSVD_OP_CUR) {
+    const CpqrPlan cp2 = plan_cpqr(s.k, s.m, s.k, NCU_CAP);
+    b.Crow = a.take<double>((size_t)s.m * s.kp);
+    b.cq2_work = a.take<char>(cpqr_work_bytes(cp2));
+    b.J2 = a.take<int64_t>(s.m);
+    b.S11t2 = a.take<double>((size_t)s.k * s.kp);
+    b.S12t2 = a.take<double>((size_t)(s.m - s.k + 1) * s.kp);
+    b.pivn2 = a.take<double>(s.k);
+    b.Rt = a.take<double>((size_t)s.n * s.kp);
+    b.Qt = a.take<double>((size_t)s.n * s.kp);
+    b.Rtt = a.take<double>((size_t)s.lp * s.lp);
+    b.Qres = a.take<double>((size_t)(s.n - s.k + 1) * s.kp);
+    b.Mb = a.take<double>((size_t)s.kp * s.kp);
+  }
+  if (out) *out = b;
+  return a.off;
+}
+
+struct Ctx {
+  hipStream_t st;
+  int ncu;
+  int32_t* info;
+  uint64_t seed;
+  uint32_t orth_calls;
+};
+
+#define RSVD_TRY(x)                         \
+  do {                                      \
+    hipError_t e_ = (x);                    \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+
+// Q = orth(Y) by CholeskyQR2 (rows x l); optionally R = R2 R1 (lp x lp, ldr).
+hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
+                int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
+                int64_t ldr) {
+  const int lp = (int)rup(l, 16);
+  const GemmPlan pg = plan_gemm(l, rows, l, std::min(c.ncu, NCU_CAP), 0);
+  // pass 1: G = Y^T Y, G = R1^T R1, Qa = Y R1^{-1}, dependent columns replaced
+  RSVD_TRY(launch_gemm(y_f32 ? GEMM_FFDD : GEMM_DDDD, true, Y, ldy, Y, ldy, ob.G, lp, l, rows, l,
+                       pg, ob.part, ob.part_bytes, c.st));
+  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, nullptr,
+                       nullptr, c.st));
+  RSVD_TRY(launch_trsm(y_f32, false, Y, ldy, rows, l, lp, ob.R1, lp, ob.Rd1, ob.Qa, lp, nullptr,
+                       c.st));
+  RSVD_TRY(launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st));
+  // pass 2 on Qa
+  RSVD_TRY(launch_gemm(GEMM_DDDD, true, ob.Qa, lp, ob.Qa, lp, ob.G, lp, l, rows, l, pg, ob.part,
+                       ob.part_bytes, c.st));
+  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, nullptr,
+                       nullptr, c.st));
+  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, nullptr,
+                       c.st));
+  if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, Rout, ldr, lp, c.st));
+  return hipSuccess;
+}
+
+hipError_t pass(Ctx& c, bool f32, bool trans, int64_t m, int64_t n, int l, const void* A,
+                int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* part,
+                size_t part_bytes) {
+  const int64_t M = trans ? n : m, K = trans ? m : n;
+  const GemmPlan pg = plan_gemm(M, K, l, std::min(c.ncu, NCU_CAP), 0);
+  return launch_gemm(f32 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l, pg, part,
+                     part_bytes, c.st);
+}
+
+struct Outs {
+  void* U; int64_t ldu; double* S; void* V; int64_t ldv;
+  int64_t* J; double* T; int64_t ldt;
+  int64_t* Jc; int64_t* Jr; double* Ucur; int64_t lduc;
+};
+
+hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, int64_t lda,
+                         const Outs& o) {
+  const bool f32 = s.f32;
+  const int l = s.l, lp = s.lp, k = s.k;
+  const int64_t m = s.m, n = s.n;
+  RSVD_TRY(launch_set_word(c.info, 0, c.st));
+  RSVD_TRY(launch_set_word(c.info + 1, 0, c.st));
+  // range finder
+  RSVD_TRY(launch_sketch(f32, c.seed, 0, 0, n, l, b.Om, lp, c.st));
+  RSVD_TRY(pass(c, f32, false, m, n, l, A, lda, b.Om, lp, b.Y, lp, b.ob.part, b.ob.part_bytes));
+  for (int j = 0; j < s.q; ++j) {
+    RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
+    RSVD_TRY(pass(c, f32, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes));
+    RSVD_TRY(orth(c, b.ob, f32, b.Z, lp, n, l, b.Zq, f32, lp, nullptr, 0));
+    RSVD_TRY(pass(c, f32, false, m, n, l, A, lda, b.Zq, lp, b.Y, lp, b.ob.part, b.ob.part_bytes));
+  }
+  RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
+  RSVD_TRY(pass(c, f32, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes));   // B^T
+  const int ncu = std::min(c.ncu, NCU_CAP);
+  if (o.U) {
+    // [Qh, Rh] = qr(B^T); Rh = Uh S Vh^T; U = Q Vh_k; V = Qh Uh_k
+    RSVD_TRY(orth(c, b.ob, f32, b.Z, lp, n, l, b.Qh, false, lp, b.Rh, lp));
+    RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, b.Vj, lp, o.S, b.Uh, s.kp, b.Vh, s.kp,
+                           JACOBI_MAX_SWEEPS, c.info, c.st));
+    const GemmPlan pu = plan_gemm(m, l, k, ncu, 0);
+    RSVD_TRY(launch_gemm(f32 ? GEMM_FDDF : GEMM_DDDD, false, b.Q, lp, b.Vh, s.kp, o.U, o.ldu, m, l,
+                         k, pu, b.ob.part, b.ob.part_bytes, c.st));
+    const GemmPlan pv = plan_gemm(n, l, k, ncu, 0);
+    RSVD_TRY(launch_gemm(f32 ? GEMM_DDDF : GEMM_DDDD, false, b.Qh, lp, b.Uh, s.kp, o.V, o.ldv, n,
+                         l, k, pv, b.ob.part, b.ob.part_bytes, c.st));
+  }
+  if (o.J || o.Jr) {
+    int64_t* J = o.J ? o.J : b.J;
+    double* T = o.T ? o.T : b.T;
+    const int64_t ldt = o.T ? o.ldt : (n - k);
+    const CpqrPlan cp = plan_cpqr(l, n, k, ncu);
+    RSVD_TRY(launch_cpqr(f32, b.Z, lp, l, n, k, cp, b.cq_work, J, b.S11t, b.S12t, s.kp, b.pivn,
+                         c.info, c.st));
+    RSVD_TRY(launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st));
+    if (o.Jr) {
+      // row selection on C^T = A(:, J_k)^T
+      RSVD_TRY(launch_gather_cols(f32, A, lda, m, n, J, k, b.Crow, s.kp, c.st));
+      const CpqrPlan cp2 = plan_cpqr(k, m, k, ncu);
+      RSVD_TRY(launch_cpqr(false, b.Crow, s.kp, k, m, k, cp2, b.cq2_work, b.J2, b.S11t2, b.S12t2,
+                           s.kp, b.pivn2, c.info, c.st));
+      // R^T = A(Jr, :)^T = Qt Rt
+      RSVD_TRY(launch_gather_rows_t(f32, A, lda, m, n, b.J2, k, b.Rt, s.kp, c.st));
+      RSVD_TRY(orth(c, b.ob, false, b.Rt, s.kp, n, k, b.Qt, false, s.kp, b.Rtt, s.kp));
+      // M = T Qt(J_res, :) + Qt(J_k, :)
+      RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J + k, n - k, k, b.Qres, s.kp, false, c.st));
+      if (n > k) {
+        const GemmPlan pm = plan_gemm(k, n - k, k, ncu, 0);
+        RSVD_TRY(launch_gemm(GEMM_DDDD, false, T, ldt, b.Qres, s.kp, b.Mb, s.kp, k, n - k, k, pm,
+                             b.ob.part, b.ob.part_bytes, c.st));
+        RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J, k, k, b.Mb, s.kp, true, c.st));
+      } else {
+        RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J, k, k, b.Mb, s.kp, false, c.st));
+      }
+      // U Rt^T = M  <=>  Rt U^T = M^T
+      RSVD_TRY(launch_backsub(b.Rtt, s.kp, 1, b.Mb, 1, s.kp, k, k, o.Ucur, 1, o.lduc, c.st));
+      RSVD_TRY(hipMemcpyAsync(o.Jr, b.J2, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, c.st));
+      if (o.Jc)
+        RSVD_TRY(hipMemcpyAsync(o.Jc, J, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, c.st));
+    }
+  }
+  return hipSuccess;
+}
+
+int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (k < 1 || k > std::min(m, n)) return -5;
+  if (p < 0) return -6;
+  if (q < 0) return -7;
+  return 0;
+}
+
+int finish(hipError_t e) { return e == hipSuccess ? RSVD_OK : RSVD_ERR_HIP; }
+
+}  // namespace
+}  // namespace rsvd
+
+using namespace rsvd;
+
+extern "C" {
+
+int rsvd_create(rsvd_handle_t* handle, int device) {
+  if (!handle) return -1;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return RSVD_ERR_NO_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RSVD_ERR_HIP;
+  rsvd_handle_s* h = new rsvd_handle_s;
+  h->device = device;
+  h->ncu = prop.multiProcessorCount;
+  *handle = h;
+  return RSVD_OK;
+}
+
+int rsvd_destroy(rsvd_handle_t handle) {
+  delete handle;
+  return RSVD_OK;
+}
+
+const char* rsvd_status_string(int code) {
+  if (code < 0) return "invalid argument";
+  switch (code) {
+    case RSVD_OK: return "ok";
+    case RSVD_ERR_HIP: return "HIP error";
+    case RSVD_ERR_WORKSPACE: return "workspace too small";
+    case RSVD_ERR_UNSUPPORTED: return "unsupported by this build";
+    case RSVD_ERR_NO_DEVICE: return "no such device";
+    default: return "unknown status";
+  }
+}
+
+size_t rsvd_workspace_bytes(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || m < 1 || n < 1 || k < 1 ||
+      k > std::min(m, n) || p < 0 || q < 0 || (ops & 7) == 0)
+    return 0;
+  if (ops & RSVD_OP_CUR) ops |= RSVD_OP_ID;
+  const Shape s = make_shape(ops, dtype, m, n, k, p, q);
+  return layout(s, nullptr, nullptr);
+}
+
+int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                   uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
+                   void* V, int64_t ldv, int64_t* J, double* T, int64_t ldt, int64_t* Jr,
+                   double* Ucur, int64_t lduc, void* work, size_t work_bytes, int32_t* info,
+                   void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  const bool svd = U || S || V;
+  if (svd) {
+    if (!U) return -11;
+    if (ldu < k) return -12;
+    if (!S) return -13;
+    if (!V) return -14;
+    if (ldv < k) return -15;
+  }
+  const bool id = J || T;
+  if (id) {
+    if (!J) return -16;
+    if (!T) return -17;
+    if (ldt < n - k) return -18;
+  }
+  const bool cur = Jr || Ucur;
+  if (cur) {
+    if (!Jr) return -19;
+    if (!Ucur) return -20;
+    if (lduc < k) return -21;
+  }
+  if (!svd && !id && !cur) return -11;
+  if (!work) return -22;
+  if (!info) return -24;
+  int ops = (svd ? RSVD_OP_SVD : 0) | (id ? RSVD_OP_ID : 0) | (cur ? RSVD_OP_CUR : 0);
+  if (cur) ops |= RSVD_OP_ID;
+  const Shape s = make_shape(ops, dtype, m, n, k, p, q);
+  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if ((id || cur) && !plan_cpqr(s.l, n, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
+  if (cur && !plan_cpqr(k, m, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
+  Bufs b;
+  const size_t need = layout(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
+  o.J = J; o.T = T; o.ldt = ldt;
+  o.Jr = Jr; o.Ucur = Ucur; o.lduc = lduc;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+             uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
+             void* V, int64_t ldv, void* work, size_t work_bytes, int32_t* info,
+             void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (!U) return -11;
+  if (ldu < k) return -12;
+  if (!S) return -13;
+  if (!V) return -14;
+  if (ldv < k) return -15;
+  if (!work) return -16;
+  if (!info) return -18;
+  const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
+  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  Bufs b;
+  const size_t need = layout(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+            uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
+            void* work, size_t work_bytes, int32_t* info, void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (!J) return -11;
+  if (!T) return -12;
+  if (ldt < n - k || ldt < 1) return -13;
+  if (!work) return -14;
+  if (!info) return -16;
+  const Shape s = make_shape(RSVD_OP_ID, dtype, m, n, k, p, q);
+  if (s.l > MAX_L || !plan_cpqr(s.l, n, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
+  Bufs b;
+  const size_t need = layout(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.J = J; o.T = T; o.ldt = ldt;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+             uint64_t seed, const void* A, int64_t lda, int64_t* Jc, int64_t* Jr,
+             double* Ucur, int64_t lduc, void* work, size_t work_bytes, int32_t* info,
+             void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (!Jc) return -11;
+  if (!Jr) return -12;
+  if (!Ucur) return -13;
+  if (lduc < k) return -14;
+  if (!work) return -15;
+  if (!info) return -17;
+  const Shape s = make_shape(RSVD_OP_CUR | RSVD_OP_ID, dtype, m, n, k, p, q);
+  if (s.l > MAX_L || !plan_cpqr(s.l, n, k, NCU_CAP).ok || !plan_cpqr(k, m, k, NCU_CAP).ok)
+    return RSVD_ERR_UNSUPPORTED;
+  Bufs b;
+  const size_t need = layout(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.Jc = Jc; o.Jr = Jr; o.Ucur = Ucur; o.lduc = lduc;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+// ---------------------------------------------------------------- stages --
+
+int rsvd_sketch(rsvd_handle_t h, int dtype, uint64_t seed, int64_t n, int64_t l, void* Omega,
+                int64_t ldo, void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (n < 0) return -4;
+  if (l < 0) return -5;
+  if (!Omega && n * l > 0) return -6;
+  if (ldo < l) return -7;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  return finish(launch_sketch(dtype == RSVD_F32, seed, 0, 0, n, l, Omega, ldo,
+                              static_cast<hipStream_t>(stream)));
+}
+
+int rsvd_philox(rsvd_handle_t h, uint64_t seed, uint32_t stream_id, uint32_t batch,
+                uint64_t first, int64_t count, uint32_t* out, void* stream) {
+  if (!h) return -1;
+  if (count < 0) return -6;
+  if (!out && count > 0) return -7;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  return finish(launch_philox_words(seed, stream_id, batch, first, count, out,
+                                    static_cast<hipStream_t>(stream)));
+}
+
+size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int64_t l) {
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || m < 1 || n < 1 || l < 1) return 0;
+  const int64_t M = trans ? n : m, K = trans ? m : n;
+  return gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8) + 256;
+}
+
+int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64_t l,
+              const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy,
+              void* work, size_t work_bytes, void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (trans != 0 && trans != 1) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (l < 1) return -6;
+  if (!A) return -7;
+  if (lda < n) return -8;
+  if (!X) return -9;
+  if (ldx < l) return -10;
+  if (!Y) return -11;
+  if (ldy < l) return -12;
+  if (work_bytes < rsvd_pass_workspace_bytes(dtype, trans, m, n, l)) return RSVD_ERR_WORKSPACE;
+  if (work_bytes > 256 && !work) return -13;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0};
+  return finish(pass(c, dtype == RSVD_F32, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy,
+                     work, work ? work_bytes : 0));
+}
+
+size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || l < 1 || rows < l || l > MAX_L) return 0;
+  const int lp = (int)rup(l, 16);
+  Arena a(nullptr);
+  a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
+  a.take<double>((size_t)rows * lp);
+  a.take<int32_t>(2 * (size_t)lp);
+  a.take<char>(gemm_part_bytes(plan_gemm(l, rows, l, NCU_CAP, 0), 8));
+  return a.off;
+}
+
+int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
+              void* Q, int64_t ldq, double* R, int64_t ldr, uint64_t seed, void* work,
+              size_t work_bytes, int32_t* info, void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (rows < 1) return -3;
+  if (l < 1 || l > rows) return -4;
+  if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (!Y) return -5;
+  if (ldy < l) return -6;
+  if (!Q) return -7;
+  if (ldq < l) return -8;
+  if (R && ldr < l) return -10;
+  if (!work) return -12;
+  if (work_bytes < rsvd_orth_workspace_bytes(dtype, rows, l)) return RSVD_ERR_WORKSPACE;
+  if (!info) return -14;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  const int lp = (int)rup(l, 16);
+  Arena a(work);
+  double* blk = a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
+  OrthBufs ob;
+  ob.G = blk;
+  ob.R1 = blk + (size_t)lp * lp;
+  ob.R2 = blk + 2 * (size_t)lp * lp;
+  double* Rfull = blk + 3 * (size_t)lp * lp;
+  ob.Rd1 = blk + 4 * (size_t)lp * lp;
+  ob.Rd2 = ob.Rd1 + (size_t)lp * 16;
+  ob.Qa = a.take<double>((size_t)rows * lp);
+  ob.dep = a.take<int32_t>(2 * (size_t)lp);
+  ob.dep2 = ob.dep + lp;
+  ob.part_bytes = gemm_part_bytes(plan_gemm(l, rows, l, NCU_CAP, 0), 8);
+  ob.part = a.take<char>(ob.part_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ctx c{st, h->ncu, info, seed, 0};
+  hipError_t e = launch_set_word(info, 0, st);
+  if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
+  const bool f32 = dtype == RSVD_F32;
+  if (e == hipSuccess) e = orth(c, ob, f32, Y, ldy, rows, (int)l, Q, f32, ldq, R ? Rfull : nullptr, lp);
+  if (e == hipSuccess && R)
+    e = hipMemcpy2DAsync(R, ldr * sizeof(double), Rfull, lp * sizeof(double), l * sizeof(double),
+                         l, hipMemcpyDeviceToDevice, st);
+  return finish(e);
+}
+
+size_t rsvd_small_svd_workspace_bytes(int64_t l) {
+  if (l < 1 || l > MAX_L) return 0;
+  return 2 * (size_t)l * l * sizeof(double) + 512;
+}
+
+int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t ldr, double* S,
+                   double* Uh, int64_t lduh, double* Vh, int64_t ldvh, void* work,
+                   size_t work_bytes, int32_t* info, void* stream) {
+  if (!h) return -1;
+  if (l < 1) return -2;
+  if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (k < 1 || k > l) return -3;
+  if (!Rh) return -4;
+  if (ldr < l) return -5;
+  if (!S) return -6;
+  if (!Uh) return -7;
+  if (lduh < k) return -8;
+  if (!Vh) return -9;
+  if (ldvh < k) return -10;
+  if (!work) return -11;
+  if (work_bytes < rsvd_small_svd_workspace_bytes(l)) return RSVD_ERR_WORKSPACE;
+  if (!info) return -13;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* W = static_cast<double*>(work);
+  double* V = W + (size_t)l * l;
+  hipError_t e = launch_set_word(info, 0, st);
+  if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
+  if (e == hipSuccess)
+    e = launch_jacobi(Rh, ldr, (int)l, k, W, V, l, S, Uh, lduh, Vh, ldvh, JACOBI_MAX_SWEEPS, info,
+                      st);
+  return finish(e);
+}
+
+size_t rsvd_cpqr_workspace_bytes(int64_t r, int64_t c, int k) {
+  if (r < 1 || c < 1 || k < 1 || k > std::min<int64_t>(std::min(r, c), 256)) return 0;
+  const CpqrPlan p = plan_cpqr((int)r, c, k, NCU_CAP);
+  if (!p.ok) return 0;
+  const int kp = (int)rup(k, 16);
+  Arena a(nullptr);
+  a.take<char>(cpqr_work_bytes(p));
+  a.take<double>((size_t)k * kp);
+  a.take<double>((size_t)(c - k + 1) * kp);
+  a.take<double>(k);
+  return a.off;
+}
+
+int rsvd_cpqr(rsvd_handle_t h, int dtype, int64_t r, int64_t c, int k, const void* Bcols,
+              int64_t ldb, int64_t* J, double* T, int64_t ldt, double* pivn, void* work,
+              size_t work_bytes, int32_t* info, void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (r < 1 || r > 65536) return -3;
+  if (c < 1) return -4;
+  if (k < 1 || k > std::min(r, c)) return -5;
+  if (k > 256) return RSVD_ERR_UNSUPPORTED;
+  if (!Bcols) return -6;
+  if (ldb < r) return -7;
+  if (!J) return -8;
+  if (!T && c > k) return -9;
+  if (ldt < c - k) return -10;
+  if (!work) return -12;
+  const CpqrPlan p = plan_cpqr((int)r, c, k, NCU_CAP);
+  if (!p.ok) return RSVD_ERR_UNSUPPORTED;
+  if (work_bytes < rsvd_cpqr_workspace_bytes(r, c, k)) return RSVD_ERR_WORKSPACE;
+  if (!info) return -14;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int kp = (int)rup(k, 16);
+  Arena a(work);
+  void* cw = a.take<char>(cpqr_work_bytes(p));
+  double* S11t = a.take<double>((size_t)k * kp);
+  double* S12t = a.take<double>((size_t)(c - k + 1) * kp);
+  double* pv = a.take<double>(k);
+  const CpqrPlan pr = plan_cpqr((int)r, c, k, std::min(h->ncu, NCU_CAP));
+  hipError_t e = launch_set_word(info, 0, st);
+  if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
+  if (e == hipSuccess)
+    e = launch_cpqr(dtype == RSVD_F32, Bcols, ldb, (int)r, c, k, pr, cw, J, S11t, S12t, kp, pv,
+                    info, st);
+  if (e == hipSuccess && c > k)
+    e = launch_backsub(S11t, 1, kp, S12t, 1, kp, k, c - k, T, ldt, 1, st);
+  if (e == hipSuccess && pivn)
+    e = hipMemcpyAsync(pivn, pv, sizeof(double) * k, hipMemcpyDeviceToDevice, st);
+  return finish(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* librsvd.so loads and exports every function declared in include/rsvd.h;
+* argument validation returns the documented negative codes before any
+  device work (a dummy non-null handle is enough for invalid arguments);
+* the workspace query is a pure function that grows with the problem.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1502_05366_amd import _lib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rsvd.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(rsvd_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares exactly those
+    assert sorted(_lib.SIGNATURES) == names
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced on the invalid-argument paths
+NULLP = None
+PTR = ctypes.c_void_p(0x2000)
+
+
+def svd_call(lib, **kw):
+    a = dict(h=FAKE, dtype=0, m=100, n=80, k=10, p=5, q=1, seed=1, A=PTR, lda=80, U=PTR, ldu=10,
+             S=PTR, V=PTR, ldv=10, work=PTR, wb=1 << 40, info=PTR, stream=NULLP)
+    a.update(kw)
+    return lib.rsvd_svd(a['h'], a['dtype'], a['m'], a['n'], a['k'], a['p'], a['q'], a['seed'],
+                        a['A'], a['lda'], a['U'], a['ldu'], a['S'], a['V'], a['ldv'], a['work'],
+                        a['wb'], a['info'], a['stream'])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(h=NULLP), -1), (dict(dtype=7), -2), (dict(m=0), -3), (dict(n=-1), -4),
+    (dict(k=0), -5), (dict(k=81), -5), (dict(p=-1), -6), (dict(q=-2), -7),
+    (dict(A=NULLP), -9), (dict(lda=79), -10), (dict(U=NULLP), -11), (dict(ldu=9), -12),
+    (dict(S=NULLP), -13), (dict(V=NULLP), -14), (dict(ldv=3), -15), (dict(work=NULLP), -16),
+    (dict(info=NULLP), -18), (dict(wb=16), 2), (dict(k=250, p=10, m=400, n=300, lda=300, ldu=250,
+                                                     ldv=250), 3),
+])
+def test_svd_argument_codes(lib, kw, code):
+    assert svd_call(lib, **kw) == code
+
+
+def test_id_cur_argument_codes(lib):
+    assert lib.rsvd_id(FAKE, 0, 50, 40, 5, 5, 1, 1, PTR, 40, NULLP, PTR, 35, PTR, 1 << 40, PTR,
+                       NULLP) == -11
+    assert lib.rsvd_id(FAKE, 0, 50, 40, 5, 5, 1, 1, PTR, 40, PTR, PTR, 34, PTR, 1 << 40, PTR,
+                       NULLP) == -13
+    assert lib.rsvd_cur(FAKE, 1, 50, 40, 5, 5, 1, 1, PTR, 40, PTR, PTR, PTR, 4, PTR, 1 << 40,
+                        PTR, NULLP) == -14
+    assert lib.rsvd_cur(FAKE, 1, 50, 40, 5, 5, 1, 1, PTR, 40, PTR, PTR, PTR, 5, PTR, 8,
+                        PTR, NULLP) == 2
+
+
+def test_status_strings(lib):
+    assert lib.rsvd_status_string(0) == b"ok"
+    assert lib.rsvd_status_string(-3) == b"invalid argument"
+    assert lib.rsvd_status_string(2) == b"workspace too small"
+
+
+def test_workspace_query(lib):
+    w = lib.rsvd_workspace_bytes
+    assert w(1, 0, 100, 80, 10, 5, 1) > 0
+    assert w(0, 0, 100, 80, 10, 5, 1) == 0           # no op selected
+    assert w(1, 0, 100, 80, 90, 5, 1) == 0           # k > min(m, n)
+    small = w(1, 0, 2000, 1000, 20, 10, 1)
+    big = w(1, 0, 20000, 10000, 200, 20, 2)
+    assert big > small
+    # the FP64 C2 sizes fit comfortably in one GPU's HBM
+    assert w(7, 0, 20000, 10000, 200, 20, 2) < 4 << 30
+    assert w(7, 1, 20000, 10000, 200, 20, 2) < w(7, 0, 20000, 10000, 200, 20, 2)
+    assert w(4, 0, 300, 200, 10, 5, 1) == w(6, 0, 300, 200, 10, 5, 1)
+
+
+def test_step_workspace_queries(lib):
+    assert lib.rsvd_orth_workspace_bytes(0, 1000, 30) > 0
+    assert lib.rsvd_orth_workspace_bytes(0, 10, 30) == 0
+    assert lib.rsvd_orth_workspace_bytes(0, 1000, 300) == 0
+    assert lib.rsvd_small_svd_workspace_bytes(220) >= 2 * 220 * 220 * 8
+    assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 200) > 0
+    assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 300) == 0
+    assert lib.rsvd_pass_workspace_bytes(0, 0, 20000, 10000, 220) > 0
