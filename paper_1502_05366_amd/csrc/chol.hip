@@ -4,7 +4,7 @@
 // applied twice (CholeskyQR2) so that Q is orthonormal to working precision.
 //
 // Kernels here:
-//  * chol_kernel: one workgroup of 16 waves factors an lp x lp Gram matrix
+//  * chol_kernel: one workgroup of 8 waves factors an lp x lp Gram matrix
 //    (lp <= 256) held in 16x16 matrix-core accumulator tiles (right-looking,
 //    block size 16).  It writes R (upper triangular, zero below), the inverses
 //    of its 16x16 diagonal blocks, and a flag per column.  A column whose
@@ -22,10 +22,12 @@
 namespace rsvd {
 namespace {
 
-constexpr int CH_NT = 1024;
+constexpr int CH_NT = 512;
 constexpr int CH_NW = CH_NT / 64;  // waves
 constexpr int MAXNB = 16;          // lp <= 256
 constexpr int MAXT = MAXNB * (MAXNB + 1) / 2;
+
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
 // Tile t of the row-major enumeration of the upper triangle of an nb x nb
 // tile grid: row a starts at t = a*nb - a*(a-1)/2.  Arguments are uniform.
@@ -82,10 +84,8 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
 
   for (int j = tid; j < lp; j += CH_NT) diag0[j] = (j < l) ? G[(int64_t)j * ldg + j] : 1.0;
   // zero the strictly lower part of R
-  for (int64_t e = tid; e < (int64_t)lp * lp; e += CH_NT) {
-    const int r = (int)(e / lp), c = (int)(e % lp);
-    if (r > c) R[(int64_t)r * ldr + c] = 0.0;
-  }
+  for (int r = 1 + (tid >> 6); r < lp; r += CH_NT / 64)
+    for (int c = tid & 63; c < r; c += 64) R[(int64_t)r * ldr + c] = 0.0;
   __syncthreads();
   const int ntiles = nb * (nb + 1) / 2;
 
@@ -108,60 +108,69 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
       }
     }
     __syncthreads();
-    // (b) wave 0 factors the 16x16 block in LDS; lane c < 16 owns column c
+    // (b) wave 0 factors the 16x16 block held in its 64 lanes (accumulator
+    // layout: lane (g, c) element v is row 4v + g, column c) and inverts it
     if (wave == 0) {
-      const int c = lane;
+      const int g = lk, c = li;
+      double x[4], y[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[v] = Dss[drow(g, v) * 17 + c];
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double d = Dss[j * 17 + j];
-        const int gj = s * 16 + j;
+        const int vj = j >> 2, gj_lane = 16 * (j & 3);
+        const double d = shfl_d(x[vj], gj_lane + j);
+        const int gcol = s * 16 + j;
         const bool finite = isfinite(d);
-        const bool ok = finite && d > eta * diag0[gj];
+        const bool ok = finite && d > eta * diag0[gcol];
         const double rjj = ok ? sqrt(d) : 1.0;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (c < 16) {
-          if (c == j) Dss[j * 17 + j] = rjj;
-          else if (c > j) Dss[j * 17 + c] = ok ? Dss[j * 17 + c] / rjj : 0.0;
+        // row j of R for this lane's column c
+        double rj = shfl_d(x[vj], gj_lane + c);
+        if (c == j) rj = rjj;
+        else if (c > j) rj = ok ? rj / rjj : 0.0;
+        else rj = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = drow(g, v);
+          const double rja = shfl_d(rj, a);        // R[j][a] from any lane of column a
+          if (a > j && a <= c) x[v] -= rja * rj;
+          if (a == j) x[v] = rj;
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (c < 16 && c > j) {
-          const double rjc = Dss[j * 17 + c];
-          for (int a = j + 1; a <= c; ++a) Dss[a * 17 + c] -= Dss[j * 17 + a] * rjc;
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         if (lane == 0) {
           depblk[j] = ok ? 0 : 1;
-          if (!ok && gj < l) {
-            dep[gj] = 1;
-            info_or(info, finite ? INFO_ORTH_FALLBACK : INFO_NONFINITE);
-          } else if (gj < l) {
-            dep[gj] = 0;
+          if (gcol < l) {
+            dep[gcol] = ok ? 0 : 1;
+            if (!ok) info_or(info, finite ? INFO_ORTH_FALLBACK : INFO_NONFINITE);
+            if (anomaly && (!ok || d < 0.25 * diag0[gcol] || d > 4.0 * diag0[gcol]))
+              atomicOr(anomaly, 1);
           }
-          if (anomaly && gj < l && (!ok || d < 0.25 * diag0[gj] || d > 4.0 * diag0[gj]))
-            atomicOr(anomaly, 1);
         }
       }
-      // R_ss (zero below the diagonal) to LDS and to R
-      if (c < 16) {
-        for (int a = 0; a < 16; ++a) {
-          const double v = (a <= c) ? Dss[a * 17 + c] : 0.0;
-          Dss[a * 17 + c] = v;
-          R[(int64_t)(s * 16 + a) * ldr + s * 16 + c] = v;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = drow(g, v);
+        if (a > c) x[v] = 0.0;
+        y[v] = (a == c) ? 1.0 : 0.0;
+      }
+      // X = R_ss^{-1} by back substitution on all columns at once
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        const int vi = i >> 2, gi_lane = 16 * (i & 3);
+        const double rii = shfl_d(x[vi], gi_lane + i);
+        const double xi = shfl_d(y[vi], gi_lane + c) / rii;     // X[i][c]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = drow(g, v);
+          const double rai = shfl_d(x[v], 16 * g + i);          // R[a][i]
+          if (a < i) y[v] -= rai * xi;
+          if (a == i) y[v] = xi;
         }
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      // inverse of R_ss, column c by back substitution (x_i stored in Xss[i][c])
-      if (c < 16) {
-        for (int i = 15; i >= 0; --i) {
-          double acc_i = (i == c) ? 1.0 : 0.0;
-          for (int j = i + 1; j <= c; ++j) acc_i -= Dss[i * 17 + j] * Xss[j * 16 + c];
-          const double xi = (i <= c) ? acc_i / Dss[i * 17 + i] : 0.0;
-          Xss[i * 16 + c] = xi;
-          Rdinv[(int64_t)s * 256 + i * 16 + c] = xi;
-        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = drow(g, v);
+        R[(int64_t)(s * 16 + a) * ldr + s * 16 + c] = x[v];
+        Xss[a * 16 + c] = y[v];
+        Rdinv[(int64_t)s * 256 + a * 16 + c] = y[v];
       }
     }
     __syncthreads();
@@ -326,7 +335,127 @@ __global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am
 
 __global__ void set_word_kernel(int32_t* w, int32_t v) { *w = v; }
 
+// Gram matrix G = Y^T Y (FP64) of a tall Y (rows x l), upper 16x16 tiles only.
+// Workgroup w reduces rows [w*rows/G, (w+1)*rows/G): 16-row chunks of Y are
+// staged in LDS (double-buffered, coalesced row loads) and each wave
+// accumulates its share of the upper tiles on the matrix cores; the partial
+// tiles go to part[w], and gram_reduce_kernel adds the G partials in
+// workgroup order (deterministic).
+constexpr int GR_NT = 512;
+constexpr int GR_NW = GR_NT / 64;
+
+template <typename TY, int TPW>
+__global__ __launch_bounds__(GR_NT) void gram_kernel(const TY* __restrict__ Y, int64_t ldy,
+                                                     int64_t rows, int l, int lp,
+                                                     double* __restrict__ part, int G) {
+  __shared__ double Ys[2][16 * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int nb = lp / 16;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int64_t w = blockIdx.x;
+  const int64_t r0 = (w * rows) / G, r1 = ((w + 1) * rows) / G;
+  d4 acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nch = (int)cdiv(r1 - r0, 16);
+  auto load = [&](int ch, int buf) {
+    const int64_t base = r0 + (int64_t)ch * 16;
+    for (int e = tid; e < 16 * lp; e += GR_NT) {
+      const int k = e / lp, c = e - (e / lp) * lp;
+      const int64_t r = base + k;
+      Ys[buf][k * 256 + c] = (r < r1 && c < l) ? (double)Y[r * ldy + c] : 0.0;
+    }
+  };
+  if (nch > 0) load(0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load(ch + 1, buf ^ 1);
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + GR_NW * q;
+      if (t < ntiles) {
+        const int a = tile_row(t, nb), b = tile_col(t, nb);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lk;
+          acc[q] = Mfma<double>::mma(Ys[buf][k * 256 + a * 16 + li], Ys[buf][k * 256 + b * 16 + li],
+                                     acc[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* P = part + w * (int64_t)ntiles * 256;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + GR_NW * q;
+    if (t < ntiles) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[(int64_t)t * 256 + drow(lk, v) * 16 + li] = acc[q][v];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int G,
+                                                          int lp, double* __restrict__ Gm,
+                                                          int64_t ldg) {
+  const int nb = lp / 16;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ntiles * 256) return;
+  const int t = (int)(e >> 8), ij = (int)(e & 255);
+  double s = 0.0;
+  for (int w = 0; w < G; ++w) s += part[(int64_t)w * ntiles * 256 + e];
+  const int a = tile_row(t, nb), b = tile_col(t, nb);
+  Gm[(int64_t)(a * 16 + (ij >> 4)) * ldg + b * 16 + (ij & 15)] = s;
+}
+
 }  // namespace
+
+int gram_groups(int64_t rows, int ncu) {
+  int64_t G = cdiv(rows, 48);
+  if (G > ncu) G = ncu;
+  if (G < 1) G = 1;
+  return (int)G;
+}
+
+size_t gram_part_bytes(int lp, int G) {
+  const int nb = lp / 16;
+  return (size_t)G * (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
+}
+
+hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
+                       double* Gm, int64_t ldg, double* part, int G, hipStream_t s) {
+  if (lp > 256 || lp % 16) return hipErrorInvalidValue;
+  const int nb = lp / 16;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int tpw = (int)cdiv(ntiles, GR_NW);
+#define RSVD_GRAM(T)                                                                           \
+  do {                                                                                         \
+    if (y_f32)                                                                                 \
+      hipLaunchKernelGGL((gram_kernel<float, T>), dim3(G), dim3(GR_NT), 0, s, (const float*)Y, \
+                         ldy, rows, l, lp, part, G);                                           \
+    else                                                                                       \
+      hipLaunchKernelGGL((gram_kernel<double, T>), dim3(G), dim3(GR_NT), 0, s,                 \
+                         (const double*)Y, ldy, rows, l, lp, part, G);                         \
+  } while (0)
+  if (tpw <= 1) RSVD_GRAM(1);
+  else if (tpw <= 2) RSVD_GRAM(2);
+  else if (tpw <= 4) RSVD_GRAM(4);
+  else if (tpw <= 7) RSVD_GRAM(7);
+  else if (tpw <= 10) RSVD_GRAM(10);
+  else if (tpw <= 14) RSVD_GRAM(14);
+  else RSVD_GRAM(17);
+#undef RSVD_GRAM
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)cdiv((int64_t)ntiles * 256, 256)),
+                     dim3(256), 0, s, part, G, lp, Gm, ldg);
+  return hipGetLastError();
+}
 
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
                        int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
@@ -341,7 +470,9 @@ hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, 
   else if (tpw <= 2) RSVD_CHOL(2);
   else if (tpw <= 4) RSVD_CHOL(4);
   else if (tpw <= 7) RSVD_CHOL(7);
-  else RSVD_CHOL(9);
+  else if (tpw <= 10) RSVD_CHOL(10);
+  else if (tpw <= 14) RSVD_CHOL(14);
+  else RSVD_CHOL(17);
 #undef RSVD_CHOL
   return hipGetLastError();
 }

@@ -29,10 +29,10 @@ struct CpqrArgs {
   const void* Bt; int64_t ldb;     // column j of B at Bt + j * ldb
   int r; int64_t c; int k;
   int G; int64_t cs; int rp;
-  double* slots;                   // [2][G][slot_len]
+  double* slots;                   // [2][G][slot_len]: norm^2, index, ||.||_F^2 part, column
   int64_t slot_len;
-  double* fro;                     // [G] partial ||B||_F^2
-  uint32_t* bar;                   // [3] barrier count, generation, abort flag
+  uint32_t* tags;                  // [2][G] step + 1 of the last post in each slot
+  uint32_t* abort_flag;            // set when a wait exceeds its spin cap
   int64_t* J;                      // [c]
   double* S11t;                    // column t = top k rows of pivot column t (ld = lds)
   double* S12t;                    // column rho = top k rows of residual column rho
@@ -41,40 +41,40 @@ struct CpqrArgs {
   int32_t* info;                   // [2]
 };
 
-// Sense-free grid barrier: bar[0] counts arrivals, bar[1] is the generation,
-// bar[2] an abort flag.  A wait that exceeds its spin cap raises the abort
-// flag and INFO_BARRIER; every later barrier then returns at once, so the
-// kernel always runs to its end (results are then invalid and flagged).
-__device__ void grid_barrier(uint32_t* bar, uint32_t G, int32_t* info) {
+// Exchange between the workgroups of one step: every workgroup posts its
+// candidate into its own slot and then raises the slot's tag to step + 1
+// (release); readers wait for each tag (acquire) and read the slot with
+// agent-scope loads.  No counter is shared, so no atomic is contended.  A wait
+// longer than its spin cap raises the abort flag and INFO_BARRIER; all later
+// waits then return at once, so the kernel always runs to its end (its
+// results are then flagged invalid).
+constexpr uint32_t SPIN_CAP = 1u << 22;
+
+// Called by every thread of the workgroup after the slot data has been stored
+// with agent-scope stores: one release fence per wave, then lane 0 of wave 0
+// raises the tag.
+__device__ __forceinline__ void post_tag(uint32_t* tag, uint32_t value) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t* count = bar;
-    uint32_t* gen = bar + 1;
-    uint32_t* abort_flag = bar + 2;
-    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-      const uint32_t my = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      const uint32_t old =
-          __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == G - 1) {
-        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
-          if (++spins > (1u << 22) ||
-              __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            info_or(info, INFO_BARRIER);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
+  if (threadIdx.x == 0) __hip_atomic_store(tag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Relaxed polling (no cache maintenance per poll); the caller issues one
+// acquire fence per wave after all its waits.
+__device__ __forceinline__ void wait_tag(const uint32_t* tag, uint32_t value, uint32_t* abort_flag,
+                                         int32_t* info) {
+  uint32_t spins = 0;
+  while (__hip_atomic_load(tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != value) {
+    if ((++spins & 63) == 0) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (spins > SPIN_CAP) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        info_or(info, INFO_BARRIER);
+        break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_s_sleep(1);
   }
-  __syncthreads();
 }
 
 __device__ __forceinline__ double ld_agent(const double* p) {
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     slab[e] = (i < r) ? (double)Bt[(j0 + jj) * a.ldb + i] : 0.0;
   }
   __syncthreads();
-  // initial norms and ||B||_F^2
+  // initial norms and the workgroup's share of ||B||_F^2
   double fpart = 0.0;
   for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
     double s2 = 0.0;
@@ -162,17 +162,12 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     fpart += (lane == 0) ? s2 : 0.0;
   }
   fpart = block_sum(fpart, red);
-  if (tid == 0) st_agent(a.fro + g, fpart);
-  __threadfence();
-  grid_barrier(a.bar, (uint32_t)a.G, a.info);
-  double fro2 = 0.0;
-  for (int w = 0; w < a.G; ++w) fro2 += ld_agent(a.fro + w);
-  const double tol = (double)(r > a.c ? r : a.c) * DEPS * sqrt(fro2);
+  double tol = 0.0;
   int frank = a.k;
 
   for (int s = 0; s < a.k; ++s) {
     const int par = s & 1;
-    // 1. local candidate
+    // 1. local candidate, posted to this workgroup's slot
     double bv = -1.0;
     int64_t bi = INT64_MAX;
     int bg = g;
@@ -185,24 +180,34 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     if (tid == 0) {
       st_agent(myslot + 0, bv);
       st_agent(myslot + 1, (double)(bi == INT64_MAX ? -1 : bi));
+      st_agent(myslot + 2, fpart);
     }
     if (bi != INT64_MAX) {
       const int64_t jj = bi - j0;
-      for (int i = s + tid; i < r; i += CQ_NT) st_agent(myslot + 2 + i, slab[jj * rp + i]);
+      for (int i = s + tid; i < r; i += CQ_NT) st_agent(myslot + 3 + i, slab[jj * rp + i]);
     }
-    __threadfence();
-    grid_barrier(a.bar, (uint32_t)a.G, a.info);
-    // 3. global pivot
+    post_tag(a.tags + par * a.G + g, (uint32_t)s + 1u);
+    // 2./3. wait for every slot of this step, then pick the global pivot
     double gv = -1.0;
     int64_t gi = INT64_MAX;
     int gg = 0;
+    double fro_part = 0.0;
+    for (int w = tid; w < a.G; w += CQ_NT)
+      wait_tag(a.tags + par * a.G + w, (uint32_t)s + 1u, a.abort_flag, a.info);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
     for (int w = tid; w < a.G; w += CQ_NT) {
       const double* sl = a.slots + ((int64_t)par * a.G + w) * a.slot_len;
       const double vv = ld_agent(sl + 0);
       const double iv = ld_agent(sl + 1);
+      if (s == 0) fro_part += ld_agent(sl + 2);
       if (iv < 0.0) continue;
       const int64_t ii = (int64_t)iv;
       if (better(vv, ii, gv, gi)) { gv = vv; gi = ii; gg = w; }
+    }
+    if (s == 0) {
+      const double fro2 = block_sum(fro_part, red);
+      tol = (double)(r > a.c ? r : a.c) * DEPS * sqrt(fro2);
     }
     block_argmax(gv, gi, gg, redv, redi, redg);
     if (gi < 0 || gi >= a.c) { gi = 0; gg = 0; }     // only after an aborted barrier
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     const double* psl = a.slots + ((int64_t)par * a.G + gg) * a.slot_len;
     double xs2 = 0.0;
     for (int i = s + tid; i < r; i += CQ_NT) {
-      const double x = ld_agent(psl + 2 + i);
+      const double x = ld_agent(psl + 3 + i);
       v[i] = x;
       xs2 += x * x;
     }
@@ -326,6 +331,17 @@ __global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__
   }
 }
 
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t cpqr_lds_bytes(int64_t cs, int rp, int k) {
@@ -342,13 +358,14 @@ CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
   p.G = (int)G;
   p.cs = cdiv(c, G);
   p.lds = cpqr_lds_bytes(p.cs, p.rp, k);
-  p.slot_len = 2 + p.rp;
+  p.slot_len = 3 + p.rp;
   p.ok = p.lds <= 150 * 1024 && k <= 256 && k <= r && k <= c;
   return p;
 }
 
 size_t cpqr_work_bytes(const CpqrPlan& p) {
-  return (size_t)(2 * p.G * p.slot_len + p.G) * sizeof(double) + 64;
+  return (size_t)(2 * p.G * p.slot_len) * sizeof(double) + (size_t)(2 * p.G + 2) * sizeof(uint32_t) +
+         64;
 }
 
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
@@ -361,11 +378,10 @@ hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c
   double* w = static_cast<double*>(work);
   a.slots = w;
   a.slot_len = p.slot_len;
-  a.fro = w + 2 * p.G * p.slot_len;
-  a.bar = reinterpret_cast<uint32_t*>(a.fro + p.G);
+  a.tags = reinterpret_cast<uint32_t*>(w + 2 * p.G * p.slot_len);
+  a.abort_flag = a.tags + 2 * p.G;
   a.J = J; a.S11t = S11t; a.S12t = S12t; a.lds = lds; a.pivn = pivn; a.info = info;
-  hipError_t e = launch_set_word(reinterpret_cast<int32_t*>(a.bar), 0, s);
-  if (e == hipSuccess) e = launch_set_word(reinterpret_cast<int32_t*>(a.bar) + 2, 0, s);
+  hipError_t e = launch_fill_u32(a.tags, 0u, 2 * p.G + 1, s);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
   const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;

@@ -197,6 +197,10 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 }
 
 // Adds the partial sums of every tile that was split between workgroups.
+// Grid: (tile, chunk of FIX_CHUNK elements); each thread sums its elements
+// over the workgroups that covered the tile, in workgroup order.
+constexpr int FIX_CHUNK = 1024;
+
 template <typename TC, typename TO, int CBW>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
   constexpr int BN = 32 * CBW;
@@ -211,16 +215,19 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
   const int64_t col0 = (tile % g.nct) * BN;
   const TC* P = static_cast<const TC*>(g.part);
   TO* C = static_cast<TO*>(g.C);
-  for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+  const int e0 = blockIdx.y * FIX_CHUNK;
+  const int e1 = min(e0 + FIX_CHUNK, BM * BN);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t r = row0 + e / BN;
+    const int64_t c = col0 + e % BN;
+    if (r >= g.M || c >= g.L) continue;
     TC s = TC(0);
     for (int64_t w = wf; w <= wl; ++w) {
       if (range_begin(w, g.U, g.G) == range_begin(w + 1, g.U, g.G)) continue;
       const int64_t slot = 2 * w + (w == wf ? 1 : 0);
       s += P[slot * (int64_t)(BM * BN) + e];
     }
-    const int64_t r = row0 + e / BN;
-    const int64_t c = col0 + e % BN;
-    if (r < g.M && c < g.L) C[r * g.ldc + c] = (TO)s;
+    C[r * g.ldc + c] = (TO)s;
   }
 }
 
@@ -232,7 +239,9 @@ hipError_t run(const GemmArgs& g, hipStream_t s) {
   // with one workgroup per tile every range is a whole tile: no fix-up
   const int64_t T = g.U / g.KI;
   if (g.G != T) {
-    hipLaunchKernelGGL((gemm_fixup_kernel<TC, TO, CBW>), dim3(T), dim3(256), 0, s, g);
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((gemm_fixup_kernel<TC, TO, CBW>), dim3((unsigned)T, nch), dim3(256), 0, s,
+                       g);
     e = hipGetLastError();
   }
   return e;

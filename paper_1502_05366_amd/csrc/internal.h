@@ -48,6 +48,12 @@ namespace rsvd {
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
                        int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
                        const int32_t* gate, hipStream_t s);
+// G = Y^T Y (upper 16x16 tiles of an lp x lp matrix) in FP64 for a tall Y;
+// `part` holds gram_part_bytes(lp, G) bytes, G = gram_groups(rows, ncu).
+int gram_groups(int64_t rows, int ncu);
+size_t gram_part_bytes(int lp, int G);
+hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
+                       double* Gm, int64_t ldg, double* part, int G, hipStream_t s);
 // Q = Y R^{-1} (M x l); Y and Q may be FP32 or FP64; arithmetic in FP64.
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
@@ -61,9 +67,12 @@ hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int6
 hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s);
 
 // ---------------------------------------------------------------- jacobi --
-hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* Wwork, double* Vwork,
-                         int64_t ldw, double* S, double* Uh, int64_t lduh, double* Vh,
-                         int64_t ldvh, int max_sweeps, int32_t* info, hipStream_t s);
+// work: jacobi_work_bytes(l) bytes; sweeps_out (device int, may be null)
+// receives the number of sweeps of the block iteration.
+size_t jacobi_work_bytes(int l);
+hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
+                         double* Uh, int64_t lduh, double* Vh, int64_t ldvh, int max_sweeps,
+                         int32_t* info, int32_t* sweeps_out, hipStream_t s);
 
 // ------------------------------------------------------------------ cpqr --
 struct CpqrPlan {

@@ -10,11 +10,12 @@
 // On exit R_hat V = W with orthogonal columns: sigma_j = ||w_j||,
 // Uh_j = w_j / sigma_j, Vh_j = v_j, so R_hat = Uh diag(sigma) Vh^T.
 //
-// One workgroup of 16 waves; pairs are scheduled in round-robin rounds of
-// disjoint pairs (circle method), one pair per wave at a time; the dot
-// products are wave reductions.  W and V live in LDS when they fit and in
-// global memory (L2-resident) otherwise.  Output: the k largest sigma in
-// descending order (stable for ties) and the matching columns of Uh and Vh.
+// Pairs are scheduled in round-robin rounds of disjoint pairs (circle
+// method), one pair per wave at a time; the dot products are wave
+// reductions.  Small factors (l <= 64) run in one workgroup with W and V in
+// LDS; larger ones run as a block Jacobi over several workgroups (below).
+// Output: the k largest sigma in descending order (stable for ties) and the
+// matching columns of Uh and Vh.
 #include "common.h"
 #include "internal.h"
 
@@ -34,85 +35,13 @@ __device__ __forceinline__ int rr_player(int pos, int r, int N) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (N - 1)) + 1;
 }
 
-// W, V: column-major, column j at base + j * ld (ld >= l)
-template <bool IN_LDS>
-__global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ Rh, int64_t ldr,
-                                                     int l, int k, double* Wg, double* Vg,
-                                                     int64_t ldw, double* __restrict__ S,
-                                                     double* __restrict__ Uh, int64_t lduh,
-                                                     double* __restrict__ Vh, int64_t ldvh,
-                                                     int max_sweeps, double tol, int32_t* info) {
-  extern __shared__ double smem[];
-  __shared__ int rotated;
-  __shared__ double sig[256];
+// Singular values = column norms of W; the k largest (stable descending
+// order) go to S with Uh(:, rank) = w_j / sigma_j and Vh(:, rank) = v_j.
+// Called by every thread of a workgroup of JNT threads; sig has l entries.
+__device__ void jacobi_finish(const double* W, const double* V, int64_t ld, int l, int k,
+                              double* sig, double* __restrict__ S, double* __restrict__ Uh,
+                              int64_t lduh, double* __restrict__ Vh, int64_t ldvh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* W;
-  double* V;
-  int64_t ld;
-  if (IN_LDS) {
-    ld = l;
-    W = smem;
-    V = smem + (int64_t)l * l;
-  } else {
-    ld = ldw;
-    W = Wg;
-    V = Vg;
-  }
-  // W = R_hat (column-major), V = I
-  for (int64_t e = tid; e < (int64_t)l * l; e += JNT) {
-    const int j = (int)(e / l), i = (int)(e % l);
-    W[j * ld + i] = Rh[(int64_t)i * ldr + j];
-    V[j * ld + i] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-
-  const int N = l + (l & 1);
-  int sweep = 0;
-  bool converged = (l < 2);
-  while (!converged && sweep < max_sweeps) {
-    ++sweep;
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < N - 1; ++r) {
-      for (int pi = wave; pi < N / 2; pi += JNT / 64) {
-        int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
-        if (a >= l || b >= l) continue;
-        if (a > b) { const int t = a; a = b; b = t; }
-        double* wa = W + a * ld;
-        double* wb = W + b * ld;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < l; i += 64) {
-          const double x = wa[i], y = wb[i];
-          al += x * x; be += y * y; ga += x * y;
-        }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al * be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
-        for (int i = lane; i < l; i += 64) {
-          const double x = wa[i], y = wb[i];
-          wa[i] = cs * x - sn * y;
-          wb[i] = sn * x + cs * y;
-        }
-        double* va = V + a * ld;
-        double* vb = V + b * ld;
-        for (int i = lane; i < l; i += 64) {
-          const double x = va[i], y = vb[i];
-          va[i] = cs * x - sn * y;
-          vb[i] = sn * x + cs * y;
-        }
-        if (lane == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    converged = (rotated == 0);
-    __syncthreads();
-  }
-  if (!converged && tid == 0) info_or(info, INFO_JACOBI_CAP);
-
-  // singular values = column norms
   for (int j = wave; j < l; j += JNT / 64) {
     double s2 = 0.0;
     for (int i = lane; i < l; i += 64) { const double x = W[j * ld + i]; s2 += x * x; }
@@ -120,7 +49,6 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
     if (lane == 0) sig[j] = sqrt(s2);
   }
   __syncthreads();
-  // stable descending rank, then write the first k
   for (int j = wave; j < l; j += JNT / 64) {
     const double sj = sig[j];
     int rank = 0;
@@ -141,21 +69,275 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
   }
 }
 
+// Rotate the column pair (a, b) of W (and V) if it is not yet orthogonal;
+// executed by one wave.  Returns true when a rotation was applied.
+__device__ __forceinline__ bool rotate_pair(double* wa, double* wb, double* va, double* vb, int l,
+                                            int lane, double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = lane; i < l; i += 64) {
+    const double x = wa[i], y = wb[i];
+    al += x * x; be += y * y; ga += x * y;
+  }
+  al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double sn = cs * t;
+  for (int i = lane; i < l; i += 64) {
+    const double x = wa[i], y = wb[i];
+    wa[i] = cs * x - sn * y;
+    wb[i] = sn * x + cs * y;
+  }
+  for (int i = lane; i < l; i += 64) {
+    const double x = va[i], y = vb[i];
+    va[i] = cs * x - sn * y;
+    vb[i] = sn * x + cs * y;
+  }
+  return true;
+}
+
+// l <= LDS_MAX_L: the whole iteration in one workgroup, W and V in LDS.
+__global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restrict__ Rh, int64_t ldr,
+                                                         int l, int k, double* __restrict__ S,
+                                                         double* __restrict__ Uh, int64_t lduh,
+                                                         double* __restrict__ Vh, int64_t ldvh,
+                                                         int max_sweeps, double tol, int32_t* info) {
+  extern __shared__ double smem[];
+  __shared__ int rotated;
+  __shared__ double sig[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ld = l;
+  double* W = smem;
+  double* V = smem + (int64_t)l * l;
+  for (int j = wave; j < l; j += JNT / 64)
+    for (int i = lane; i < l; i += 64) {
+      W[j * ld + i] = Rh[(int64_t)i * ldr + j];
+      V[j * ld + i] = (i == j) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  const int N = l + (l & 1);
+  int sweep = 0;
+  bool converged = (l < 2);
+  while (!converged && sweep < max_sweeps) {
+    ++sweep;
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      for (int pi = wave; pi < N / 2; pi += JNT / 64) {
+        int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
+        if (a >= l || b >= l) continue;
+        if (a > b) { const int t = a; a = b; b = t; }
+        if (rotate_pair(W + a * ld, W + b * ld, V + a * ld, V + b * ld, l, lane, tol) && lane == 0)
+          rotated = 1;
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0) info_or(info, INFO_JACOBI_CAP);
+  jacobi_finish(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
+}
+
+// ---- block one-sided Jacobi over several workgroups (l > LDS_MAX_L) -------
+//
+// The l columns are cut into blocks of BS; blocks are paired by the same
+// round-robin schedule as columns, and each of the NB/2 workgroups of a
+// cooperative launch takes one block pair per round: it loads the 2*BS
+// columns of W and V into LDS, rotates every cross pair (x from the first
+// block, y from the second; in round 0 also the pairs inside each block),
+// and writes the columns back.  Between rounds the workgroups exchange
+// progress through per-workgroup tags (agent-scope release / acquire); a
+// sweep over all rounds visits every column pair exactly once.  The
+// iteration stops after the first sweep without a rotation.
+constexpr int BS = 16;
+
+struct JacArgs {
+  double* W; double* V; int64_t ld;
+  int l, nbp, G, max_sweeps;
+  double tol;
+  uint32_t* tags;       // [G] rounds completed by each workgroup
+  uint32_t* rot;        // [2][G] rotation flag of the current / previous sweep
+  uint32_t* abort_flag;
+  int32_t* info;
+  int32_t* sweeps_out;
+};
+
+__device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
+  const int tid = threadIdx.x;
+  if (tid < a.G) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(a.tags + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if ((++spins & 63) == 0) {
+        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (spins > (1u << 22)) {
+          __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          info_or(a.info, INFO_BARRIER);
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
+  extern __shared__ double smem[];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = blockIdx.x;
+  const int l = a.l, LD = l;
+  double* Wl = smem;                        // [2*BS][LD]
+  double* Vl = smem + 2 * BS * LD;
+  uint32_t done = 0;
+  int sweep = 0;
+  bool converged = false;
+  if (tid == 0) rotated = 0;
+  while (!converged && sweep < a.max_sweeps) {
+    for (int r = 0; r < a.nbp - 1; ++r) {
+      const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
+      // load the two blocks (columns >= l read as zero)
+      for (int c = wave; c < 2 * BS; c += JNT / 64) {
+        const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
+        for (int i = lane; i < l; i += 64) {
+          const bool ok = gcol < l;
+          Wl[c * LD + i] = ok ? a.W[(int64_t)gcol * a.ld + i] : 0.0;
+          Vl[c * LD + i] = ok ? a.V[(int64_t)gcol * a.ld + i] : 0.0;
+        }
+      }
+      __syncthreads();
+      if (r == 0) {
+        // pairs inside each block: BS-1 round-robin rounds, both blocks at once
+        for (int t = 0; t < BS - 1; ++t) {
+          if (wave < BS) {
+            const int half = wave / (BS / 2), pi = wave % (BS / 2);
+            int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
+            if (p > q) { const int x = p; p = q; q = x; }
+            p += half * BS; q += half * BS;
+            if (rotate_pair(Wl + p * LD, Wl + q * LD, Vl + p * LD, Vl + q * LD, l, lane, a.tol) &&
+                lane == 0)
+              rotated = 1;
+          }
+          __syncthreads();
+        }
+      }
+      // cross pairs: (x_i, y_{(i+t) mod BS}) for t = 0 .. BS-1
+      for (int t = 0; t < BS; ++t) {
+        if (wave < BS) {
+          const int p = wave, q = BS + (wave + t) % BS;
+          if (rotate_pair(Wl + p * LD, Wl + q * LD, Vl + p * LD, Vl + q * LD, l, lane, a.tol) &&
+              lane == 0)
+            rotated = 1;
+        }
+        __syncthreads();
+      }
+      for (int c = wave; c < 2 * BS; c += JNT / 64) {
+        const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
+        if (gcol < l)
+          for (int i = lane; i < l; i += 64) {
+            a.W[(int64_t)gcol * a.ld + i] = Wl[c * LD + i];
+            a.V[(int64_t)gcol * a.ld + i] = Vl[c * LD + i];
+          }
+      }
+      const bool last = (r == a.nbp - 2);
+      if (last && tid == 0)
+        __hip_atomic_store(a.rot + (sweep & 1) * a.G + w, (uint32_t)rotated, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      ++done;
+      if (tid == 0) __hip_atomic_store(a.tags + w, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      jac_wait_all(a, done);
+    }
+    // every workgroup reads the same flags, so all take the same decision
+    uint32_t any = 0;
+    for (int v = 0; v < a.G; ++v)
+      any |= __hip_atomic_load(a.rot + (sweep & 1) * a.G + v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    ++sweep;
+    converged = (any == 0);
+    __syncthreads();
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+  }
+  if (w == 0 && tid == 0) {
+    if (!converged) info_or(a.info, INFO_JACOBI_CAP);
+    if (a.sweeps_out) *a.sweeps_out = sweep;
+  }
+}
+
+__global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restrict__ Rh,
+                                                          int64_t ldr, int l,
+                                                          double* __restrict__ W,
+                                                          double* __restrict__ V, int64_t ld,
+                                                          uint32_t* ctl, int nctl) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nctl) ctl[e] = 0;
+  if (e >= (int64_t)l * l) return;
+  const int j = (int)(e / l), i = (int)(e - (int64_t)j * l);
+  W[(int64_t)j * ld + i] = Rh[(int64_t)i * ldr + j];
+  V[(int64_t)j * ld + i] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __restrict__ W,
+                                                            const double* __restrict__ V,
+                                                            int64_t ld, int l, int k,
+                                                            double* __restrict__ S,
+                                                            double* __restrict__ Uh, int64_t lduh,
+                                                            double* __restrict__ Vh,
+                                                            int64_t ldvh) {
+  __shared__ double sig[256];
+  jacobi_finish(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
+}
+
 }  // namespace
 
-hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* Wwork, double* Vwork,
-                         int64_t ldw, double* S, double* Uh, int64_t lduh, double* Vh,
-                         int64_t ldvh, int max_sweeps, int32_t* info, hipStream_t s) {
+size_t jacobi_work_bytes(int l) {
+  // W, V (l x l each) and the control words of the block iteration
+  return 2 * (size_t)l * l * sizeof(double) + 64 * sizeof(uint32_t) + 256;
+}
+
+hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
+                         double* Uh, int64_t lduh, double* Vh, int64_t ldvh, int max_sweeps,
+                         int32_t* info, int32_t* sweeps_out, hipStream_t s) {
   if (l > 256) return hipErrorInvalidValue;
   const double tol = (double)l * 2.220446049250313e-16;
   if (l <= LDS_MAX_L) {
     const size_t shm = 2 * (size_t)l * l * sizeof(double);
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(JNT), shm, s, Rh, ldr, l, k, Wwork,
-                       Vwork, ldw, S, Uh, lduh, Vh, ldvh, max_sweeps, tol, info);
-  } else {
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(JNT), 0, s, Rh, ldr, l, k, Wwork,
-                       Vwork, ldw, S, Uh, lduh, Vh, ldvh, max_sweeps, tol, info);
+    hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(JNT), shm, s, Rh, ldr, l, k, S, Uh, lduh,
+                       Vh, ldvh, max_sweeps, tol, info);
+    return hipGetLastError();
   }
+  double* W = work;
+  double* V = work + (size_t)l * l;
+  uint32_t* ctl = reinterpret_cast<uint32_t*>(V + (size_t)l * l);
+  const int nb = (int)cdiv(l, BS);
+  const int nbp = nb + (nb & 1);
+  JacArgs a;
+  a.W = W; a.V = V; a.ld = l; a.l = l; a.nbp = nbp; a.G = nbp / 2; a.max_sweeps = max_sweeps;
+  a.tol = tol;
+  a.tags = ctl;
+  a.rot = ctl + 16;
+  a.abort_flag = ctl + 48;
+  a.info = info;
+  a.sweeps_out = sweeps_out;
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)cdiv((int64_t)l * l, 256)), dim3(256), 0,
+                     s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t shm = 4 * (size_t)BS * l * sizeof(double);
+  e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JNT), args, shm,
+                                 s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, (int64_t)l, l, k, S, Uh,
+                     lduh, Vh, ldvh);
   return hipGetLastError();
 }
 

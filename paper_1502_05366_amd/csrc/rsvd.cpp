@@ -74,11 +74,12 @@ struct OrthBufs {
   int32_t *dep, *dep2;
   void* part;
   size_t part_bytes;
+  double* gpart;          // partial Gram tiles, gram_part_bytes(lp, NCU_CAP)
 };
 
 struct Bufs {
   void *Om, *Y, *Q, *Z, *Zq;
-  double *Qh, *Rh, *Wj, *Vj, *Uh, *Vh;
+  double *Qh, *Rh, *Wj, *Uh, *Vh;
   OrthBufs ob;
   // ID
   void* cq_work;
@@ -100,11 +101,8 @@ size_t max_part(const Shape& s) {
   };
   upd(s.m, s.n, s.l);
   upd(s.n, s.m, s.l);
-  upd(s.l, s.m, s.l);
-  upd(s.l, s.n, s.l);
   upd(s.m, s.l, s.k);
   upd(s.n, s.l, s.k);
-  upd(s.k, s.n, s.k);
   upd(s.k, s.n - s.k, s.k);
   return b;
 }
@@ -129,11 +127,11 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
   b.ob.dep2 = a.take<int32_t>(s.lp);
   b.ob.part_bytes = max_part(s);
   b.ob.part = a.take<char>(b.ob.part_bytes);
+  b.ob.gpart = a.take<double>(gram_part_bytes(s.lp, NCU_CAP) / sizeof(double));
   if (s.ops & RSVD_OP_SVD) {
     b.Qh = a.take<double>((size_t)s.n * s.lp);
     b.Rh = a.take<double>((size_t)s.lp * s.lp);
-    b.Wj = a.take<double>((size_t)s.lp * s.lp);
-    b.Vj = a.take<double>((size_t)s.lp * s.lp);
+    b.Wj = a.take<double>(jacobi_work_bytes(s.l) / sizeof(double) + 1);
     b.Uh = a.take<double>((size_t)s.lp * s.kp);
     b.Vh = a.take<double>((size_t)s.lp * s.kp);
   }
@@ -183,18 +181,16 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
                 int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
                 int64_t ldr) {
   const int lp = (int)rup(l, 16);
-  const GemmPlan pg = plan_gemm(l, rows, l, std::min(c.ncu, NCU_CAP), 0);
+  const int gG = gram_groups(rows, std::min(c.ncu, NCU_CAP));
   // pass 1: G = Y^T Y, G = R1^T R1, Qa = Y R1^{-1}, dependent columns replaced
-  RSVD_TRY(launch_gemm(y_f32 ? GEMM_FFDD : GEMM_DDDD, true, Y, ldy, Y, ldy, ob.G, lp, l, rows, l,
-                       pg, ob.part, ob.part_bytes, c.st));
+  RSVD_TRY(launch_gram(y_f32, Y, ldy, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, nullptr,
                        nullptr, c.st));
   RSVD_TRY(launch_trsm(y_f32, false, Y, ldy, rows, l, lp, ob.R1, lp, ob.Rd1, ob.Qa, lp, nullptr,
                        c.st));
   RSVD_TRY(launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st));
   // pass 2 on Qa
-  RSVD_TRY(launch_gemm(GEMM_DDDD, true, ob.Qa, lp, ob.Qa, lp, ob.G, lp, l, rows, l, pg, ob.part,
-                       ob.part_bytes, c.st));
+  RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, nullptr,
                        nullptr, c.st));
   RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, nullptr,
@@ -240,8 +236,8 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
   if (o.U) {
     // [Qh, Rh] = qr(B^T); Rh = Uh S Vh^T; U = Q Vh_k; V = Qh Uh_k
     RSVD_TRY(orth(c, b.ob, f32, b.Z, lp, n, l, b.Qh, false, lp, b.Rh, lp));
-    RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, b.Vj, lp, o.S, b.Uh, s.kp, b.Vh, s.kp,
-                           JACOBI_MAX_SWEEPS, c.info, c.st));
+    RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, o.S, b.Uh, s.kp, b.Vh, s.kp, JACOBI_MAX_SWEEPS,
+                           c.info, nullptr, c.st));
     const GemmPlan pu = plan_gemm(m, l, k, ncu, 0);
     RSVD_TRY(launch_gemm(f32 ? GEMM_FDDF : GEMM_DDDD, false, b.Q, lp, b.Vh, s.kp, o.U, o.ldu, m, l,
                          k, pu, b.ob.part, b.ob.part_bytes, c.st));
@@ -539,7 +535,7 @@ size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {
   a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
   a.take<double>((size_t)rows * lp);
   a.take<int32_t>(2 * (size_t)lp);
-  a.take<char>(gemm_part_bytes(plan_gemm(l, rows, l, NCU_CAP, 0), 8));
+  a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
   return a.off;
 }
 
@@ -573,8 +569,9 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   ob.Qa = a.take<double>((size_t)rows * lp);
   ob.dep = a.take<int32_t>(2 * (size_t)lp);
   ob.dep2 = ob.dep + lp;
-  ob.part_bytes = gemm_part_bytes(plan_gemm(l, rows, l, NCU_CAP, 0), 8);
-  ob.part = a.take<char>(ob.part_bytes);
+  ob.part = nullptr;
+  ob.part_bytes = 0;
+  ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ctx c{st, h->ncu, info, seed, 0};
   hipError_t e = launch_set_word(info, 0, st);
@@ -589,7 +586,7 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
 
 size_t rsvd_small_svd_workspace_bytes(int64_t l) {
   if (l < 1 || l > MAX_L) return 0;
-  return 2 * (size_t)l * l * sizeof(double) + 512;
+  return jacobi_work_bytes((int)l) + sizeof(int32_t) + 256;
 }
 
 int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t ldr, double* S,
@@ -611,13 +608,13 @@ int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t 
   if (!info) return -13;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  double* W = static_cast<double*>(work);
-  double* V = W + (size_t)l * l;
+  Arena a(work);
+  double* jw = a.take<double>(jacobi_work_bytes((int)l) / sizeof(double) + 1);
   hipError_t e = launch_set_word(info, 0, st);
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   if (e == hipSuccess)
-    e = launch_jacobi(Rh, ldr, (int)l, k, W, V, l, S, Uh, lduh, Vh, ldvh, JACOBI_MAX_SWEEPS, info,
-                      st);
+    e = launch_jacobi(Rh, ldr, (int)l, k, jw, S, Uh, lduh, Vh, ldvh, JACOBI_MAX_SWEEPS, info,
+                      nullptr, st);
   return finish(e);
 }
 
