@@ -90,10 +90,13 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
   const int ntiles = nb * (nb + 1) / 2;
 
   d4 acc[TPW];
+  int ta[TPW], tb[TPW];      // tile coordinates (wave-uniform); ta = nb marks no tile
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     const int t = wave + CH_NW * q;
-    if (t < ntiles) acc[q] = load_gtile(G, ldg, l, tile_row(t, nb), tile_col(t, nb), lane);
+    ta[q] = (t < ntiles) ? tile_row(t, nb) : nb;
+    tb[q] = (t < ntiles) ? tile_col(t, nb) : nb;
+    if (t < ntiles) acc[q] = load_gtile(G, ldg, l, ta[q], tb[q], lane);
     else acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
@@ -101,8 +104,7 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
     // (a) the owner of tile (s, s) hands it to LDS
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-      const int t = wave + CH_NW * q;
-      if (t < ntiles && tile_row(t, nb) == s && tile_col(t, nb) == s) {
+      if (ta[q] == s && tb[q] == s) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) Dss[drow(lk, v) * 17 + li] = acc[q][v];
       }
@@ -177,9 +179,8 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
     // (c) panel: R_sb = R_ss^{-T} G_sb for b > s, zero rows of dependent columns
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-      const int t = wave + CH_NW * q;
-      if (t < ntiles && tile_row(t, nb) == s && tile_col(t, nb) > s) {
-        const int b = tile_col(t, nb);
+      if (ta[q] == s && tb[q] > s && tb[q] < nb) {
+        const int b = tb[q];
 #pragma unroll
         for (int v = 0; v < 4; ++v) Tw[wave][drow(lk, v) * 16 + li] = acc[q][v];
         __builtin_amdgcn_wave_barrier();
@@ -204,17 +205,16 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
       }
     }
     __syncthreads();
-    // (d) trailing update: G_ab -= R_sa^T R_sb for s < a <= b
+    // (d) trailing update: G_ab -= R_sa^T R_sb for s < a <= b; the k-steps
+    // run outermost so that consecutive products go to different tiles
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      const int t = wave + CH_NW * q;
-      if (t < ntiles && tile_row(t, nb) > s) {
-        const int a = tile_row(t, nb), b = tile_col(t, nb);
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kk + lk;
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int k = 4 * kk + lk;
-          const double av = -P[k * 256 + a * 16 + li];
-          const double bv = P[k * 256 + b * 16 + li];
+      for (int q = 0; q < TPW; ++q) {
+        if (ta[q] > s && ta[q] < nb) {
+          const double av = -P[k * 256 + ta[q] * 16 + li];
+          const double bv = P[k * 256 + tb[q] * 16 + li];
           acc[q] = Mfma<double>::mma(av, bv, acc[q]);
         }
       }
@@ -399,16 +399,32 @@ __global__ __launch_bounds__(GR_NT) void gram_kernel(const TY* __restrict__ Y, i
   }
 }
 
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int G,
-                                                          int lp, double* __restrict__ Gm,
-                                                          int64_t ldg) {
+// Stage 1: block (x, y) sums partials y*GR_SPLIT .. of 256 elements;
+// stage 2 adds the GR_SPLIT sums in order.  Both orders are fixed.
+constexpr int GR_SPLIT = 16;
+
+__global__ __launch_bounds__(256) void gram_reduce1_kernel(const double* __restrict__ part, int G,
+                                                           int ntiles, double* __restrict__ mid) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)ntiles * 256;
+  if (e >= total) return;
+  const int w0 = (int)(((int64_t)blockIdx.y * G) / GR_SPLIT);
+  const int w1 = (int)(((int64_t)(blockIdx.y + 1) * G) / GR_SPLIT);
+  double s = 0.0;
+  for (int w = w0; w < w1; ++w) s += part[(int64_t)w * total + e];
+  mid[(int64_t)blockIdx.y * total + e] = s;
+}
+
+__global__ __launch_bounds__(256) void gram_reduce2_kernel(const double* __restrict__ mid, int lp,
+                                                           double* __restrict__ Gm, int64_t ldg) {
   const int nb = lp / 16;
   const int ntiles = nb * (nb + 1) / 2;
+  const int64_t total = (int64_t)ntiles * 256;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)ntiles * 256) return;
-  const int t = (int)(e >> 8), ij = (int)(e & 255);
+  if (e >= total) return;
   double s = 0.0;
-  for (int w = 0; w < G; ++w) s += part[(int64_t)w * ntiles * 256 + e];
+  for (int y = 0; y < GR_SPLIT; ++y) s += mid[(int64_t)y * total + e];
+  const int t = (int)(e >> 8), ij = (int)(e & 255);
   const int a = tile_row(t, nb), b = tile_col(t, nb);
   Gm[(int64_t)(a * 16 + (ij >> 4)) * ldg + b * 16 + (ij & 15)] = s;
 }
@@ -424,7 +440,7 @@ int gram_groups(int64_t rows, int ncu) {
 
 size_t gram_part_bytes(int lp, int G) {
   const int nb = lp / 16;
-  return (size_t)G * (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
+  return (size_t)(G + GR_SPLIT) * (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
 }
 
 hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
@@ -452,8 +468,13 @@ hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int
 #undef RSVD_GRAM
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)cdiv((int64_t)ntiles * 256, 256)),
-                     dim3(256), 0, s, part, G, lp, Gm, ldg);
+  const unsigned nblk = (unsigned)cdiv((int64_t)ntiles * 256, 256);
+  double* mid = part + (int64_t)G * ntiles * 256;
+  hipLaunchKernelGGL(gram_reduce1_kernel, dim3(nblk, GR_SPLIT), dim3(256), 0, s, part, G, ntiles,
+                     mid);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce2_kernel, dim3(nblk), dim3(256), 0, s, mid, lp, Gm, ldg);
   return hipGetLastError();
 }
 

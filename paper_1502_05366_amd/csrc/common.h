@@ -55,4 +55,30 @@ __device__ __forceinline__ void info_or(int32_t* info, int32_t bits) {
   if (info) atomicOr(info, bits);
 }
 
+// Cross-workgroup exchange without cache maintenance: data and flags are
+// written and read with agent-scope atomic stores / loads (coherent across
+// the XCDs without L2 write-back or invalidation), and a writer waits for its
+// own stores to complete before it raises a flag.
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// all stores issued by this wave have completed
+__device__ __forceinline__ void stores_done() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// flags live 128 bytes apart so that pollers of different flags do not share
+// a cache line
+constexpr int FLAG_STRIDE = 32;
+
 }  // namespace rsvd

@@ -22,7 +22,7 @@
 namespace rsvd {
 namespace {
 
-constexpr int CQ_NT = 256;
+constexpr int CQ_NT = 1024;
 constexpr double DEPS = 2.220446049250313e-16;
 
 struct CpqrArgs {
@@ -31,7 +31,7 @@ struct CpqrArgs {
   int G; int64_t cs; int rp;
   double* slots;                   // [2][G][slot_len]: norm^2, index, ||.||_F^2 part, column
   int64_t slot_len;
-  uint32_t* tags;                  // [2][G] step + 1 of the last post in each slot
+  uint32_t* tags;                  // [2][G] (FLAG_STRIDE apart) step + 1 of the last post
   uint32_t* abort_flag;            // set when a wait exceeds its spin cap
   int64_t* J;                      // [c]
   double* S11t;                    // column t = top k rows of pivot column t (ld = lds)
@@ -51,37 +51,29 @@ struct CpqrArgs {
 constexpr uint32_t SPIN_CAP = 1u << 22;
 
 // Called by every thread of the workgroup after the slot data has been stored
-// with agent-scope stores: one release fence per wave, then lane 0 of wave 0
+// with agent-scope stores: each wave waits for its stores, then thread 0
 // raises the tag.
 __device__ __forceinline__ void post_tag(uint32_t* tag, uint32_t value) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  stores_done();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(tag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) st_agent_u32(tag, value);
 }
 
-// Relaxed polling (no cache maintenance per poll); the caller issues one
-// acquire fence per wave after all its waits.
+// Relaxed polling; the slot data is then read with agent-scope loads.
 __device__ __forceinline__ void wait_tag(const uint32_t* tag, uint32_t value, uint32_t* abort_flag,
                                          int32_t* info) {
   uint32_t spins = 0;
-  while (__hip_atomic_load(tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != value) {
+  while (ld_agent_u32(tag) != value) {
     if ((++spins & 63) == 0) {
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (ld_agent_u32(abort_flag) != 0) break;
       if (spins > SPIN_CAP) {
-        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_agent_u32(abort_flag, 1u);
         info_or(info, INFO_BARRIER);
         break;
       }
     }
     __builtin_amdgcn_s_sleep(1);
   }
-}
-
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // block-wide reductions (CQ_NT threads)
@@ -186,15 +178,14 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
       const int64_t jj = bi - j0;
       for (int i = s + tid; i < r; i += CQ_NT) st_agent(myslot + 3 + i, slab[jj * rp + i]);
     }
-    post_tag(a.tags + par * a.G + g, (uint32_t)s + 1u);
+    post_tag(a.tags + (par * a.G + g) * FLAG_STRIDE, (uint32_t)s + 1u);
     // 2./3. wait for every slot of this step, then pick the global pivot
     double gv = -1.0;
     int64_t gi = INT64_MAX;
     int gg = 0;
     double fro_part = 0.0;
     for (int w = tid; w < a.G; w += CQ_NT)
-      wait_tag(a.tags + par * a.G + w, (uint32_t)s + 1u, a.abort_flag, a.info);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      wait_tag(a.tags + (par * a.G + w) * FLAG_STRIDE, (uint32_t)s + 1u, a.abort_flag, a.info);
     __syncthreads();
     for (int w = tid; w < a.G; w += CQ_NT) {
       const double* sl = a.slots + ((int64_t)par * a.G + w) * a.slot_len;
@@ -364,8 +355,8 @@ CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
 }
 
 size_t cpqr_work_bytes(const CpqrPlan& p) {
-  return (size_t)(2 * p.G * p.slot_len) * sizeof(double) + (size_t)(2 * p.G + 2) * sizeof(uint32_t) +
-         64;
+  return (size_t)(2 * p.G * p.slot_len) * sizeof(double) +
+         (size_t)(2 * p.G + 1) * FLAG_STRIDE * sizeof(uint32_t) + 64;
 }
 
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
@@ -379,9 +370,9 @@ hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c
   a.slots = w;
   a.slot_len = p.slot_len;
   a.tags = reinterpret_cast<uint32_t*>(w + 2 * p.G * p.slot_len);
-  a.abort_flag = a.tags + 2 * p.G;
+  a.abort_flag = a.tags + 2 * p.G * FLAG_STRIDE;
   a.J = J; a.S11t = S11t; a.S12t = S12t; a.lds = lds; a.pivn = pivn; a.info = info;
-  hipError_t e = launch_fill_u32(a.tags, 0u, 2 * p.G + 1, s);
+  hipError_t e = launch_fill_u32(a.tags, 0u, (2 * p.G + 1) * FLAG_STRIDE, s);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
   const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;

@@ -157,7 +157,7 @@ struct JacArgs {
   double* W; double* V; int64_t ld;
   int l, nbp, G, max_sweeps;
   double tol;
-  uint32_t* tags;       // [G] rounds completed by each workgroup
+  uint32_t* tags;       // [G] rounds completed by each workgroup (FLAG_STRIDE apart)
   uint32_t* rot;        // [2][G] rotation flag of the current / previous sweep
   uint32_t* abort_flag;
   int32_t* info;
@@ -168,11 +168,11 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   const int tid = threadIdx.x;
   if (tid < a.G) {
     uint32_t spins = 0;
-    while (__hip_atomic_load(a.tags + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (ld_agent_u32(a.tags + tid * FLAG_STRIDE) < target) {
       if ((++spins & 63) == 0) {
-        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (ld_agent_u32(a.abort_flag)) break;
         if (spins > (1u << 22)) {
-          __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          st_agent_u32(a.abort_flag, 1u);
           info_or(a.info, INFO_BARRIER);
           break;
         }
@@ -180,7 +180,6 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
 }
 
@@ -199,13 +198,28 @@ __global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
   while (!converged && sweep < a.max_sweeps) {
     for (int r = 0; r < a.nbp - 1; ++r) {
       const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
-      // load the two blocks (columns >= l read as zero)
-      for (int c = wave; c < 2 * BS; c += JNT / 64) {
-        const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-        for (int i = lane; i < l; i += 64) {
-          const bool ok = gcol < l;
-          Wl[c * LD + i] = ok ? a.W[(int64_t)gcol * a.ld + i] : 0.0;
-          Vl[c * LD + i] = ok ? a.V[(int64_t)gcol * a.ld + i] : 0.0;
+      // load the two blocks (columns >= l read as zero): every thread issues
+      // all its loads before it writes any of them to LDS
+      {
+        constexpr int PER = (2 * BS * 256 + JNT - 1) / JNT;   // elements per thread
+        double wv[PER], vv[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int idx = tid + e * JNT;
+          const int c = idx / 256, i = idx % 256;
+          const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
+          const bool ok = c < 2 * BS && i < l && gcol < l;
+          wv[e] = ok ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
+          vv[e] = ok ? ld_agent(a.V + (int64_t)gcol * a.ld + i) : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int idx = tid + e * JNT;
+          const int c = idx / 256, i = idx % 256;
+          if (c < 2 * BS && i < l) {
+            Wl[c * LD + i] = wv[e];
+            Vl[c * LD + i] = vv[e];
+          }
         }
       }
       __syncthreads();
@@ -234,29 +248,32 @@ __global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
         }
         __syncthreads();
       }
-      for (int c = wave; c < 2 * BS; c += JNT / 64) {
-        const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-        if (gcol < l)
-          for (int i = lane; i < l; i += 64) {
-            a.W[(int64_t)gcol * a.ld + i] = Wl[c * LD + i];
-            a.V[(int64_t)gcol * a.ld + i] = Vl[c * LD + i];
+      {
+        constexpr int PER = (2 * BS * 256 + JNT - 1) / JNT;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int idx = tid + e * JNT;
+          const int c = idx / 256, i = idx % 256;
+          const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
+          if (c < 2 * BS && i < l && gcol < l) {
+            st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * LD + i]);
+            st_agent(a.V + (int64_t)gcol * a.ld + i, Vl[c * LD + i]);
           }
+        }
       }
       const bool last = (r == a.nbp - 2);
       if (last && tid == 0)
-        __hip_atomic_store(a.rot + (sweep & 1) * a.G + w, (uint32_t)rotated, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        st_agent_u32(a.rot + ((sweep & 1) * a.G + w) * FLAG_STRIDE, (uint32_t)rotated);
+      stores_done();
       __syncthreads();
       ++done;
-      if (tid == 0) __hip_atomic_store(a.tags + w, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) st_agent_u32(a.tags + w * FLAG_STRIDE, done);
       jac_wait_all(a, done);
     }
     // every workgroup reads the same flags, so all take the same decision
     uint32_t any = 0;
     for (int v = 0; v < a.G; ++v)
-      any |= __hip_atomic_load(a.rot + (sweep & 1) * a.G + v, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      any |= ld_agent_u32(a.rot + ((sweep & 1) * a.G + v) * FLAG_STRIDE);
     ++sweep;
     converged = (any == 0);
     __syncthreads();
@@ -297,7 +314,7 @@ __global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __rest
 
 size_t jacobi_work_bytes(int l) {
   // W, V (l x l each) and the control words of the block iteration
-  return 2 * (size_t)l * l * sizeof(double) + 64 * sizeof(uint32_t) + 256;
+  return 2 * (size_t)l * l * sizeof(double) + 64 * FLAG_STRIDE * sizeof(uint32_t) + 256;
 }
 
 hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
@@ -319,13 +336,13 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
   JacArgs a;
   a.W = W; a.V = V; a.ld = l; a.l = l; a.nbp = nbp; a.G = nbp / 2; a.max_sweeps = max_sweeps;
   a.tol = tol;
-  a.tags = ctl;
-  a.rot = ctl + 16;
-  a.abort_flag = ctl + 48;
+  a.tags = ctl;                                   // 16 flags
+  a.rot = ctl + 16 * FLAG_STRIDE;                 // 2 x 16 flags
+  a.abort_flag = ctl + 48 * FLAG_STRIDE;
   a.info = info;
   a.sweeps_out = sweeps_out;
   hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)cdiv((int64_t)l * l, 256)), dim3(256), 0,
-                     s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64);
+                     s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64 * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t shm = 4 * (size_t)BS * l * sizeof(double);
