@@ -139,17 +139,17 @@ def two_sided_id(A, J, k):
     return Jr, W, f['frank']
 
 
-def cur(A, k, p, q, seed):
+def cur(A, k, p, q, seed, Q=None):
     """Randomized CUR (Sec. 3.6 and Alg. 3): A ~ C U R.
 
     Column ID from B = Q^T A gives Jc and V; k steps of CPQR on C^T give Jr;
     R = A(Jr, :); with R^T = Qt Rt (thin Householder QR),
     U = V^T R^dagger = (V^T Qt) Rt^{-T}, i.e. the least-squares solution of
-    U R = V^T (Sec. 2.5).  Returns dict(Jc (k,), Jr (k,), U (k x k), ID
-    fields)."""
+    U R = V^T (Sec. 2.5).  Q, when given, is the range finder's basis (saves
+    recomputing it).  Returns dict(Jc (k,), Jr (k,), U (k x k), ID fields)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
-    d = qb_id(A, k, p, q, seed)
+    d = qb_id(A, k, p, q, seed, Q=Q)
     J, T = d['J'], d['T']
     Jc = J[:k]
     C = A[:, Jc]
