@@ -30,6 +30,30 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+# HBM bytes of one pass over A (Y = A X and Z = A^T X averaged), from the
+# FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
+# script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
+# below; valid only while the pass kernel's sources hash to "sources".
+PASS_TRAFFIC = {"sources": "9921d9cd6b63dd684232ac6ec45a6ffb6822c60b5ee97c34a85fdbe0cfb3b21e",
+                "bytes": 4164107650}
+PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
+
+
+def pass_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pass_traffic():
+    if PASS_TRAFFIC is None or PASS_TRAFFIC["sources"] != pass_sources_hash():
+        return None
+    return PASS_TRAFFIC["bytes"]
+
+
 def alg_flops(m, n, k, p, q):
     l = min(k + p, m, n)
     return (2 * (2 * q + 2) * m * n * l + (q + 1) * (2 * m * l * l - 2 * l ** 3 / 3)
@@ -198,7 +222,8 @@ def main():
                    "m": m, "n": n, "k": k, "p": p, "q": q, "l": l},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": pass_traffic(),
+                     "traffic_unit": "bytes per pass",
                      "kernel": "pass over A (gemm_sk_kernel + fix-up), FP64 MFMA 16x16x4",
                      "pass_ms": {kk: round(v, 4) for kk, v in pass_ms.items()},
                      "pass_hbm_GBs": round(a_bytes / (t_pass * 1e-3) / 1e9, 1),

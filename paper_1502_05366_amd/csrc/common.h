@@ -77,6 +77,49 @@ __device__ __forceinline__ void stores_done() {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+// Wave-wide helpers.  dpp_d moves a double between lanes with a DPP control
+// (both 32-bit halves); readlane_d reads one lane's value as a uniform.
+template <int CTRL> __device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 64 lanes of a wave (all lanes active), returned in every lane:
+// DPP exchanges inside each row of 16 lanes (xor 1, xor 2, half-row mirror,
+// row mirror leave every lane with its row's sum), then the four row sums
+// are added in a fixed order.
+__device__ __forceinline__ double wave_allsum(double x) {
+  x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
+  x += dpp_d<0x4E>(x);     // quad_perm [2, 3, 0, 1]
+  x += dpp_d<0x141>(x);    // row_half_mirror
+  x += dpp_d<0x140>(x);    // row_mirror
+  return ((readlane_d(x, 0) + readlane_d(x, 16)) + readlane_d(x, 32)) + readlane_d(x, 48);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (errors of a few ulps; x > 0 and normal).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 // flags live 128 bytes apart so that pollers of different flags do not share
 // a cache line
 constexpr int FLAG_STRIDE = 32;

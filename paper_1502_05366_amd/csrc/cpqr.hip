@@ -76,43 +76,13 @@ __device__ __forceinline__ void wait_tag(const uint32_t* tag, uint32_t value, ui
   }
 }
 
-// block-wide reductions (CQ_NT threads)
-__device__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < CQ_NT / 64; ++w) s += red[w];
-  __syncthreads();
-  return s;
-}
-
 // argmax of (val, idx): larger val wins, lower idx on equal val
 __device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t i2) {
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
 
-__device__ void block_argmax(double& v, int64_t& i, int& g, double* redv, int64_t* redi,
-                             int* redg) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int64_t oi = __shfl_xor(i, off, 64);
-    const int og = __shfl_xor(g, off, 64);
-    if (better(ov, oi, v, i)) { v = ov; i = oi; g = og; }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) { redv[wave] = v; redi[wave] = i; redg[wave] = g; }
-  __syncthreads();
-  v = redv[0]; i = redi[0]; g = redg[0];
-  for (int w = 1; w < CQ_NT / 64; ++w)
-    if (better(redv[w], redi[w], v, i)) { v = redv[w]; i = redi[w]; g = redg[w]; }
-  __syncthreads();
-}
+constexpr int CQ_NW = CQ_NT / 64;
+constexpr int CQ_RPL = 4;          // rows per lane: r <= 256
 
 template <typename TB>
 __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
@@ -130,11 +100,13 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   double* v = nrm + a.cs;                      // [rp]
   int* chosen_at = (int*)(v + rp);             // [cs] step at which chosen, -1 if not
   int64_t* piv = (int64_t*)(chosen_at + a.cs + (a.cs & 1));  // [k]
-  __shared__ double redv[CQ_NT / 64];
-  __shared__ int64_t redi[CQ_NT / 64];
-  __shared__ int redg[CQ_NT / 64];
-  __shared__ double red[CQ_NT / 64];
-  __shared__ double sh_beta, sh_alpha;
+  __shared__ double redv[2][CQ_NW];
+  __shared__ int64_t redi[2][CQ_NW];
+  __shared__ int redg[2][CQ_NW];
+  __shared__ double redf[CQ_NW];
+  __shared__ double sh_beta, sh_alpha, sh_gv;
+  __shared__ int64_t sh_gi;
+  __shared__ int sh_gg;
 
   const TB* Bt = static_cast<const TB*>(a.Bt);
   for (int64_t e = tid; e < ncols * rp; e += CQ_NT) {
@@ -143,77 +115,97 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     slab[e] = (i < r) ? (double)Bt[(j0 + jj) * a.ldb + i] : 0.0;
   }
   __syncthreads();
-  // initial norms and the workgroup's share of ||B||_F^2
+  // initial norms, the workgroup's share of ||B||_F^2 and each wave's best
+  // column (largest norm, lowest index on ties)
   double fpart = 0.0;
-  for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+  double bv = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
     double s2 = 0.0;
-    for (int i = lane; i < r; i += 64) { const double x = slab[jj * rp + i]; s2 += x * x; }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+    for (int e = 0; e < CQ_RPL; ++e) {
+      const int i = lane + 64 * e;
+      const double x = (i < r) ? slab[jj * rp + i] : 0.0;
+      s2 = fma(x, x, s2);
+    }
+    s2 = wave_allsum(s2);
     if (lane == 0) { nrm[jj] = s2; chosen_at[jj] = -1; }
-    fpart += (lane == 0) ? s2 : 0.0;
+    fpart += s2;
+    if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
   }
-  fpart = block_sum(fpart, red);
+  if (lane == 0) redf[wave] = fpart;
   double tol = 0.0;
   int frank = a.k;
 
   for (int s = 0; s < a.k; ++s) {
     const int par = s & 1;
-    // 1. local candidate, posted to this workgroup's slot
-    double bv = -1.0;
-    int64_t bi = INT64_MAX;
-    int bg = g;
-    for (int64_t jj = tid; jj < ncols; jj += CQ_NT) {
-      if (chosen_at[jj] >= 0) continue;
-      if (better(nrm[jj], j0 + jj, bv, bi)) { bv = nrm[jj]; bi = j0 + jj; }
-    }
-    block_argmax(bv, bi, bg, redv, redi, redg);
+    // 1. the workgroup's candidate (waves' bests, fixed order), posted
+    if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
+    __syncthreads();
     double* myslot = a.slots + ((int64_t)par * a.G + g) * a.slot_len;
+    double cv = redv[par][0];
+    int64_t ci = redi[par][0];
+    for (int w = 1; w < CQ_NW; ++w)
+      if (better(redv[par][w], redi[par][w], cv, ci)) { cv = redv[par][w]; ci = redi[par][w]; }
     if (tid == 0) {
-      st_agent(myslot + 0, bv);
-      st_agent(myslot + 1, (double)(bi == INT64_MAX ? -1 : bi));
-      st_agent(myslot + 2, fpart);
+      double f = 0.0;
+      if (s == 0)
+        for (int w = 0; w < CQ_NW; ++w) f += redf[w];
+      st_agent(myslot + 0, cv);
+      st_agent(myslot + 1, (double)(ci == INT64_MAX ? -1 : ci));
+      st_agent(myslot + 2, f);
     }
-    if (bi != INT64_MAX) {
-      const int64_t jj = bi - j0;
+    if (ci != INT64_MAX) {
+      const int64_t jj = ci - j0;
       for (int i = s + tid; i < r; i += CQ_NT) st_agent(myslot + 3 + i, slab[jj * rp + i]);
     }
     post_tag(a.tags + (par * a.G + g) * FLAG_STRIDE, (uint32_t)s + 1u);
-    // 2./3. wait for every slot of this step, then pick the global pivot
+    // 2./3. thread w waits for workgroup w's tag and reads its candidate; the
+    // global pivot is the best candidate (lowest index on ties)
     double gv = -1.0;
     int64_t gi = INT64_MAX;
     int gg = 0;
     double fro_part = 0.0;
-    for (int w = tid; w < a.G; w += CQ_NT)
-      wait_tag(a.tags + (par * a.G + w) * FLAG_STRIDE, (uint32_t)s + 1u, a.abort_flag, a.info);
-    __syncthreads();
     for (int w = tid; w < a.G; w += CQ_NT) {
+      wait_tag(a.tags + (par * a.G + w) * FLAG_STRIDE, (uint32_t)s + 1u, a.abort_flag, a.info);
       const double* sl = a.slots + ((int64_t)par * a.G + w) * a.slot_len;
       const double vv = ld_agent(sl + 0);
       const double iv = ld_agent(sl + 1);
       if (s == 0) fro_part += ld_agent(sl + 2);
-      if (iv < 0.0) continue;
-      const int64_t ii = (int64_t)iv;
-      if (better(vv, ii, gv, gi)) { gv = vv; gi = ii; gg = w; }
+      if (iv >= 0.0) {
+        const int64_t ii = (int64_t)iv;
+        if (better(vv, ii, gv, gi)) { gv = vv; gi = ii; gg = w; }
+      }
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(gv, off, 64);
+      const int64_t oi = __shfl_xor(gi, off, 64);
+      const int og = __shfl_xor(gg, off, 64);
+      if (better(ov, oi, gv, gi)) { gv = ov; gi = oi; gg = og; }
+    }
+    if (s == 0) fro_part = wave_allsum(fro_part);
+    const int rb = par ^ 1;                // the other half of the reduction buffers
+    if (lane == 0) { redv[rb][wave] = gv; redi[rb][wave] = gi; redg[rb][wave] = gg; }
+    if (s == 0 && lane == 0) redf[wave] = fro_part;
+    __syncthreads();
+    gv = redv[rb][0]; gi = redi[rb][0]; gg = redg[rb][0];
+    for (int w = 1; w < CQ_NW; ++w)
+      if (better(redv[rb][w], redi[rb][w], gv, gi)) { gv = redv[rb][w]; gi = redi[rb][w]; gg = redg[rb][w]; }
     if (s == 0) {
-      const double fro2 = block_sum(fro_part, red);
+      double fro2 = 0.0;
+      for (int w = 0; w < CQ_NW; ++w) fro2 += redf[w];
       tol = (double)(r > a.c ? r : a.c) * DEPS * sqrt(fro2);
     }
-    block_argmax(gv, gi, gg, redv, redi, redg);
     if (gi < 0 || gi >= a.c) { gi = 0; gg = 0; }     // only after an aborted barrier
+    // the pivot's posted norm^2 is ||x||^2 of its rows s..r-1
     const double pnorm = sqrt(gv > 0.0 ? gv : 0.0);
     if (frank == a.k && pnorm <= tol) frank = s;
     const double* psl = a.slots + ((int64_t)par * a.G + gg) * a.slot_len;
-    double xs2 = 0.0;
-    for (int i = s + tid; i < r; i += CQ_NT) {
-      const double x = ld_agent(psl + 3 + i);
-      v[i] = x;
-      xs2 += x * x;
-    }
-    xs2 = block_sum(xs2, red);           // also orders the writes of v
+    for (int i = s + tid; i < r; i += CQ_NT) v[i] = ld_agent(psl + 3 + i);
+    __syncthreads();
     if (tid == 0) {
-      const double normx = sqrt(xs2);
+      const double normx = pnorm;
       const double x0 = v[s];
       if (normx == 0.0) {
         sh_beta = 0.0;
@@ -229,11 +221,21 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
         a.J[s] = gi;
         a.pivn[s] = pnorm;
       }
+      piv[s] = gi;
     }
     __syncthreads();
     const double beta = sh_beta, alpha = sh_alpha;
-    // apply H to the unchosen owned columns (one wave per column)
-    for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+    double vr[CQ_RPL];
+#pragma unroll
+    for (int e = 0; e < CQ_RPL; ++e) {
+      const int i = lane + 64 * e;
+      vr[e] = (i >= s && i < r) ? v[i] : 0.0;
+    }
+    // apply H to the unchosen owned columns (one wave per column), recompute
+    // their norms over rows s+1.. and track each wave's best column
+    bv = -1.0;
+    bi = INT64_MAX;
+    for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
       if (chosen_at[jj] >= 0) continue;
       double* col = slab + jj * rp;
       if (j0 + jj == gi) {
@@ -241,29 +243,43 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
         if (lane == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
         continue;
       }
-      if (beta != 0.0) {
-        double w = 0.0;
-        for (int i = s + lane; i < r; i += 64) w += v[i] * col[i];
+      double x[CQ_RPL];
+      double dot = 0.0;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-        w *= beta;
-        for (int i = s + lane; i < r; i += 64) col[i] -= w * v[i];
+      for (int e = 0; e < CQ_RPL; ++e) {
+        const int i = lane + 64 * e;
+        x[e] = (i < r) ? col[i] : 0.0;
+        dot = fma(vr[e], x[e], dot);
+      }
+      if (beta != 0.0) {
+        const double w = beta * wave_allsum(dot);
+#pragma unroll
+        for (int e = 0; e < CQ_RPL; ++e) {
+          const int i = lane + 64 * e;
+          if (i >= s && i < r) {
+            x[e] = fma(-w, vr[e], x[e]);
+            col[i] = x[e];
+          }
+        }
       }
       double s2 = 0.0;
-      for (int i = s + 1 + lane; i < r; i += 64) { const double x = col[i]; s2 += x * x; }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+      for (int e = 0; e < CQ_RPL; ++e) {
+        const int i = lane + 64 * e;
+        if (i > s && i < r) s2 = fma(x[e], x[e], s2);
+      }
+      s2 = wave_allsum(s2);
       if (lane == 0) nrm[jj] = s2;
+      if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
     }
-    if (tid == 0) piv[s] = gi;
-    __syncthreads();
   }
+  __syncthreads();
   if (g == 0 && tid == 0 && frank < a.k) {
     info_or(a.info, INFO_RANK);
     a.info[1] = frank;
   }
   // outputs: top k rows of every owned column
-  for (int64_t jj = wave; jj < ncols; jj += CQ_NT / 64) {
+  for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
     const int64_t j = j0 + jj;
     const int t = chosen_at[jj];
     double* dst;
@@ -350,7 +366,7 @@ CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
   p.cs = cdiv(c, G);
   p.lds = cpqr_lds_bytes(p.cs, p.rp, k);
   p.slot_len = 3 + p.rp;
-  p.ok = p.lds <= 150 * 1024 && k <= 256 && k <= r && k <= c;
+  p.ok = p.lds <= 150 * 1024 && r <= 256 && k <= 256 && k <= r && k <= c;
   return p;
 }
 

@@ -31,6 +31,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Rotation (c, s) that orthogonalizes a column pair with squared norms al, be
+// and inner product ga (the formulas in the header); false when the pair is
+// already orthogonal to within tol.
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol,
+                                                double& cs, double& sn) {
+  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+  const double az = fabs(zeta);
+  double t;
+  if (az < 1e150) {
+    const double z2 = fma(zeta, zeta, 1.0);
+    t = rcp_nr(az + z2 * rsq_nr(z2));
+  } else {
+    t = 0.5 / az;
+  }
+  t = zeta >= 0.0 ? t : -t;
+  cs = rsq_nr(fma(t, t, 1.0));
+  sn = cs * t;
+  return true;
+}
+
 __device__ __forceinline__ int rr_player(int pos, int r, int N) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (N - 1)) + 1;
 }
@@ -78,12 +99,9 @@ __device__ __forceinline__ bool rotate_pair(double* wa, double* wb, double* va, 
     const double x = wa[i], y = wb[i];
     al += x * x; be += y * y; ga += x * y;
   }
-  al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
-  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t);
-  const double sn = cs * t;
+  al = wave_allsum(al); be = wave_allsum(be); ga = wave_allsum(ga);
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
   for (int i = lane; i < l; i += 64) {
     const double x = wa[i], y = wb[i];
     wa[i] = cs * x - sn * y;
@@ -183,14 +201,44 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   __syncthreads();
 }
 
+// One column pair held by a wave, 4 rows per lane (rows lane + 64 e; rows
+// >= l are zero): rotate when not orthogonal.
+__device__ __forceinline__ bool rotate_regs(double (&xw)[4], double (&xv)[4], double (&yw)[4],
+                                            double (&yv)[4], double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    al = fma(xw[e], xw[e], al);
+    be = fma(yw[e], yw[e], be);
+    ga = fma(xw[e], yw[e], ga);
+  }
+  al = wave_allsum(al);
+  be = wave_allsum(be);
+  ga = wave_allsum(ga);
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double a = xw[e], b = yw[e];
+    xw[e] = cs * a - sn * b;
+    yw[e] = sn * a + cs * b;
+    const double c = xv[e], d = yv[e];
+    xv[e] = cs * c - sn * d;
+    yv[e] = sn * c + cs * d;
+  }
+  return true;
+}
+
+constexpr int JLD = 256;    // LDS column length (rows >= l hold zeros)
+
 __global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
   extern __shared__ double smem[];
   __shared__ int rotated;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int w = blockIdx.x;
-  const int l = a.l, LD = l;
-  double* Wl = smem;                        // [2*BS][LD]
-  double* Vl = smem + 2 * BS * LD;
+  const int l = a.l;
+  double* Wl = smem;                        // [2*BS][JLD]
+  double* Vl = smem + 2 * BS * JLD;
   uint32_t done = 0;
   int sweep = 0;
   bool converged = false;
@@ -198,66 +246,98 @@ __global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
   while (!converged && sweep < a.max_sweeps) {
     for (int r = 0; r < a.nbp - 1; ++r) {
       const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
-      // load the two blocks (columns >= l read as zero): every thread issues
-      // all its loads before it writes any of them to LDS
+      // load the two blocks (columns >= l and rows >= l read as zero): every
+      // thread issues all its loads before it writes any of them to LDS
       {
-        constexpr int PER = (2 * BS * 256 + JNT - 1) / JNT;   // elements per thread
+        constexpr int PER = 2 * BS * JLD / JNT;
         double wv[PER], vv[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JNT;
-          const int c = idx / 256, i = idx % 256;
+          const int c = idx / JLD, i = idx % JLD;
           const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-          const bool ok = c < 2 * BS && i < l && gcol < l;
+          const bool ok = i < l && gcol < l;
           wv[e] = ok ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
           vv[e] = ok ? ld_agent(a.V + (int64_t)gcol * a.ld + i) : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JNT;
-          const int c = idx / 256, i = idx % 256;
-          if (c < 2 * BS && i < l) {
-            Wl[c * LD + i] = wv[e];
-            Vl[c * LD + i] = vv[e];
-          }
+          Wl[tid + e * JNT] = wv[e];
+          Vl[tid + e * JNT] = vv[e];
         }
       }
       __syncthreads();
+      bool rot = false;
       if (r == 0) {
         // pairs inside each block: BS-1 round-robin rounds, both blocks at once
         for (int t = 0; t < BS - 1; ++t) {
-          if (wave < BS) {
-            const int half = wave / (BS / 2), pi = wave % (BS / 2);
-            int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
-            if (p > q) { const int x = p; p = q; q = x; }
-            p += half * BS; q += half * BS;
-            if (rotate_pair(Wl + p * LD, Wl + q * LD, Vl + p * LD, Vl + q * LD, l, lane, a.tol) &&
-                lane == 0)
-              rotated = 1;
+          const int half = wave / (BS / 2), pi = wave % (BS / 2);
+          int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
+          if (p > q) { const int x = p; p = q; q = x; }
+          p += half * BS; q += half * BS;
+          double xw[4], xv[4], yw[4], yv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            xw[e] = Wl[p * JLD + lane + 64 * e]; xv[e] = Vl[p * JLD + lane + 64 * e];
+            yw[e] = Wl[q * JLD + lane + 64 * e]; yv[e] = Vl[q * JLD + lane + 64 * e];
+          }
+          if (rotate_regs(xw, xv, yw, yv, a.tol)) {
+            rot = true;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              Wl[p * JLD + lane + 64 * e] = xw[e]; Vl[p * JLD + lane + 64 * e] = xv[e];
+              Wl[q * JLD + lane + 64 * e] = yw[e]; Vl[q * JLD + lane + 64 * e] = yv[e];
+            }
           }
           __syncthreads();
         }
       }
-      // cross pairs: (x_i, y_{(i+t) mod BS}) for t = 0 .. BS-1
-      for (int t = 0; t < BS; ++t) {
-        if (wave < BS) {
-          const int p = wave, q = BS + (wave + t) % BS;
-          if (rotate_pair(Wl + p * LD, Wl + q * LD, Vl + p * LD, Vl + q * LD, l, lane, a.tol) &&
-              lane == 0)
-            rotated = 1;
-        }
-        __syncthreads();
-      }
+      // cross pairs (x_p, y_{(p+t) mod BS}), t = 0 .. BS-1: wave p keeps x_p in
+      // registers, the y columns move from wave to wave through LDS
       {
-        constexpr int PER = (2 * BS * 256 + JNT - 1) / JNT;
+        const int p = wave;
+        double xw[4], xv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xw[e] = Wl[p * JLD + lane + 64 * e];
+          xv[e] = Vl[p * JLD + lane + 64 * e];
+        }
+        for (int t = 0; t < BS; ++t) {
+          const int q = BS + (p + t) % BS;
+          double yw[4], yv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            yw[e] = Wl[q * JLD + lane + 64 * e];
+            yv[e] = Vl[q * JLD + lane + 64 * e];
+          }
+          if (rotate_regs(xw, xv, yw, yv, a.tol)) {
+            rot = true;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              Wl[q * JLD + lane + 64 * e] = yw[e];
+              Vl[q * JLD + lane + 64 * e] = yv[e];
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          Wl[p * JLD + lane + 64 * e] = xw[e];
+          Vl[p * JLD + lane + 64 * e] = xv[e];
+        }
+      }
+      if (rot && lane == 0) rotated = 1;
+      __syncthreads();
+      {
+        constexpr int PER = 2 * BS * JLD / JNT;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JNT;
-          const int c = idx / 256, i = idx % 256;
+          const int c = idx / JLD, i = idx % JLD;
           const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-          if (c < 2 * BS && i < l && gcol < l) {
-            st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * LD + i]);
-            st_agent(a.V + (int64_t)gcol * a.ld + i, Vl[c * LD + i]);
+          if (i < l && gcol < l) {
+            st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[idx]);
+            st_agent(a.V + (int64_t)gcol * a.ld + i, Vl[idx]);
           }
         }
       }
@@ -345,7 +425,7 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                      s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64 * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t shm = 4 * (size_t)BS * l * sizeof(double);
+  const size_t shm = 4 * (size_t)BS * JLD * sizeof(double);
   e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
