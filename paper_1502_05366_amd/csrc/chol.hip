@@ -81,6 +81,8 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
   __shared__ double Tw[CH_NW][16 * 16]; // per-wave transpose scratch
   __shared__ int depblk[16];
   __shared__ double diag0[256];
+  __shared__ double rowb[16];           // row j of R_ss (diagonal-block step j)
+  __shared__ double xcb[16];            // column j of R_ss^{-1}
 
   for (int j = tid; j < lp; j += CH_NT) diag0[j] = (j < l) ? G[(int64_t)j * ldg + j] : 1.0;
   // zero the strictly lower part of R
@@ -111,32 +113,58 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
     }
     __syncthreads();
     // (b) wave 0 factors the 16x16 block held in its 64 lanes (accumulator
-    // layout: lane (g, c) element v is row 4v + g, column c) and inverts it
+    // layout: lane (g, c) element v is row 4v + g, column c) and builds
+    // X = R_ss^{-1} alongside, column by column:
+    //   X[r][j] = (delta_rj - S_r[j]) / R[j][j],  S_r[b] += X[r][j] R[j][b] (b > j),
+    // where S_r[b] = sum_{a<b} X[r][a] R[a][b] waits in element (r, b) of y.
+    // Row j of R and column j of X reach every lane through two 16-entry
+    // LDS buffers; the pivot is read as a uniform value.
     if (wave == 0) {
       const int g = lk, c = li;
       double x[4], y[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) x[v] = Dss[drow(g, v) * 17 + c];
+      for (int v = 0; v < 4; ++v) { x[v] = Dss[drow(g, v) * 17 + c]; y[v] = 0.0; }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int vj = j >> 2, gj_lane = 16 * (j & 3);
-        const double d = shfl_d(x[vj], gj_lane + j);
+        const int vj = j >> 2, gj = j & 3;
+        const double d = readlane_d(x[vj], 16 * gj + j);      // Schur pivot G'[j][j]
         const int gcol = s * 16 + j;
         const bool finite = isfinite(d);
         const bool ok = finite && d > eta * diag0[gcol];
-        const double rjj = ok ? sqrt(d) : 1.0;
-        // row j of R for this lane's column c
-        double rj = shfl_d(x[vj], gj_lane + c);
-        if (c == j) rj = rjj;
-        else if (c > j) rj = ok ? rj / rjj : 0.0;
-        else rj = 0.0;
+        const double inv = ok ? rsq_nr(d) : 1.0;             // 1 / R[j][j]
+        const double rjj = ok ? d * inv : 1.0;
+        if (g == gj) {
+          // this lane holds G'[j][c]: row j of R, and (lane c == j) column j of X
+          double rj;
+          if (c == j) rj = rjj;
+          else if (c > j) rj = ok ? x[vj] * inv : 0.0;
+          else rj = 0.0;
+          rowb[c] = rj;
+        }
+        if (c == j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = drow(g, v);
+            y[v] = ((r == j ? 1.0 : 0.0) - y[v]) * inv;
+            xcb[r] = y[v];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double rjc = rowb[c];                           // R[j][c]
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a = drow(g, v);
-          const double rja = shfl_d(rj, a);        // R[j][a] from any lane of column a
-          if (a > j && a <= c) x[v] -= rja * rj;
-          if (a == j) x[v] = rj;
+          const double rja = rowb[a];                         // R[j][a]
+          const double xaj = xcb[a];                          // X[a][j]
+          if (a > j && a <= c) x[v] = fma(-rja, rjc, x[v]);
+          if (a == j) x[v] = rjc;
+          if (c > j) y[v] = fma(xaj, rjc, y[v]);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane == 0) {
           depblk[j] = ok ? 0 : 1;
           if (gcol < l) {
@@ -151,25 +179,6 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
       for (int v = 0; v < 4; ++v) {
         const int a = drow(g, v);
         if (a > c) x[v] = 0.0;
-        y[v] = (a == c) ? 1.0 : 0.0;
-      }
-      // X = R_ss^{-1} by back substitution on all columns at once
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        const int vi = i >> 2, gi_lane = 16 * (i & 3);
-        const double rii = shfl_d(x[vi], gi_lane + i);
-        const double xi = shfl_d(y[vi], gi_lane + c) / rii;     // X[i][c]
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = drow(g, v);
-          const double rai = shfl_d(x[v], 16 * g + i);          // R[a][i]
-          if (a < i) y[v] -= rai * xi;
-          if (a == i) y[v] = xi;
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = drow(g, v);
         R[(int64_t)(s * 16 + a) * ldr + s * 16 + c] = x[v];
         Xss[a * 16 + c] = y[v];
         Rdinv[(int64_t)s * 256 + a * 16 + c] = y[v];

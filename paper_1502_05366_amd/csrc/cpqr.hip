@@ -22,7 +22,7 @@
 namespace rsvd {
 namespace {
 
-constexpr int CQ_NT = 1024;
+constexpr int CQ_NT = 512;
 constexpr double DEPS = 2.220446049250313e-16;
 
 struct CpqrArgs {
@@ -82,12 +82,22 @@ __device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t
 }
 
 constexpr int CQ_NW = CQ_NT / 64;
-constexpr int CQ_RPL = 4;          // rows per lane: r <= 256
+constexpr int CQ_RPL = 16;         // rows per lane (16 lanes per column): r <= 256
+
+// sum over the 16 lanes of a row, returned in each of them
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_d<0xB1>(x);
+  x += dpp_d<0x4E>(x);
+  x += dpp_d<0x141>(x);
+  x += dpp_d<0x140>(x);
+  return x;
+}
 
 template <typename TB>
 __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cg = lane >> 4, rl = lane & 15;
   const int g = blockIdx.x;
   const int64_t j0 = (int64_t)g * a.cs;
   int64_t ncols = a.c - j0;
@@ -115,31 +125,42 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     slab[e] = (i < r) ? (double)Bt[(j0 + jj) * a.ldb + i] : 0.0;
   }
   __syncthreads();
-  // initial norms, the workgroup's share of ||B||_F^2 and each wave's best
-  // column (largest norm, lowest index on ties)
+  // initial norms, the workgroup's share of ||B||_F^2 and each lane's best
+  // column (largest norm, lowest index on ties).  A column is handled by one
+  // row of 16 lanes (rows rl + 16 e of the column), four columns per wave.
   double fpart = 0.0;
   double bv = -1.0;
   int64_t bi = INT64_MAX;
-  for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
+  for (int64_t jb = 0; jb < ncols; jb += CQ_NW * 4) {
+    const int64_t jj = jb + wave * 4 + cg;
+    const bool act = jj < ncols;
     double s2 = 0.0;
 #pragma unroll
     for (int e = 0; e < CQ_RPL; ++e) {
-      const int i = lane + 64 * e;
-      const double x = (i < r) ? slab[jj * rp + i] : 0.0;
+      const int i = rl + 16 * e;
+      const double x = (act && i < r) ? slab[jj * rp + i] : 0.0;
       s2 = fma(x, x, s2);
     }
-    s2 = wave_allsum(s2);
-    if (lane == 0) { nrm[jj] = s2; chosen_at[jj] = -1; }
-    fpart += s2;
-    if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+    s2 = row16_sum(s2);
+    if (act) {
+      if (rl == 0) { nrm[jj] = s2; chosen_at[jj] = -1; fpart += s2; }
+      if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+    }
   }
+  fpart = wave_allsum(fpart);
   if (lane == 0) redf[wave] = fpart;
   double tol = 0.0;
   int frank = a.k;
 
   for (int s = 0; s < a.k; ++s) {
     const int par = s & 1;
-    // 1. the workgroup's candidate (waves' bests, fixed order), posted
+    // 1. the workgroup's candidate (lanes' bests, fixed order), posted
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int64_t oi = __shfl_xor(bi, off, 64);
+      if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
     if (lane == 0) { redv[par][wave] = bv; redi[par][wave] = bi; }
     __syncthreads();
     double* myslot = a.slots + ((int64_t)par * a.G + g) * a.slot_len;
@@ -228,49 +249,56 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     double vr[CQ_RPL];
 #pragma unroll
     for (int e = 0; e < CQ_RPL; ++e) {
-      const int i = lane + 64 * e;
+      const int i = rl + 16 * e;
       vr[e] = (i >= s && i < r) ? v[i] : 0.0;
     }
-    // apply H to the unchosen owned columns (one wave per column), recompute
-    // their norms over rows s+1.. and track each wave's best column
+    // apply H to the unchosen owned columns, recompute their norms over rows
+    // s+1.. and track each lane's best column
     bv = -1.0;
     bi = INT64_MAX;
-    for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
-      if (chosen_at[jj] >= 0) continue;
+    for (int64_t jb = 0; jb < ncols; jb += CQ_NW * 4) {
+      const int64_t jj = jb + wave * 4 + cg;
+      const bool act = (jj < ncols) ? (chosen_at[jj] < 0) : false;
+      const bool is_piv = act && (j0 + jj == gi);
       double* col = slab + jj * rp;
-      if (j0 + jj == gi) {
-        for (int i = s + lane; i < r; i += 64) col[i] = (i == s) ? alpha : 0.0;
-        if (lane == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
-        continue;
-      }
       double x[CQ_RPL];
       double dot = 0.0;
 #pragma unroll
       for (int e = 0; e < CQ_RPL; ++e) {
-        const int i = lane + 64 * e;
-        x[e] = (i < r) ? col[i] : 0.0;
+        const int i = rl + 16 * e;
+        x[e] = (act && i < r) ? col[i] : 0.0;
         dot = fma(vr[e], x[e], dot);
       }
-      if (beta != 0.0) {
-        const double w = beta * wave_allsum(dot);
+      const double wdot = beta * row16_sum(dot);
+      if (act && !is_piv && beta != 0.0) {
 #pragma unroll
         for (int e = 0; e < CQ_RPL; ++e) {
-          const int i = lane + 64 * e;
+          const int i = rl + 16 * e;
           if (i >= s && i < r) {
-            x[e] = fma(-w, vr[e], x[e]);
+            x[e] = fma(-wdot, vr[e], x[e]);
             col[i] = x[e];
           }
         }
       }
+      if (is_piv) {
+#pragma unroll
+        for (int e = 0; e < CQ_RPL; ++e) {
+          const int i = rl + 16 * e;
+          if (i >= s && i < r) col[i] = (i == s) ? alpha : 0.0;
+        }
+        if (rl == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
+      }
       double s2 = 0.0;
 #pragma unroll
       for (int e = 0; e < CQ_RPL; ++e) {
-        const int i = lane + 64 * e;
+        const int i = rl + 16 * e;
         if (i > s && i < r) s2 = fma(x[e], x[e], s2);
       }
-      s2 = wave_allsum(s2);
-      if (lane == 0) nrm[jj] = s2;
-      if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+      s2 = row16_sum(s2);
+      if (act && !is_piv) {
+        if (rl == 0) nrm[jj] = s2;
+        if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+      }
     }
   }
   __syncthreads();

@@ -201,24 +201,40 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   __syncthreads();
 }
 
-// One column pair held by a wave, 4 rows per lane (rows lane + 64 e; rows
-// >= l are zero): rotate when not orthogonal.
-__device__ __forceinline__ bool rotate_regs(double (&xw)[4], double (&xv)[4], double (&yw)[4],
-                                            double (&yv)[4], double tol) {
+// The block kernel gives each column pair to one row of 16 lanes, so a wave
+// works on four pairs at once: lane (row g, position c) holds rows c + 16 e
+// (e = 0..15) of both columns of its pair.  Sums over a pair are DPP
+// exchanges inside the row; the rotation is computed by every lane of the row
+// (rows whose pair is already orthogonal apply the identity).
+constexpr int JB_NT = 256;   // 4 waves x 4 pairs = BS pairs per step
+constexpr int JLD = 256;     // LDS column length (rows >= l hold zeros)
+constexpr int JRPL = JLD / 16;
+
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
+  x += dpp_d<0x4E>(x);     // quad_perm [2, 3, 0, 1]
+  x += dpp_d<0x141>(x);    // row_half_mirror
+  x += dpp_d<0x140>(x);    // row_mirror
+  return x;
+}
+
+__device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xv)[JRPL],
+                                             double (&yw)[JRPL], double (&yv)[JRPL], double tol) {
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < JRPL; ++e) {
     al = fma(xw[e], xw[e], al);
     be = fma(yw[e], yw[e], be);
     ga = fma(xw[e], yw[e], ga);
   }
-  al = wave_allsum(al);
-  be = wave_allsum(be);
-  ga = wave_allsum(ga);
+  al = row16_sum(al);
+  be = row16_sum(be);
+  ga = row16_sum(ga);
   double cs, sn;
-  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+  const bool rot = jacobi_rotation(al, be, ga, tol, cs, sn);
+  if (!rot) { cs = 1.0; sn = 0.0; }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < JRPL; ++e) {
     const double a = xw[e], b = yw[e];
     xw[e] = cs * a - sn * b;
     yw[e] = sn * a + cs * b;
@@ -226,15 +242,24 @@ __device__ __forceinline__ bool rotate_regs(double (&xw)[4], double (&xv)[4], do
     xv[e] = cs * c - sn * d;
     yv[e] = sn * c + cs * d;
   }
-  return true;
+  return rot;
 }
 
-constexpr int JLD = 256;    // LDS column length (rows >= l hold zeros)
+__device__ __forceinline__ void lds_col_load(const double* base, int rl, double (&v)[JRPL]) {
+#pragma unroll
+  for (int e = 0; e < JRPL; ++e) v[e] = base[rl + 16 * e];
+}
+__device__ __forceinline__ void lds_col_store(double* base, int rl, const double (&v)[JRPL]) {
+#pragma unroll
+  for (int e = 0; e < JRPL; ++e) base[rl + 16 * e] = v[e];
+}
 
-__global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
+__global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   extern __shared__ double smem[];
   __shared__ int rotated;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rl = lane & 15;
+  const int ps = wave * 4 + (lane >> 4);    // pair slot 0 .. BS-1
   const int w = blockIdx.x;
   const int l = a.l;
   double* Wl = smem;                        // [2*BS][JLD]
@@ -246,93 +271,62 @@ __global__ __launch_bounds__(JNT) void jacobi_block_kernel(JacArgs a) {
   while (!converged && sweep < a.max_sweeps) {
     for (int r = 0; r < a.nbp - 1; ++r) {
       const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
-      // load the two blocks (columns >= l and rows >= l read as zero): every
-      // thread issues all its loads before it writes any of them to LDS
-      {
-        constexpr int PER = 2 * BS * JLD / JNT;
-        double wv[PER], vv[PER];
+      // load the two blocks (columns >= l and rows >= l read as zero), W then
+      // V, each thread issuing all its loads of a matrix before its LDS writes
+      constexpr int PER = 2 * BS * JLD / JB_NT;
+#pragma unroll
+      for (int mtx = 0; mtx < 2; ++mtx) {
+        const double* src = mtx ? a.V : a.W;
+        double* dst = mtx ? Vl : Wl;
+        double vv[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JNT;
+          const int idx = tid + e * JB_NT;
           const int c = idx / JLD, i = idx % JLD;
           const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-          const bool ok = i < l && gcol < l;
-          wv[e] = ok ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
-          vv[e] = ok ? ld_agent(a.V + (int64_t)gcol * a.ld + i) : 0.0;
+          vv[e] = (i < l && gcol < l) ? ld_agent(src + (int64_t)gcol * a.ld + i) : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-          Wl[tid + e * JNT] = wv[e];
-          Vl[tid + e * JNT] = vv[e];
-        }
+        for (int e = 0; e < PER; ++e) dst[tid + e * JB_NT] = vv[e];
       }
       __syncthreads();
       bool rot = false;
+      double xw[JRPL], xv[JRPL], yw[JRPL], yv[JRPL];
       if (r == 0) {
         // pairs inside each block: BS-1 round-robin rounds, both blocks at once
         for (int t = 0; t < BS - 1; ++t) {
-          const int half = wave / (BS / 2), pi = wave % (BS / 2);
+          const int half = ps / (BS / 2), pi = ps % (BS / 2);
           int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
           if (p > q) { const int x = p; p = q; q = x; }
           p += half * BS; q += half * BS;
-          double xw[4], xv[4], yw[4], yv[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            xw[e] = Wl[p * JLD + lane + 64 * e]; xv[e] = Vl[p * JLD + lane + 64 * e];
-            yw[e] = Wl[q * JLD + lane + 64 * e]; yv[e] = Vl[q * JLD + lane + 64 * e];
-          }
-          if (rotate_regs(xw, xv, yw, yv, a.tol)) {
-            rot = true;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              Wl[p * JLD + lane + 64 * e] = xw[e]; Vl[p * JLD + lane + 64 * e] = xv[e];
-              Wl[q * JLD + lane + 64 * e] = yw[e]; Vl[q * JLD + lane + 64 * e] = yv[e];
-            }
-          }
+          lds_col_load(Wl + p * JLD, rl, xw); lds_col_load(Vl + p * JLD, rl, xv);
+          lds_col_load(Wl + q * JLD, rl, yw); lds_col_load(Vl + q * JLD, rl, yv);
+          rot |= rotate_row16(xw, xv, yw, yv, a.tol);
+          lds_col_store(Wl + p * JLD, rl, xw); lds_col_store(Vl + p * JLD, rl, xv);
+          lds_col_store(Wl + q * JLD, rl, yw); lds_col_store(Vl + q * JLD, rl, yv);
           __syncthreads();
         }
       }
-      // cross pairs (x_p, y_{(p+t) mod BS}), t = 0 .. BS-1: wave p keeps x_p in
-      // registers, the y columns move from wave to wave through LDS
+      // cross pairs (x_p, y_{(p+t) mod BS}), t = 0 .. BS-1: pair slot p keeps
+      // x_p in registers, the y columns move between slots through LDS
       {
-        const int p = wave;
-        double xw[4], xv[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          xw[e] = Wl[p * JLD + lane + 64 * e];
-          xv[e] = Vl[p * JLD + lane + 64 * e];
-        }
+        const int p = ps;
+        lds_col_load(Wl + p * JLD, rl, xw); lds_col_load(Vl + p * JLD, rl, xv);
         for (int t = 0; t < BS; ++t) {
           const int q = BS + (p + t) % BS;
-          double yw[4], yv[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            yw[e] = Wl[q * JLD + lane + 64 * e];
-            yv[e] = Vl[q * JLD + lane + 64 * e];
-          }
-          if (rotate_regs(xw, xv, yw, yv, a.tol)) {
-            rot = true;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              Wl[q * JLD + lane + 64 * e] = yw[e];
-              Vl[q * JLD + lane + 64 * e] = yv[e];
-            }
-          }
+          lds_col_load(Wl + q * JLD, rl, yw); lds_col_load(Vl + q * JLD, rl, yv);
+          rot |= rotate_row16(xw, xv, yw, yv, a.tol);
+          lds_col_store(Wl + q * JLD, rl, yw); lds_col_store(Vl + q * JLD, rl, yv);
           __syncthreads();
         }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          Wl[p * JLD + lane + 64 * e] = xw[e];
-          Vl[p * JLD + lane + 64 * e] = xv[e];
-        }
+        lds_col_store(Wl + p * JLD, rl, xw); lds_col_store(Vl + p * JLD, rl, xv);
       }
-      if (rot && lane == 0) rotated = 1;
+      if (rot) rotated = 1;
       __syncthreads();
       {
-        constexpr int PER = 2 * BS * JLD / JNT;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JNT;
+          const int idx = tid + e * JB_NT;
           const int c = idx / JLD, i = idx % JLD;
           const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
           if (i < l && gcol < l) {
@@ -430,7 +424,7 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JNT), args, shm,
+  e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args, shm,
                                  s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, (int64_t)l, l, k, S, Uh,
