@@ -246,12 +246,6 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     }
     __syncthreads();
     const double beta = sh_beta, alpha = sh_alpha;
-    double vr[CQ_RPL];
-#pragma unroll
-    for (int e = 0; e < CQ_RPL; ++e) {
-      const int i = rl + 16 * e;
-      vr[e] = (i >= s && i < r) ? v[i] : 0.0;
-    }
     // apply H to the unchosen owned columns, recompute their norms over rows
     // s+1.. and track each lane's best column
     bv = -1.0;
@@ -261,15 +255,16 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
       const bool act = (jj < ncols) ? (chosen_at[jj] < 0) : false;
       const bool is_piv = act && (j0 + jj == gi);
       double* col = slab + jj * rp;
-      double x[CQ_RPL];
-      double dot = 0.0;
+      double x[CQ_RPL], vr[CQ_RPL];
+      double dp[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: short FMA chains
 #pragma unroll
       for (int e = 0; e < CQ_RPL; ++e) {
         const int i = rl + 16 * e;
+        vr[e] = (i >= s && i < r) ? v[i] : 0.0;
         x[e] = (act && i < r) ? col[i] : 0.0;
-        dot = fma(vr[e], x[e], dot);
+        dp[e & 3] = fma(vr[e], x[e], dp[e & 3]);
       }
-      const double wdot = beta * row16_sum(dot);
+      const double wdot = beta * row16_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
       if (act && !is_piv && beta != 0.0) {
 #pragma unroll
         for (int e = 0; e < CQ_RPL; ++e) {
@@ -288,13 +283,13 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
         }
         if (rl == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
       }
-      double s2 = 0.0;
+      double sp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int e = 0; e < CQ_RPL; ++e) {
         const int i = rl + 16 * e;
-        if (i > s && i < r) s2 = fma(x[e], x[e], s2);
+        if (i > s && i < r) sp[e & 3] = fma(x[e], x[e], sp[e & 3]);
       }
-      s2 = row16_sum(s2);
+      const double s2 = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
       if (act && !is_piv) {
         if (rl == 0) nrm[jj] = s2;
         if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }

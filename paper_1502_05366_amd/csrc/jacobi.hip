@@ -203,12 +203,16 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
 
 // The block kernel gives each column pair to one row of 16 lanes, so a wave
 // works on four pairs at once: lane (row g, position c) holds rows c + 16 e
-// (e = 0..15) of both columns of its pair.  Sums over a pair are DPP
+// (e = 0..15) of both W columns of its pair.  Sums over a pair are DPP
 // exchanges inside the row; the rotation is computed by every lane of the row
-// (rows whose pair is already orthogonal apply the identity).
+// (rows whose pair is already orthogonal apply the identity).  V is not
+// rotated column by column: the rotations of a round are accumulated in a
+// 2BS x 2BS orthogonal J (two rows per lane), and the round ends with
+// V(:, pair blocks) <- V(:, pair blocks) J on the matrix cores.
 constexpr int JB_NT = 256;   // 4 waves x 4 pairs = BS pairs per step
-constexpr int JLD = 256;     // LDS column length (rows >= l hold zeros)
+constexpr int JLD = 256;     // LDS column length of W (rows >= l hold zeros)
 constexpr int JRPL = JLD / 16;
+constexpr int JJ = 2 * BS;   // order of J
 
 __device__ __forceinline__ double row16_sum(double x) {
   x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
@@ -218,29 +222,32 @@ __device__ __forceinline__ double row16_sum(double x) {
   return x;
 }
 
-__device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xv)[JRPL],
-                                             double (&yw)[JRPL], double (&yv)[JRPL], double tol) {
-  double al = 0.0, be = 0.0, ga = 0.0;
+__device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xj)[2],
+                                             double (&yw)[JRPL], double (&yj)[2], double tol) {
+  double al[2] = {0.0, 0.0}, be[2] = {0.0, 0.0}, ga[2] = {0.0, 0.0};   // two chains each
 #pragma unroll
   for (int e = 0; e < JRPL; ++e) {
-    al = fma(xw[e], xw[e], al);
-    be = fma(yw[e], yw[e], be);
-    ga = fma(xw[e], yw[e], ga);
+    al[e & 1] = fma(xw[e], xw[e], al[e & 1]);
+    be[e & 1] = fma(yw[e], yw[e], be[e & 1]);
+    ga[e & 1] = fma(xw[e], yw[e], ga[e & 1]);
   }
-  al = row16_sum(al);
-  be = row16_sum(be);
-  ga = row16_sum(ga);
+  const double alpha = row16_sum(al[0] + al[1]);
+  const double beta = row16_sum(be[0] + be[1]);
+  const double gamma = row16_sum(ga[0] + ga[1]);
   double cs, sn;
-  const bool rot = jacobi_rotation(al, be, ga, tol, cs, sn);
+  const bool rot = jacobi_rotation(alpha, beta, gamma, tol, cs, sn);
   if (!rot) { cs = 1.0; sn = 0.0; }
 #pragma unroll
   for (int e = 0; e < JRPL; ++e) {
     const double a = xw[e], b = yw[e];
     xw[e] = cs * a - sn * b;
     yw[e] = sn * a + cs * b;
-    const double c = xv[e], d = yv[e];
-    xv[e] = cs * c - sn * d;
-    yv[e] = sn * c + cs * d;
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double c = xj[e], d = yj[e];
+    xj[e] = cs * c - sn * d;
+    yj[e] = sn * c + cs * d;
   }
   return rot;
 }
@@ -253,6 +260,14 @@ __device__ __forceinline__ void lds_col_store(double* base, int rl, const double
 #pragma unroll
   for (int e = 0; e < JRPL; ++e) base[rl + 16 * e] = v[e];
 }
+__device__ __forceinline__ void lds_j_load(const double* Jl, int col, int rl, double (&v)[2]) {
+  v[0] = Jl[col * JJ + rl];
+  v[1] = Jl[col * JJ + rl + 16];
+}
+__device__ __forceinline__ void lds_j_store(double* Jl, int col, int rl, const double (&v)[2]) {
+  Jl[col * JJ + rl] = v[0];
+  Jl[col * JJ + rl + 16] = v[1];
+}
 
 __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   extern __shared__ double smem[];
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   const int w = blockIdx.x;
   const int l = a.l;
   double* Wl = smem;                        // [2*BS][JLD]
-  double* Vl = smem + 2 * BS * JLD;
+  double* Jl = smem + 2 * BS * JLD;         // [JJ][JJ], column-major
   uint32_t done = 0;
   int sweep = 0;
   bool converged = false;
@@ -271,27 +286,30 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   while (!converged && sweep < a.max_sweeps) {
     for (int r = 0; r < a.nbp - 1; ++r) {
       const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
-      // load the two blocks (columns >= l and rows >= l read as zero), W then
-      // V, each thread issuing all its loads of a matrix before its LDS writes
-      constexpr int PER = 2 * BS * JLD / JB_NT;
-#pragma unroll
-      for (int mtx = 0; mtx < 2; ++mtx) {
-        const double* src = mtx ? a.V : a.W;
-        double* dst = mtx ? Vl : Wl;
+      auto gcol_of = [&](int c) { return (c < BS) ? bi * BS + c : bj * BS + (c - BS); };
+      // load the two W blocks (columns >= l and rows >= l read as zero), each
+      // thread issuing all its loads before its LDS writes; J = I
+      {
+        constexpr int PER = 2 * BS * JLD / JB_NT;
         double vv[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JB_NT;
           const int c = idx / JLD, i = idx % JLD;
-          const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-          vv[e] = (i < l && gcol < l) ? ld_agent(src + (int64_t)gcol * a.ld + i) : 0.0;
+          const int gcol = gcol_of(c);
+          vv[e] = (i < l && gcol < l) ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < PER; ++e) dst[tid + e * JB_NT] = vv[e];
+        for (int e = 0; e < PER; ++e) Wl[tid + e * JB_NT] = vv[e];
+#pragma unroll
+        for (int e = 0; e < JJ * JJ / JB_NT; ++e) {
+          const int idx = tid + e * JB_NT;
+          Jl[idx] = (idx / JJ == idx % JJ) ? 1.0 : 0.0;
+        }
       }
       __syncthreads();
       bool rot = false;
-      double xw[JRPL], xv[JRPL], yw[JRPL], yv[JRPL];
+      double xw[JRPL], yw[JRPL], xj[2], yj[2];
       if (r == 0) {
         // pairs inside each block: BS-1 round-robin rounds, both blocks at once
         for (int t = 0; t < BS - 1; ++t) {
@@ -299,11 +317,11 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
           int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
           if (p > q) { const int x = p; p = q; q = x; }
           p += half * BS; q += half * BS;
-          lds_col_load(Wl + p * JLD, rl, xw); lds_col_load(Vl + p * JLD, rl, xv);
-          lds_col_load(Wl + q * JLD, rl, yw); lds_col_load(Vl + q * JLD, rl, yv);
-          rot |= rotate_row16(xw, xv, yw, yv, a.tol);
-          lds_col_store(Wl + p * JLD, rl, xw); lds_col_store(Vl + p * JLD, rl, xv);
-          lds_col_store(Wl + q * JLD, rl, yw); lds_col_store(Vl + q * JLD, rl, yv);
+          lds_col_load(Wl + p * JLD, rl, xw); lds_j_load(Jl, p, rl, xj);
+          lds_col_load(Wl + q * JLD, rl, yw); lds_j_load(Jl, q, rl, yj);
+          rot |= rotate_row16(xw, xj, yw, yj, a.tol);
+          lds_col_store(Wl + p * JLD, rl, xw); lds_j_store(Jl, p, rl, xj);
+          lds_col_store(Wl + q * JLD, rl, yw); lds_j_store(Jl, q, rl, yj);
           __syncthreads();
         }
       }
@@ -311,27 +329,61 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
       // x_p in registers, the y columns move between slots through LDS
       {
         const int p = ps;
-        lds_col_load(Wl + p * JLD, rl, xw); lds_col_load(Vl + p * JLD, rl, xv);
+        lds_col_load(Wl + p * JLD, rl, xw); lds_j_load(Jl, p, rl, xj);
         for (int t = 0; t < BS; ++t) {
           const int q = BS + (p + t) % BS;
-          lds_col_load(Wl + q * JLD, rl, yw); lds_col_load(Vl + q * JLD, rl, yv);
-          rot |= rotate_row16(xw, xv, yw, yv, a.tol);
-          lds_col_store(Wl + q * JLD, rl, yw); lds_col_store(Vl + q * JLD, rl, yv);
+          lds_col_load(Wl + q * JLD, rl, yw); lds_j_load(Jl, q, rl, yj);
+          rot |= rotate_row16(xw, xj, yw, yj, a.tol);
+          lds_col_store(Wl + q * JLD, rl, yw); lds_j_store(Jl, q, rl, yj);
           __syncthreads();
         }
-        lds_col_store(Wl + p * JLD, rl, xw); lds_col_store(Vl + p * JLD, rl, xv);
+        lds_col_store(Wl + p * JLD, rl, xw); lds_j_store(Jl, p, rl, xj);
       }
       if (rot) rotated = 1;
       __syncthreads();
+      // W back to memory
       {
+        constexpr int PER = 2 * BS * JLD / JB_NT;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JB_NT;
           const int c = idx / JLD, i = idx % JLD;
-          const int gcol = (c < BS) ? bi * BS + c : bj * BS + (c - BS);
-          if (i < l && gcol < l) {
-            st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[idx]);
-            st_agent(a.V + (int64_t)gcol * a.ld + i, Vl[idx]);
+          const int gcol = gcol_of(c);
+          if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[idx]);
+        }
+      }
+      // V(:, pair) <- V(:, pair) J: wave v takes row tiles v, v+4, v+8, v+12
+      // (16 rows each) and both 16-column halves; it reads all of its rows
+      // before it writes any, and no other wave touches them
+      {
+        const int li = lane & 15, lk = lane >> 4;
+        double av[4][JJ / 4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = (wave + 4 * q) * 16 + li;
+#pragma unroll
+          for (int kk = 0; kk < JJ / 4; ++kk) {
+            const int gcol = gcol_of(kk * 4 + lk);
+            av[q][kk] = (row < l && gcol < l) ? ld_agent(a.V + (int64_t)gcol * a.ld + row) : 0.0;
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < JJ / 16; ++ct) {
+          double bv[JJ / 4];
+#pragma unroll
+          for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJ + kk * 4 + lk];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < JJ / 4; ++kk)
+              acc = Mfma<double>::mma(av[q][kk], bv[kk], acc);
+            const int gcol = gcol_of(ct * 16 + li);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = (wave + 4 * q) * 16 + drow(lk, v);
+              if (row < l && gcol < l) st_agent(a.V + (int64_t)gcol * a.ld + row, acc[v]);
+            }
           }
         }
       }
@@ -419,7 +471,7 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                      s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64 * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t shm = 4 * (size_t)BS * JLD * sizeof(double);
+  const size_t shm = (2 * (size_t)BS * JLD + (size_t)JJ * JJ) * sizeof(double);
   e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
