@@ -400,7 +400,7 @@ size_t cpqr_work_bytes(const CpqrPlan& p) {
 
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
                        const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
-                       int64_t lds, double* pivn, int32_t* info, hipStream_t s) {
+                       int64_t lds, double* pivn, int32_t* info, bool coop, hipStream_t s) {
   if (!p.ok) return hipErrorInvalidValue;
   CpqrArgs a;
   a.Bt = Bt; a.ldb = ldb; a.r = r; a.c = c; a.k = k;
@@ -417,7 +417,11 @@ hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c
   const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
   if (e != hipSuccess) return e;
-  e = hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
+  if (coop) {
+    e = hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
+  } else {
+    e = hipLaunchKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
+  }
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

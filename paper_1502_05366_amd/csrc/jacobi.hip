@@ -445,7 +445,7 @@ size_t jacobi_work_bytes(int l) {
 
 hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
                          double* Uh, int64_t lduh, double* Vh, int64_t ldvh, int max_sweeps,
-                         int32_t* info, int32_t* sweeps_out, hipStream_t s) {
+                         int32_t* info, int32_t* sweeps_out, bool coop, hipStream_t s) {
   if (l > 256) return hipErrorInvalidValue;
   const double tol = (double)l * 2.220446049250313e-16;
   if (l <= LDS_MAX_L) {
@@ -476,8 +476,12 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args, shm,
-                                 s);
+  if (coop) {
+    e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args,
+                                   shm, s);
+  } else {
+    e = hipLaunchKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args, shm, s);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, (int64_t)l, l, k, S, Uh,
                      lduh, Vh, ldvh);

@@ -25,6 +25,10 @@
 struct rsvd_handle_s {
   int device;
   int ncu;
+  // second stream and fork / join events: the SVD post-processing runs
+  // beside the ID / CUR post-processing inside rsvd_decompose
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
 };
 
 namespace rsvd {
@@ -85,7 +89,8 @@ struct Bufs {
   void* cq_work;
   int64_t* J;
   double *S11t, *S12t, *pivn, *T;
-  // CUR
+  // CUR (its orth and small products run beside the SVD branch: own buffers)
+  OrthBufs ob2;
   double* Crow;
   void* cq2_work;
   int64_t* J2;
@@ -107,6 +112,22 @@ size_t max_part(const Shape& s) {
   return b;
 }
 
+OrthBufs take_orth(Arena& a, int64_t rows, int lp, size_t part_bytes) {
+  OrthBufs ob;
+  ob.G = a.take<double>((size_t)lp * lp);
+  ob.R1 = a.take<double>((size_t)lp * lp);
+  ob.R2 = a.take<double>((size_t)lp * lp);
+  ob.Rd1 = a.take<double>((size_t)lp * 16);
+  ob.Rd2 = a.take<double>((size_t)lp * 16);
+  ob.Qa = a.take<double>((size_t)rows * lp);
+  ob.dep = a.take<int32_t>(lp);
+  ob.dep2 = a.take<int32_t>(lp);
+  ob.part_bytes = part_bytes;
+  ob.part = a.take<char>(part_bytes);
+  ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
+  return ob;
+}
+
 size_t layout(const Shape& s, void* base, Bufs* out) {
   Arena a(base);
   Bufs b;
@@ -117,17 +138,7 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
   b.Q = a.take<char>((size_t)s.m * s.lp * s.dsz);
   b.Z = a.take<char>((size_t)s.n * s.lp * s.dsz);
   b.Zq = a.take<char>((size_t)s.n * s.lp * s.dsz);
-  b.ob.G = a.take<double>((size_t)s.lp * s.lp);
-  b.ob.R1 = a.take<double>((size_t)s.lp * s.lp);
-  b.ob.R2 = a.take<double>((size_t)s.lp * s.lp);
-  b.ob.Rd1 = a.take<double>((size_t)s.lp * 16);
-  b.ob.Rd2 = a.take<double>((size_t)s.lp * 16);
-  b.ob.Qa = a.take<double>((size_t)rmax * s.lp);
-  b.ob.dep = a.take<int32_t>(s.lp);
-  b.ob.dep2 = a.take<int32_t>(s.lp);
-  b.ob.part_bytes = max_part(s);
-  b.ob.part = a.take<char>(b.ob.part_bytes);
-  b.ob.gpart = a.take<double>(gram_part_bytes(s.lp, NCU_CAP) / sizeof(double));
+  b.ob = take_orth(a, rmax, s.lp, max_part(s));
   if (s.ops & RSVD_OP_SVD) {
     b.Qh = a.take<double>((size_t)s.n * s.lp);
     b.Rh = a.take<double>((size_t)s.lp * s.lp);
@@ -157,6 +168,8 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
     b.Rtt = a.take<double>((size_t)s.lp * s.lp);
     b.Qres = a.take<double>((size_t)(s.n - s.k + 1) * s.kp);
     b.Mb = a.take<double>((size_t)s.kp * s.kp);
+    const int64_t nk = std::max<int64_t>(s.n - s.k, 1);
+    b.ob2 = take_orth(a, s.n, s.kp, gemm_part_bytes(plan_gemm(s.k, nk, s.k, NCU_CAP, 0), 8));
   }
   if (out) *out = b;
   return a.off;
@@ -168,7 +181,12 @@ struct Ctx {
   int32_t* info;
   uint64_t seed;
   uint32_t orth_calls;
+  rsvd_handle_s* h;
 };
+
+// CUs kept free for the block Jacobi (at most 8 workgroups) while the
+// pivoted QR runs beside it
+constexpr int JACOBI_CU_RESERVE = 8;
 
 #define RSVD_TRY(x)                         \
   do {                                      \
@@ -233,41 +251,54 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
   RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
   RSVD_TRY(pass(c, f32, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes));   // B^T
   const int ncu = std::min(c.ncu, NCU_CAP);
+  // With both the SVD and the ID / CUR requested, the SVD's Jacobi (a few
+  // workgroups) and its two products run on the handle's second stream while
+  // the pivoted QRs run here on all but JACOBI_CU_RESERVE CUs; the cross-
+  // workgroup waits of the two kernels then never compete for CUs.
+  const bool fork = o.U && (o.J || o.Jr) && ncu >= 4 * JACOBI_CU_RESERVE;
   if (o.U) {
     // [Qh, Rh] = qr(B^T); Rh = Uh S Vh^T; U = Q Vh_k; V = Qh Uh_k
     RSVD_TRY(orth(c, b.ob, f32, b.Z, lp, n, l, b.Qh, false, lp, b.Rh, lp));
+    hipStream_t s1 = c.st;
+    if (fork) {
+      RSVD_TRY(hipEventRecord(c.h->ev_fork, c.st));
+      RSVD_TRY(hipStreamWaitEvent(c.h->aux, c.h->ev_fork, 0));
+      s1 = c.h->aux;
+    }
     RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, o.S, b.Uh, s.kp, b.Vh, s.kp, JACOBI_MAX_SWEEPS,
-                           c.info, nullptr, c.st));
+                           c.info, nullptr, !fork, s1));
     const GemmPlan pu = plan_gemm(m, l, k, ncu, 0);
     RSVD_TRY(launch_gemm(f32 ? GEMM_FDDF : GEMM_DDDD, false, b.Q, lp, b.Vh, s.kp, o.U, o.ldu, m, l,
-                         k, pu, b.ob.part, b.ob.part_bytes, c.st));
+                         k, pu, b.ob.part, b.ob.part_bytes, s1));
     const GemmPlan pv = plan_gemm(n, l, k, ncu, 0);
     RSVD_TRY(launch_gemm(f32 ? GEMM_DDDF : GEMM_DDDD, false, b.Qh, lp, b.Uh, s.kp, o.V, o.ldv, n,
-                         l, k, pv, b.ob.part, b.ob.part_bytes, c.st));
+                         l, k, pv, b.ob.part, b.ob.part_bytes, s1));
+    if (fork) RSVD_TRY(hipEventRecord(c.h->ev_join, s1));
   }
   if (o.J || o.Jr) {
+    const int ncq = fork ? ncu - JACOBI_CU_RESERVE : ncu;
     int64_t* J = o.J ? o.J : b.J;
     double* T = o.T ? o.T : b.T;
     const int64_t ldt = o.T ? o.ldt : (n - k);
-    const CpqrPlan cp = plan_cpqr(l, n, k, ncu);
+    const CpqrPlan cp = plan_cpqr(l, n, k, ncq);
     RSVD_TRY(launch_cpqr(f32, b.Z, lp, l, n, k, cp, b.cq_work, J, b.S11t, b.S12t, s.kp, b.pivn,
-                         c.info, c.st));
+                         c.info, !fork, c.st));
     RSVD_TRY(launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st));
     if (o.Jr) {
       // row selection on C^T = A(:, J_k)^T
       RSVD_TRY(launch_gather_cols(f32, A, lda, m, n, J, k, b.Crow, s.kp, c.st));
-      const CpqrPlan cp2 = plan_cpqr(k, m, k, ncu);
+      const CpqrPlan cp2 = plan_cpqr(k, m, k, ncq);
       RSVD_TRY(launch_cpqr(false, b.Crow, s.kp, k, m, k, cp2, b.cq2_work, b.J2, b.S11t2, b.S12t2,
-                           s.kp, b.pivn2, c.info, c.st));
+                           s.kp, b.pivn2, c.info, !fork, c.st));
       // R^T = A(Jr, :)^T = Qt Rt
       RSVD_TRY(launch_gather_rows_t(f32, A, lda, m, n, b.J2, k, b.Rt, s.kp, c.st));
-      RSVD_TRY(orth(c, b.ob, false, b.Rt, s.kp, n, k, b.Qt, false, s.kp, b.Rtt, s.kp));
+      RSVD_TRY(orth(c, b.ob2, false, b.Rt, s.kp, n, k, b.Qt, false, s.kp, b.Rtt, s.kp));
       // M = T Qt(J_res, :) + Qt(J_k, :)
       RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J + k, n - k, k, b.Qres, s.kp, false, c.st));
       if (n > k) {
         const GemmPlan pm = plan_gemm(k, n - k, k, ncu, 0);
         RSVD_TRY(launch_gemm(GEMM_DDDD, false, T, ldt, b.Qres, s.kp, b.Mb, s.kp, k, n - k, k, pm,
-                             b.ob.part, b.ob.part_bytes, c.st));
+                             b.ob2.part, b.ob2.part_bytes, c.st));
         RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J, k, k, b.Mb, s.kp, true, c.st));
       } else {
         RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J, k, k, b.Mb, s.kp, false, c.st));
@@ -279,6 +310,7 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
         RSVD_TRY(hipMemcpyAsync(o.Jc, J, sizeof(int64_t) * k, hipMemcpyDeviceToDevice, c.st));
     }
   }
+  if (fork) RSVD_TRY(hipStreamWaitEvent(c.st, c.h->ev_join, 0));
   return hipSuccess;
 }
 
@@ -309,14 +341,31 @@ int rsvd_create(rsvd_handle_t* handle, int device) {
     return RSVD_ERR_NO_DEVICE;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RSVD_ERR_HIP;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess)
+    return RSVD_ERR_HIP;
   rsvd_handle_s* h = new rsvd_handle_s;
   h->device = device;
   h->ncu = prop.multiProcessorCount;
+  h->aux = nullptr;
+  h->ev_fork = h->ev_join = nullptr;
+  const bool ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
+  (void)hipSetDevice(prev);
+  if (!ok) {
+    rsvd_destroy(h);
+    return RSVD_ERR_HIP;
+  }
   *handle = h;
   return RSVD_OK;
 }
 
 int rsvd_destroy(rsvd_handle_t handle) {
+  if (!handle) return RSVD_OK;
+  if (handle->ev_join) (void)hipEventDestroy(handle->ev_join);
+  if (handle->ev_fork) (void)hipEventDestroy(handle->ev_fork);
+  if (handle->aux) (void)hipStreamDestroy(handle->aux);
   delete handle;
   return RSVD_OK;
 }
@@ -384,7 +433,7 @@ int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int 
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
-  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   Outs o;
   std::memset(&o, 0, sizeof(o));
   o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
@@ -414,7 +463,7 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
-  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   Outs o;
   std::memset(&o, 0, sizeof(o));
   o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
@@ -439,7 +488,7 @@ int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int 
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
-  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   Outs o;
   std::memset(&o, 0, sizeof(o));
   o.J = J; o.T = T; o.ldt = ldt;
@@ -467,7 +516,7 @@ int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
-  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0};
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   Outs o;
   std::memset(&o, 0, sizeof(o));
   o.Jc = Jc; o.Jr = Jr; o.Ucur = Ucur; o.lduc = lduc;
@@ -523,7 +572,7 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
   if (work_bytes < rsvd_pass_workspace_bytes(dtype, trans, m, n, l)) return RSVD_ERR_WORKSPACE;
   if (work_bytes > 256 && !work) return -13;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
-  Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0};
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0, h};
   return finish(pass(c, dtype == RSVD_F32, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy,
                      work, work ? work_bytes : 0));
 }
@@ -573,7 +622,7 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   ob.part_bytes = 0;
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Ctx c{st, h->ncu, info, seed, 0};
+  Ctx c{st, h->ncu, info, seed, 0, h};
   hipError_t e = launch_set_word(info, 0, st);
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   const bool f32 = dtype == RSVD_F32;
@@ -614,7 +663,7 @@ int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t 
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   if (e == hipSuccess)
     e = launch_jacobi(Rh, ldr, (int)l, k, jw, S, Uh, lduh, Vh, ldvh, JACOBI_MAX_SWEEPS, info,
-                      nullptr, st);
+                      nullptr, true, st);
   return finish(e);
 }
 
@@ -663,7 +712,7 @@ int rsvd_cpqr(rsvd_handle_t h, int dtype, int64_t r, int64_t c, int k, const voi
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   if (e == hipSuccess)
     e = launch_cpqr(dtype == RSVD_F32, Bcols, ldb, (int)r, c, k, pr, cw, J, S11t, S12t, kp, pv,
-                    info, st);
+                    info, true, st);
   if (e == hipSuccess && c > k)
     e = launch_backsub(S11t, 1, kp, S12t, 1, kp, k, c - k, T, ldt, 1, st);
   if (e == hipSuccess && pivn)
