@@ -66,10 +66,7 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
                                                      int l, int lp, double eta,
                                                      double* __restrict__ R, int64_t ldr,
                                                      double* __restrict__ Rdinv,
-                                                     int32_t* __restrict__ dep, int32_t* info,
-                                                     int32_t* __restrict__ anomaly,
-                                                     const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                                     int32_t* __restrict__ dep, int32_t* info) {
   const int nb = lp / 16;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -170,8 +167,6 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
           if (gcol < l) {
             dep[gcol] = ok ? 0 : 1;
             if (!ok) info_or(info, finite ? INFO_ORTH_FALLBACK : INFO_NONFINITE);
-            if (anomaly && (!ok || d < 0.25 * diag0[gcol] || d > 4.0 * diag0[gcol]))
-              atomicOr(anomaly, 1);
           }
         }
       }
@@ -238,9 +233,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
                                                    int64_t M, int l, int lp,
                                                    const double* __restrict__ R, int64_t ldr,
                                                    const double* __restrict__ Rdinv,
-                                                   TQ* __restrict__ Q, int64_t ldq,
-                                                   const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                                   TQ* __restrict__ Q, int64_t ldq) {
   __shared__ double Qs[4][16 * 257];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -488,14 +481,13 @@ hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int
 }
 
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
-                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
-                       const int32_t* gate, hipStream_t s) {
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s) {
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
   const int nb = lp / 16;
   const int tpw = (int)cdiv(nb * (nb + 1) / 2, CH_NW);
 #define RSVD_CHOL(T)                                                                          \
   hipLaunchKernelGGL(chol_kernel<T>, dim3(1), dim3(CH_NT), 0, s, G, ldg, l, lp, eta, R, ldr, \
-                     Rdinv, dep, info, anomaly, gate)
+                     Rdinv, dep, info)
   if (tpw <= 1) RSVD_CHOL(1);
   else if (tpw <= 2) RSVD_CHOL(2);
   else if (tpw <= 4) RSVD_CHOL(4);
@@ -509,21 +501,21 @@ hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, 
 
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
-                       int64_t ldq, const int32_t* gate, hipStream_t s) {
+                       int64_t ldq, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   const dim3 grid((unsigned)cdiv(M, 64));
   if (!y_f32 && !q_f32)
     hipLaunchKernelGGL((trsm_kernel<double, double>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, gate);
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
   else if (y_f32 && q_f32)
     hipLaunchKernelGGL((trsm_kernel<float, float>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, gate);
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
   else if (y_f32 && !q_f32)
     hipLaunchKernelGGL((trsm_kernel<float, double>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, gate);
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
   else
     hipLaunchKernelGGL((trsm_kernel<double, float>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, gate);
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
   return hipGetLastError();
 }
 

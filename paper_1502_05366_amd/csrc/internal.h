@@ -42,12 +42,9 @@ namespace rsvd {
 // One Cholesky factorization of an lp x lp Gram matrix (lp <= 256, lp % 16 == 0,
 // only rows/columns < l are read).  R upper triangular (zero below), Rdinv the
 // inverses of its 16x16 diagonal blocks (lp/16 blocks of 256 doubles), dep[j]
-// = 1 for columns declared dependent (pivot <= eta * G_jj).  `anomaly` (may be
-// null) is set when a pivot leaves [0.25, 4] * G_jj.  Kernels return at once
-// when `gate` is non-null and *gate == 0.
+// = 1 for columns declared dependent (pivot <= eta * G_jj).
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
-                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, int32_t* anomaly,
-                       const int32_t* gate, hipStream_t s);
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s);
 // G = Y^T Y (upper 16x16 tiles of an lp x lp matrix) in FP64 for a tall Y;
 // `part` holds gram_part_bytes(lp, G) bytes, G = gram_groups(rows, ncu).
 int gram_groups(int64_t rows, int ncu);
@@ -57,7 +54,7 @@ hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int
 // Q = Y R^{-1} (M x l); Y and Q may be FP32 or FP64; arithmetic in FP64.
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
-                       int64_t ldq, const int32_t* gate, hipStream_t s);
+                       int64_t ldq, hipStream_t s);
 // overwrite the columns j with dep[j] != 0 of Q (M rows) by N(0, 1/M) values
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
                           uint64_t seed, uint32_t call, hipStream_t s);

@@ -202,17 +202,13 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
   const int gG = gram_groups(rows, std::min(c.ncu, NCU_CAP));
   // pass 1: G = Y^T Y, G = R1^T R1, Qa = Y R1^{-1}, dependent columns replaced
   RSVD_TRY(launch_gram(y_f32, Y, ldy, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
-  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, nullptr,
-                       nullptr, c.st));
-  RSVD_TRY(launch_trsm(y_f32, false, Y, ldy, rows, l, lp, ob.R1, lp, ob.Rd1, ob.Qa, lp, nullptr,
-                       c.st));
+  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, c.st));
+  RSVD_TRY(launch_trsm(y_f32, false, Y, ldy, rows, l, lp, ob.R1, lp, ob.Rd1, ob.Qa, lp, c.st));
   RSVD_TRY(launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st));
   // pass 2 on Qa
   RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
-  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, nullptr,
-                       nullptr, c.st));
-  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, nullptr,
-                       c.st));
+  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st));
+  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st));
   if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, Rout, ldr, lp, c.st));
   return hipSuccess;
 }
