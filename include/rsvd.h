@@ -8,12 +8,20 @@
  * ---------------------------------------
  * - All matrix pointers are DEVICE pointers; the caller allocates every
  *   input, output and workspace buffer.  The library allocates nothing per
- *   call; the handle holds only immutable per-device facts.
+ *   call.  The handle holds per-device facts and a second stream with two
+ *   events, on which rsvd_decompose runs the SVD post-processing beside the
+ *   ID / CUR post-processing (forked from and joined back into `stream`); a
+ *   handle must not be used by two host threads at once.
  * - Matrices are row-major: element (i, j) of an r x c matrix X with leading
  *   dimension ldx (>= c) is X[i * ldx + j].  Index outputs are 0-based int64.
  * - `dtype` selects the storage and pass precision of A (and of the
- *   range-finder matrices): RSVD_F64 or RSVD_F32.  Gram matrices, Cholesky
- *   factors, the small SVD and the pivoted QR always run in FP64.
+ *   range-finder matrices): RSVD_F64, RSVD_F32, or RSVD_BF16 (mixed
+ *   precision: A holds BF16 bit patterns (uint16), lda % 8 == 0 and A
+ *   16-byte aligned; the passes run on the BF16 matrix cores with FP32
+ *   accumulation, the range-finder matrices and U, V are FP32, and the last
+ *   projection B^T = A^T Q applies Q as the sum of two BF16 terms).  Gram
+ *   matrices, Cholesky factors, the small SVD and the pivoted QR always run
+ *   in FP64.  The step entry points other than rsvd_pass take F64 / F32.
  * - All work is enqueued on `stream` (a hipStream_t, may be NULL for the null
  *   stream); nothing synchronizes with the host.  Buffers must stay valid
  *   until the stream has passed the call.
@@ -38,7 +46,7 @@
 extern "C" {
 #endif
 
-typedef enum { RSVD_F64 = 0, RSVD_F32 = 1 } rsvd_dtype_t;
+typedef enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2 } rsvd_dtype_t;
 
 enum {
   RSVD_OK = 0,
@@ -132,7 +140,10 @@ int rsvd_philox(rsvd_handle_t h, uint64_t seed, uint32_t stream_id, uint32_t bat
                 uint64_t first, int64_t count, uint32_t* out, void* stream);
 
 /* One pass over A on the matrix cores: Y = A X (trans = 0; X n x l, Y m x l)
- * or Y = A^T X (trans = 1; X m x l, Y n x l).  A, X, Y of type dtype. */
+ * or Y = A^T X (trans = 1; X m x l, Y n x l).  A, X, Y of type dtype; with
+ * RSVD_BF16, A is BF16 (lda % 8 == 0, 16-byte aligned, else argument 8 is
+ * reported), X and Y are FP32, X is rounded to BF16 in the workspace and
+ * l <= 256. */
 size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int64_t l);
 int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64_t l,
               const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy,

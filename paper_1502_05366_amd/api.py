@@ -15,6 +15,7 @@ from . import _lib
 
 F64 = 0
 F32 = 1
+BF16 = 2
 
 INFO_ORTH_FALLBACK = 1
 INFO_JACOBI_CAP = 2
@@ -64,7 +65,14 @@ def _dtype_code(t):
         return F64
     if t.dtype == torch.float32:
         return F32
-    raise RsvdError("A must be float64 or float32, got %s" % t.dtype)
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise RsvdError("A must be float64, float32 or bfloat16, got %s" % t.dtype)
+
+
+def _out_dtype(A):
+    """Element type of U, V (and of the range-finder matrices) for a given A."""
+    return torch.float32 if A.dtype == torch.bfloat16 else A.dtype
 
 
 def _stream(device):
@@ -80,6 +88,12 @@ def _row_major(A):
         raise RsvdError("expected a matrix")
     if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
         A = A.contiguous()
+    if A.dtype == torch.bfloat16 and (A.stride(0) % 8 or A.data_ptr() % 16):
+        # the BF16 passes read rows in 16-byte pieces: pad rows to 8 elements
+        m, n = A.shape
+        P = torch.zeros((m, (n + 7) // 8 * 8), dtype=A.dtype, device=A.device)
+        P[:, :n] = A
+        A = P[:, :n]
     return A
 
 
@@ -107,9 +121,9 @@ def decompose(A, k, p, q, seed, svd=True, id=True, cur=True):
     out = {}
     U = S = V = J = T = Jr = Uc = None
     if svd:
-        U = torch.empty((m, k), dtype=A.dtype, device=dev)
+        U = torch.empty((m, k), dtype=_out_dtype(A), device=dev)
         S = torch.empty(k, dtype=torch.float64, device=dev)
-        V = torch.empty((n, k), dtype=A.dtype, device=dev)
+        V = torch.empty((n, k), dtype=_out_dtype(A), device=dev)
     if id or cur:
         J = torch.empty(n, dtype=torch.int64, device=dev)
         T = torch.empty((k, max(n - k, 1)), dtype=torch.float64, device=dev)
@@ -143,9 +157,9 @@ def svd(A, k, p, q, seed):
     wb = workspace_bytes(OP_SVD, dt, m, n, k, p, q)
     work = _workspace(wb, dev)
     info = torch.zeros(2, dtype=torch.int32, device=dev)
-    U = torch.empty((m, k), dtype=A.dtype, device=dev)
+    U = torch.empty((m, k), dtype=_out_dtype(A), device=dev)
     S = torch.empty(k, dtype=torch.float64, device=dev)
-    V = torch.empty((n, k), dtype=A.dtype, device=dev)
+    V = torch.empty((n, k), dtype=_out_dtype(A), device=dev)
     rc = lib.rsvd_svd(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(U), k,
                       _ptr(S), _ptr(V), k, _ptr(work), work.numel(), _ptr(info), _stream(dev))
     _check(rc, "rsvd_svd")
@@ -219,7 +233,7 @@ def pass_(A, X, trans=False):
     l = X.shape[1]
     dt = _dtype_code(A)
     rows = n if trans else m
-    Y = torch.empty((rows, l), dtype=A.dtype, device=A.device)
+    Y = torch.empty((rows, l), dtype=_out_dtype(A), device=A.device)
     wb = lib.rsvd_pass_workspace_bytes(dt, int(trans), m, n, l)
     work = _workspace(wb, A.device)
     rc = lib.rsvd_pass(handle(A.device), dt, int(trans), m, n, l, _ptr(A), A.stride(0), _ptr(X),

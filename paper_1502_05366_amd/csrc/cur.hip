@@ -10,6 +10,14 @@
 namespace rsvd {
 namespace {
 
+// element of A as FP64; BF16 elements are stored as their 16-bit patterns
+struct Bf16Bits { uint16_t v; };
+__device__ __forceinline__ double as_double(double x) { return x; }
+__device__ __forceinline__ double as_double(float x) { return (double)x; }
+__device__ __forceinline__ double as_double(Bf16Bits x) {
+  return (double)__uint_as_float((uint32_t)x.v << 16);
+}
+
 // Crow[i * ldc + t] = A[i, J[t]]  (i < m, t < k)
 template <typename TA>
 __global__ __launch_bounds__(256) void gather_cols_kernel(const TA* __restrict__ A, int64_t lda,
@@ -22,7 +30,7 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const TA* __restrict__
     const int64_t i = e / k;
     const int t = (int)(e - i * k);
     const int64_t j = J[t];
-    Crow[i * ldc + t] = (j >= 0 && j < n) ? (double)A[i * lda + j] : 0.0;
+    Crow[i * ldc + t] = (j >= 0 && j < n) ? as_double(A[i * lda + j]) : 0.0;
   }
 }
 
@@ -38,7 +46,7 @@ __global__ __launch_bounds__(256) void gather_rows_t_kernel(const TA* __restrict
     const int t = (int)(e / n);
     const int64_t j = e - (int64_t)t * n;
     const int64_t r = Jr[t];
-    Rt[j * ldr + t] = (r >= 0 && r < m) ? (double)A[r * lda + j] : 0.0;
+    Rt[j * ldr + t] = (r >= 0 && r < m) ? as_double(A[r * lda + j]) : 0.0;
   }
 }
 
@@ -81,27 +89,35 @@ int grid_of(int64_t total) {
 
 }  // namespace
 
-hipError_t launch_gather_cols(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+hipError_t launch_gather_cols(int atype, const void* A, int64_t lda, int64_t m, int64_t n,
                               const int64_t* J, int k, double* Crow, int64_t ldc, hipStream_t s) {
   if (m <= 0 || k <= 0) return hipSuccess;
-  if (a_f32)
-    hipLaunchKernelGGL(gather_cols_kernel<float>, dim3(grid_of(m * k)), dim3(256), 0, s,
-                       (const float*)A, lda, m, n, J, k, Crow, ldc);
+  const dim3 grid(grid_of(m * k));
+  if (atype == 1)
+    hipLaunchKernelGGL(gather_cols_kernel<float>, grid, dim3(256), 0, s, (const float*)A, lda, m,
+                       n, J, k, Crow, ldc);
+  else if (atype == 2)
+    hipLaunchKernelGGL(gather_cols_kernel<Bf16Bits>, grid, dim3(256), 0, s, (const Bf16Bits*)A,
+                       lda, m, n, J, k, Crow, ldc);
   else
-    hipLaunchKernelGGL(gather_cols_kernel<double>, dim3(grid_of(m * k)), dim3(256), 0, s,
-                       (const double*)A, lda, m, n, J, k, Crow, ldc);
+    hipLaunchKernelGGL(gather_cols_kernel<double>, grid, dim3(256), 0, s, (const double*)A, lda,
+                       m, n, J, k, Crow, ldc);
   return hipGetLastError();
 }
 
-hipError_t launch_gather_rows_t(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+hipError_t launch_gather_rows_t(int atype, const void* A, int64_t lda, int64_t m, int64_t n,
                                 const int64_t* Jr, int k, double* Rt, int64_t ldr, hipStream_t s) {
   if (n <= 0 || k <= 0) return hipSuccess;
-  if (a_f32)
-    hipLaunchKernelGGL(gather_rows_t_kernel<float>, dim3(grid_of(n * k)), dim3(256), 0, s,
-                       (const float*)A, lda, m, n, Jr, k, Rt, ldr);
+  const dim3 grid(grid_of(n * k));
+  if (atype == 1)
+    hipLaunchKernelGGL(gather_rows_t_kernel<float>, grid, dim3(256), 0, s, (const float*)A, lda,
+                       m, n, Jr, k, Rt, ldr);
+  else if (atype == 2)
+    hipLaunchKernelGGL(gather_rows_t_kernel<Bf16Bits>, grid, dim3(256), 0, s,
+                       (const Bf16Bits*)A, lda, m, n, Jr, k, Rt, ldr);
   else
-    hipLaunchKernelGGL(gather_rows_t_kernel<double>, dim3(grid_of(n * k)), dim3(256), 0, s,
-                       (const double*)A, lda, m, n, Jr, k, Rt, ldr);
+    hipLaunchKernelGGL(gather_rows_t_kernel<double>, grid, dim3(256), 0, s, (const double*)A,
+                       lda, m, n, Jr, k, Rt, ldr);
   return hipGetLastError();
 }
 

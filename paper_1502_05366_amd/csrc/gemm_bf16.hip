@@ -1,0 +1,411 @@
+// Passes over a BF16 A on the matrix cores (mixed-precision range finder):
+// C[M x L] (FP32) = op(A) Xb with A and Xb in BF16 and FP32 accumulation,
+// v_mfma_f32_16x16x32_bf16.  The skinny operand arrives in FP32 or FP64 and is
+// rounded to BF16 (to nearest even) and transposed (Xt = X^T, L x K, k
+// contiguous) by convert_bf16_kernel before the pass; everything after the
+// pass (CholeskyQR, Jacobi, pivoted QR) stays in FP64.
+//
+// Work decomposition as in the FP64 pass: stream-K over (tile, k-step) units
+// with deterministic partial sums and a fix-up kernel; BM = 256 rows, BN =
+// 32 * CBW columns, BK = 64 (two MFMA depths), 8 waves (4 along M x 2 along
+// L), each wave 4 x CBW accumulator tiles.  The large BM halves the re-reads
+// of the skinny operand per byte of A; the deep k-step keeps enough bytes of
+// A in flight per workgroup for a pass that is bound by HBM, not by the
+// matrix cores.
+//
+// MFMA operand layout (16 x 16 x 32, lane l, g = l / 16, c = l % 16):
+//   A: lane l holds A[c][8 g .. 8 g + 7]; B: lane l holds B[8 g .. 8 g + 7][c];
+//   D: lane l element v holds D[4 g + v][c].
+// Both operands are staged in LDS with k contiguous ([row][k] for A, [col][k]
+// for Xt), rows padded to 40 elements, so each lane reads its 8 values with
+// one 16-byte LDS load.  A transposed pass (A stored K x M) transposes its
+// tile on the way into LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace rsvd {
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 256;
+constexpr int BK = 64;
+constexpr int KP = BK + 8;         // padded k extent of an LDS row
+constexpr int NT = 512;
+constexpr int RB = BM / 64;        // 16-row accumulator tiles per wave
+
+struct Bf16Args {
+  const uint16_t* A; int64_t lda;
+  const uint16_t* X; int64_t ldx;     // Xt: L x K, row c holds column c of X
+  float* C; int64_t ldc;
+  int64_t M, K, L;
+  int64_t nct, KI, U, G;
+  float* part;
+  int accumulate;                     // C += op(A) Xt instead of C = op(A) Xt
+};
+
+__device__ __forceinline__ int64_t range_begin(int64_t w, int64_t U, int64_t G) {
+  return (w * U) / G;
+}
+
+// RNE rounding of an FP32 value to BF16 bits (NaN kept quiet)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <bool TRANS, int CBW>
+__global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
+  constexpr int BN = 32 * CBW;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BN * KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave & 3;
+  const int wc = wave >> 2;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+
+  const int64_t w = blockIdx.x;
+  int64_t u = range_begin(w, g.U, g.G);
+  const int64_t uend = range_begin(w + 1, g.U, g.G);
+
+  // staging in 8-element (16-byte) chunks: APT per thread for A, XPT (the
+  // last one partial) for Xt
+  constexpr int ACH = BM * BK / 8;
+  constexpr int APT = ACH / NT;
+  constexpr int XCH = BK * BN / 8;
+  constexpr int XPT = (XCH + NT - 1) / NT;
+
+  while (u < uend) {
+    const int64_t tile = u / g.KI;
+    const int64_t kb = u - tile * g.KI;
+    const int64_t ke = min(g.KI, kb + (uend - u));
+    u += ke - kb;
+    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t col0 = (tile % g.nct) * BN;
+
+    f4 acc[RB][CBW];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    us8 ra[APT];
+    us8 rx[XPT];
+
+    auto gload = [&](int64_t kt) {
+      const int64_t k0 = kt * BK;
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        const int ch = tid + q * NT;
+        us8 v;
+        if (!TRANS) {
+          // row ch / 8, k chunk (ch % 8) * 8
+          const int64_t gi = row0 + (ch >> 3);
+          const int64_t gk = k0 + (ch & 7) * 8;
+          const uint16_t* p = g.A + gi * g.lda + gk;
+          if (gi < g.M && gk + 8 <= g.K) {
+            v = *reinterpret_cast<const us8*>(p);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (gi < g.M && gk + j < g.K) ? p[j] : (uint16_t)0;
+          }
+        } else {
+          // k row ch % 64, i chunk (ch / 64) * 8: consecutive lanes take
+          // consecutive k, so the transposing LDS writes do not collide
+          const int64_t gk = k0 + (ch & 63);
+          const int64_t gi = row0 + (ch >> 6) * 8;
+          const uint16_t* p = g.A + gk * g.lda + gi;
+          if (gk < g.K && gi + 8 <= g.M) {
+            v = *reinterpret_cast<const us8*>(p);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (gk < g.K && gi + j < g.M) ? p[j] : (uint16_t)0;
+          }
+        }
+        ra[q] = v;
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int ch = tid + q * NT;
+        us8 v = us8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (ch < XCH) {
+          // column ch / 8 of the tile, k chunk (ch % 8) * 8
+          const int64_t gj = col0 + (ch >> 3);
+          const int64_t gk = k0 + (ch & 7) * 8;
+          const uint16_t* p = g.X + gj * g.ldx + gk;
+          if (gj < g.L && gk + 8 <= g.K) {
+            v = *reinterpret_cast<const us8*>(p);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (gj < g.L && gk + j < g.K) ? p[j] : (uint16_t)0;
+          }
+        }
+        rx[q] = v;
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        const int ch = tid + q * NT;
+        if (!TRANS) {
+          *reinterpret_cast<us8*>(&As[buf][(ch >> 3) * KP + (ch & 7) * 8]) = ra[q];
+        } else {
+          const int kr = ch & 63, i0 = (ch >> 6) * 8;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) As[buf][(i0 + j) * KP + kr] = ra[q][j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int ch = tid + q * NT;
+        if (ch < XCH) *reinterpret_cast<us8*>(&Xs[buf][(ch >> 3) * KP + (ch & 7) * 8]) = rx[q];
+      }
+    };
+
+    gload(kb);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t kt = kb; kt < ke; ++kt) {
+      const bool more = kt + 1 < ke;
+      if (more) gload(kt + 1);
+#pragma unroll
+      for (int kk = 0; kk < BK / 32; ++kk) {
+        bf8 av[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int i = wr * 16 * RB + rb * 16 + li;
+          av[rb] = *reinterpret_cast<const bf8*>(&As[buf][i * KP + kk * 32 + lk * 8]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) {
+          const int j = wc * 16 * CBW + cb * 16 + li;
+          const bf8 bv = *reinterpret_cast<const bf8*>(&Xs[buf][j * KP + kk * 32 + lk * 8]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], bv, acc[rb][cb], 0, 0, 0);
+        }
+      }
+      if (more) sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+
+    const bool full = (kb == 0) && (ke == g.KI);
+    if (full) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
+            if (r < g.M && c < g.L) {
+              float* cp = g.C + r * g.ldc + c;
+              *cp = g.accumulate ? *cp + acc[rb][cb][v] : acc[rb][cb][v];
+            }
+          }
+    } else {
+      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      float* P = g.part + slot * (int64_t)(BM * BN);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int c = wc * 16 * CBW + cb * 16 + li;
+            P[r * BN + c] = acc[rb][cb][v];
+          }
+    }
+  }
+}
+
+// Sums the partial tiles of every split tile in workgroup order.
+constexpr int FIX_CHUNK = 1024;
+
+template <int CBW>
+__global__ __launch_bounds__(256) void bf16_fixup_kernel(Bf16Args g) {
+  constexpr int BN = 32 * CBW;
+  const int64_t tile = blockIdx.x;
+  const int64_t ufirst = tile * g.KI;
+  const int64_t ulast = ufirst + g.KI - 1;
+  const int64_t wf = ((ufirst + 1) * g.G + g.U - 1) / g.U - 1;
+  const int64_t wl = ((ulast + 1) * g.G + g.U - 1) / g.U - 1;
+  if (wf == wl) return;
+  const int64_t row0 = (tile / g.nct) * BM;
+  const int64_t col0 = (tile % g.nct) * BN;
+  const int e0 = blockIdx.y * FIX_CHUNK;
+  const int e1 = min(e0 + FIX_CHUNK, BM * BN);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t r = row0 + e / BN;
+    const int64_t c = col0 + e % BN;
+    if (r >= g.M || c >= g.L) continue;
+    float s = 0.f;
+    for (int64_t w = wf; w <= wl; ++w) {
+      if (range_begin(w, g.U, g.G) == range_begin(w + 1, g.U, g.G)) continue;
+      const int64_t slot = 2 * w + (w == wf ? 1 : 0);
+      s += g.part[slot * (int64_t)(BM * BN) + e];
+    }
+    float* cp = g.C + r * g.ldc + c;
+    *cp = g.accumulate ? *cp + s : s;
+  }
+}
+
+template <bool TRANS, int CBW>
+hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t T = g.U / g.KI;
+  if (g.G != T) {
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((bf16_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s, g);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <bool TRANS>
+hipError_t dispatch_bf16(const Bf16Args& g, int cbw, hipStream_t s) {
+  switch (cbw) {
+    case 1: return run_bf16<TRANS, 1>(g, s);
+    case 2: return run_bf16<TRANS, 2>(g, s);
+    case 3: return run_bf16<TRANS, 3>(g, s);
+    case 4: return run_bf16<TRANS, 4>(g, s);
+    case 5: return run_bf16<TRANS, 5>(g, s);
+    case 6: return run_bf16<TRANS, 6>(g, s);
+    case 7: return run_bf16<TRANS, 7>(g, s);
+    case 8: return run_bf16<TRANS, 8>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Xt[c * ldo + k] = bf16(X[k * ldi + c]) for c < cols, k < rows; the padding
+// k in [rows, ldo) is zero.  One thread per output element, k fastest.
+template <typename T>
+__global__ __launch_bounds__(256) void convert_bf16_kernel(const T* __restrict__ in, int64_t ldi,
+                                                           int64_t rows, int cols,
+                                                           uint16_t* __restrict__ out,
+                                                           int64_t ldo) {
+  const int64_t total = (int64_t)cols * ldo;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / ldo);
+    const int64_t k = e - (int64_t)c * ldo;
+    out[e] = (k < rows) ? to_bf16((float)in[k * ldi + c]) : (uint16_t)0;
+  }
+}
+
+// Xt[c * ldo + k] = bf16(X[k][c] - bf16(X[k][c])): the low part of a two-term
+// BF16 split (the subtraction is exact in FP32).
+__global__ __launch_bounds__(256) void bf16_residual_kernel(const float* __restrict__ in,
+                                                            int64_t ldi, int64_t rows, int cols,
+                                                            uint16_t* __restrict__ out,
+                                                            int64_t ldo) {
+  const int64_t total = (int64_t)cols * ldo;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / ldo);
+    const int64_t k = e - (int64_t)c * ldo;
+    uint16_t v = 0;
+    if (k < rows) {
+      const float x = in[k * ldi + c];
+      const float hi = __uint_as_float((uint32_t)to_bf16(x) << 16);
+      v = to_bf16(x - hi);
+    }
+    out[e] = v;
+  }
+}
+
+}  // namespace
+
+GemmPlan plan_gemm_bf16(int64_t M, int64_t K, int64_t L, int ncu) {
+  GemmPlan p;
+  const int64_t ncb = cdiv(L, 16);
+  p.cbw = ncb <= 16 ? (int)cdiv(ncb, 2) : 8;
+  if (p.cbw < 1) p.cbw = 1;
+  const int64_t BN = 32 * p.cbw;
+  p.nrt = cdiv(M, BM);
+  p.nct = cdiv(L, BN);
+  p.KI = cdiv(K, BK);
+  if (p.KI < 1) p.KI = 1;
+  const int64_t T = p.nrt * p.nct;
+  p.U = T * p.KI;
+  if (p.KI <= 8 && T >= ncu / 2) p.G = T;
+  else p.G = p.U < ncu ? p.U : ncu;
+  p.bm = BM;
+  p.bn = (int)BN;
+  return p;
+}
+
+size_t gemm_bf16_part_bytes(const GemmPlan& p) {
+  if (p.G == p.nrt * p.nct) return 0;
+  return (size_t)(2 * p.G) * (size_t)(p.bm * p.bn) * sizeof(float);
+}
+
+namespace {
+hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t* Xt, int64_t ldx,
+                     float* C, int64_t ldc, int64_t M, int64_t K, int64_t L, const GemmPlan& plan,
+                     void* part, size_t part_cap, bool accumulate, hipStream_t s) {
+  if (M <= 0 || L <= 0) return hipSuccess;
+  if (L > 256) return hipErrorInvalidValue;
+  GemmPlan p = plan;
+  if (gemm_bf16_part_bytes(p) > part_cap) p.G = p.nrt * p.nct;
+  Bf16Args g;
+  g.A = A; g.lda = lda; g.X = Xt; g.ldx = ldx; g.C = C; g.ldc = ldc;
+  g.M = M; g.K = K; g.L = L;
+  g.nct = p.nct; g.KI = p.KI; g.U = p.U; g.G = p.G;
+  g.part = static_cast<float*>(part);
+  g.accumulate = accumulate ? 1 : 0;
+  return trans ? dispatch_bf16<true>(g, p.cbw, s) : dispatch_bf16<false>(g, p.cbw, s);
+}
+}  // namespace
+
+hipError_t launch_gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t* Xt,
+                            int64_t ldx, float* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
+                            const GemmPlan& plan, void* part, size_t part_cap, hipStream_t s) {
+  return gemm_bf16(trans, A, lda, Xt, ldx, C, ldc, M, K, L, plan, part, part_cap, false, s);
+}
+
+hipError_t launch_gemm_bf16_acc(bool trans, const uint16_t* A, int64_t lda, const uint16_t* Xt,
+                                int64_t ldx, float* C, int64_t ldc, int64_t M, int64_t K,
+                                int64_t L, const GemmPlan& plan, void* part, size_t part_cap,
+                                hipStream_t s) {
+  return gemm_bf16(trans, A, lda, Xt, ldx, C, ldc, M, K, L, plan, part, part_cap, true, s);
+}
+
+hipError_t launch_bf16_residual(const float* X, int64_t ldx, int64_t rows, int cols,
+                                uint16_t* out, int64_t ldo, hipStream_t s) {
+  if (cols <= 0 || ldo <= 0) return hipSuccess;
+  int64_t grid = cdiv((int64_t)cols * ldo, 256);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(bf16_residual_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, ldx, rows,
+                     cols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_bf16(bool in_f32, const void* in, int64_t ldi, int64_t rows, int cols,
+                               uint16_t* out, int64_t ldo, hipStream_t s) {
+  if (cols <= 0 || ldo <= 0) return hipSuccess;
+  int64_t grid = cdiv((int64_t)cols * ldo, 256);
+  if (grid > 8192) grid = 8192;
+  if (in_f32)
+    hipLaunchKernelGGL(convert_bf16_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s,
+                       (const float*)in, ldi, rows, cols, out, ldo);
+  else
+    hipLaunchKernelGGL(convert_bf16_kernel<double>, dim3((unsigned)grid), dim3(256), 0, s,
+                       (const double*)in, ldi, rows, cols, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

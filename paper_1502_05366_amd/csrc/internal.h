@@ -34,6 +34,25 @@ hipError_t launch_gemm(GemmTypes ty, bool trans, const void* A, int64_t lda, con
                        int64_t ldx, void* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
                        const GemmPlan& p, void* part, size_t part_cap, hipStream_t s);
 
+// BF16 passes: C (FP32) = op(A) X with A in BF16 (lda % 8 == 0, 16-byte
+// aligned) and Xt = X^T in BF16 (L x ldx, ldx = rup(K, 8)); L <= 256.
+GemmPlan plan_gemm_bf16(int64_t M, int64_t K, int64_t L, int ncu);
+size_t gemm_bf16_part_bytes(const GemmPlan& p);
+hipError_t launch_gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t* Xt,
+                            int64_t ldx, float* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
+                            const GemmPlan& p, void* part, size_t part_cap, hipStream_t s);
+// the same, adding to C
+hipError_t launch_gemm_bf16_acc(bool trans, const uint16_t* A, int64_t lda, const uint16_t* Xt,
+                                int64_t ldx, float* C, int64_t ldc, int64_t M, int64_t K,
+                                int64_t L, const GemmPlan& p, void* part, size_t part_cap,
+                                hipStream_t s);
+// Xt[c * ldo + k] = bf16(X[k * ldi + c]) (round to nearest even), zero for k >= rows
+hipError_t launch_convert_bf16(bool in_f32, const void* X, int64_t ldi, int64_t rows, int cols,
+                               uint16_t* Xt, int64_t ldo, hipStream_t s);
+// Xt = bf16(X - bf16(X)), the low part of a two-term split of an FP32 X
+hipError_t launch_bf16_residual(const float* X, int64_t ldx, int64_t rows, int cols,
+                                uint16_t* Xt, int64_t ldo, hipStream_t s);
+
 }  // namespace rsvd
 
 namespace rsvd {
@@ -96,9 +115,10 @@ hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const doubl
                           int64_t x_c, hipStream_t s);
 
 // ------------------------------------------------------------------- cur --
-hipError_t launch_gather_cols(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+// atype: element type of A, 0 FP64, 1 FP32, 2 BF16
+hipError_t launch_gather_cols(int atype, const void* A, int64_t lda, int64_t m, int64_t n,
                               const int64_t* J, int k, double* Crow, int64_t ldc, hipStream_t s);
-hipError_t launch_gather_rows_t(bool a_f32, const void* A, int64_t lda, int64_t m, int64_t n,
+hipError_t launch_gather_rows_t(int atype, const void* A, int64_t lda, int64_t m, int64_t n,
                                 const int64_t* Jr, int k, double* Rt, int64_t ldr, hipStream_t s);
 // indices outside [0, in_rows) give zero rows (defensive; they never occur
 // when the pivoted QR succeeded)

@@ -53,7 +53,9 @@ struct Arena {
 struct Shape {
   int64_t m, n;
   int k, p, q, l, lp, kp;
-  bool f32;
+  bool f32;       // skinny matrices (Omega, Y, Q, Z) in FP32 (FP32 and BF16 inputs)
+  bool bf16;      // A in BF16: passes on the BF16 matrix cores
+  int atype;      // element type of A: 0 FP64, 1 FP32, 2 BF16
   size_t dsz;
   int ops;
 };
@@ -66,7 +68,9 @@ Shape make_shape(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) 
   s.l = (int)l;
   s.lp = (int)rup(l, 16);
   s.kp = (int)rup(k, 16);
-  s.f32 = dtype == RSVD_F32;
+  s.bf16 = dtype == RSVD_BF16;
+  s.f32 = dtype == RSVD_F32 || s.bf16;
+  s.atype = dtype == RSVD_F64 ? 0 : (dtype == RSVD_F32 ? 1 : 2);
   s.dsz = s.f32 ? 4 : 8;
   s.ops = ops;
   return s;
@@ -83,6 +87,7 @@ struct OrthBufs {
 
 struct Bufs {
   void *Om, *Y, *Q, *Z, *Zq;
+  uint16_t* Xt;            // BF16 passes: the skinny operand, rounded and transposed
   double *Qh, *Rh, *Wj, *Uh, *Vh;
   OrthBufs ob;
   // ID
@@ -106,6 +111,10 @@ size_t max_part(const Shape& s) {
   };
   upd(s.m, s.n, s.l);
   upd(s.n, s.m, s.l);
+  if (s.bf16) {
+    b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.m, s.n, s.l, ncu)));
+    b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.n, s.m, s.l, ncu)));
+  }
   upd(s.m, s.l, s.k);
   upd(s.n, s.l, s.k);
   upd(s.k, s.n - s.k, s.k);
@@ -138,6 +147,7 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
   b.Q = a.take<char>((size_t)s.m * s.lp * s.dsz);
   b.Z = a.take<char>((size_t)s.n * s.lp * s.dsz);
   b.Zq = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  if (s.bf16) b.Xt = a.take<uint16_t>((size_t)s.lp * rup(std::max(s.m, s.n), 8));
   b.ob = take_orth(a, rmax, s.lp, max_part(s));
   if (s.ops & RSVD_OP_SVD) {
     b.Qh = a.take<double>((size_t)s.n * s.lp);
@@ -213,13 +223,29 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
   return hipSuccess;
 }
 
-hipError_t pass(Ctx& c, bool f32, bool trans, int64_t m, int64_t n, int l, const void* A,
+// One pass over A: Y = A X (trans false) or Y = A^T X (trans true).  atype 0 / 1:
+// X and Y in A's type; atype 2 (BF16 A): X and Y in FP32, X rounded to BF16
+// into xt (l x rup(K, 8)) first.  With split, X = X_hi + X_lo is applied as
+// two BF16 passes whose FP32 results are added (X kept to ~16 bits).
+hipError_t pass(Ctx& c, int atype, bool trans, int64_t m, int64_t n, int l, const void* A,
                 int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* part,
-                size_t part_bytes) {
+                size_t part_bytes, uint16_t* xt = nullptr, bool split = false) {
   const int64_t M = trans ? n : m, K = trans ? m : n;
-  const GemmPlan pg = plan_gemm(M, K, l, std::min(c.ncu, NCU_CAP), 0);
-  return launch_gemm(f32 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l, pg, part,
-                     part_bytes, c.st);
+  if (atype != 2) {
+    const GemmPlan pg = plan_gemm(M, K, l, std::min(c.ncu, NCU_CAP), 0);
+    return launch_gemm(atype == 1 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l,
+                       pg, part, part_bytes, c.st);
+  }
+  const int64_t ldt = rup(K, 8);
+  const GemmPlan pg = plan_gemm_bf16(M, K, l, std::min(c.ncu, NCU_CAP));
+  RSVD_TRY(launch_convert_bf16(true, X, ldx, K, l, xt, ldt, c.st));
+  RSVD_TRY(launch_gemm_bf16(trans, static_cast<const uint16_t*>(A), lda, xt, ldt,
+                            static_cast<float*>(Y), ldy, M, K, l, pg, part, part_bytes, c.st));
+  if (!split) return hipSuccess;
+  // X_lo = X - bf16(X), then Y += A X_lo
+  RSVD_TRY(launch_bf16_residual(static_cast<const float*>(X), ldx, K, l, xt, ldt, c.st));
+  return launch_gemm_bf16_acc(trans, static_cast<const uint16_t*>(A), lda, xt, ldt,
+                              static_cast<float*>(Y), ldy, M, K, l, pg, part, part_bytes, c.st);
 }
 
 struct Outs {
@@ -236,16 +262,23 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
   RSVD_TRY(launch_set_word(c.info, 0, c.st));
   RSVD_TRY(launch_set_word(c.info + 1, 0, c.st));
   // range finder
+  const int at = s.atype;
   RSVD_TRY(launch_sketch(f32, c.seed, 0, 0, n, l, b.Om, lp, c.st));
-  RSVD_TRY(pass(c, f32, false, m, n, l, A, lda, b.Om, lp, b.Y, lp, b.ob.part, b.ob.part_bytes));
+  RSVD_TRY(pass(c, at, false, m, n, l, A, lda, b.Om, lp, b.Y, lp, b.ob.part, b.ob.part_bytes,
+                b.Xt));
   for (int j = 0; j < s.q; ++j) {
     RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
-    RSVD_TRY(pass(c, f32, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes));
+    RSVD_TRY(pass(c, at, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes,
+                  b.Xt));
     RSVD_TRY(orth(c, b.ob, f32, b.Z, lp, n, l, b.Zq, f32, lp, nullptr, 0));
-    RSVD_TRY(pass(c, f32, false, m, n, l, A, lda, b.Zq, lp, b.Y, lp, b.ob.part, b.ob.part_bytes));
+    RSVD_TRY(pass(c, at, false, m, n, l, A, lda, b.Zq, lp, b.Y, lp, b.ob.part, b.ob.part_bytes,
+                  b.Xt));
   }
   RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
-  RSVD_TRY(pass(c, f32, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes));   // B^T
+  // B^T = A^T Q; with a BF16 A the basis enters this last product in two
+  // BF16 parts, so B keeps ~16 bits of Q
+  RSVD_TRY(pass(c, at, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes, b.Xt,
+                true));
   const int ncu = std::min(c.ncu, NCU_CAP);
   // With both the SVD and the ID / CUR requested, the SVD's Jacobi (a few
   // workgroups) and its two products run on the handle's second stream while
@@ -282,12 +315,12 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
     RSVD_TRY(launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st));
     if (o.Jr) {
       // row selection on C^T = A(:, J_k)^T
-      RSVD_TRY(launch_gather_cols(f32, A, lda, m, n, J, k, b.Crow, s.kp, c.st));
+      RSVD_TRY(launch_gather_cols(s.atype, A, lda, m, n, J, k, b.Crow, s.kp, c.st));
       const CpqrPlan cp2 = plan_cpqr(k, m, k, ncq);
       RSVD_TRY(launch_cpqr(false, b.Crow, s.kp, k, m, k, cp2, b.cq2_work, b.J2, b.S11t2, b.S12t2,
                            s.kp, b.pivn2, c.info, !fork, c.st));
       // R^T = A(Jr, :)^T = Qt Rt
-      RSVD_TRY(launch_gather_rows_t(f32, A, lda, m, n, b.J2, k, b.Rt, s.kp, c.st));
+      RSVD_TRY(launch_gather_rows_t(s.atype, A, lda, m, n, b.J2, k, b.Rt, s.kp, c.st));
       RSVD_TRY(orth(c, b.ob2, false, b.Rt, s.kp, n, k, b.Qt, false, s.kp, b.Rtt, s.kp));
       // M = T Qt(J_res, :) + Qt(J_k, :)
       RSVD_TRY(launch_pick_rows(b.Qt, s.kp, n, J + k, n - k, k, b.Qres, s.kp, false, c.st));
@@ -312,7 +345,7 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
 
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
   if (!h) return -1;
-  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
   if (m < 1) return -3;
   if (n < 1) return -4;
   if (k < 1 || k > std::min(m, n)) return -5;
@@ -379,7 +412,7 @@ const char* rsvd_status_string(int code) {
 }
 
 size_t rsvd_workspace_bytes(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) {
-  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || m < 1 || n < 1 || k < 1 ||
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) || m < 1 || n < 1 || k < 1 ||
       k > std::min(m, n) || p < 0 || q < 0 || (ops & 7) == 0)
     return 0;
   if (ops & RSVD_OP_CUR) ops |= RSVD_OP_ID;
@@ -396,6 +429,7 @@ int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int 
   if (rc) return rc;
   if (!A) return -9;
   if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
   const bool svd = U || S || V;
   if (svd) {
     if (!U) return -11;
@@ -446,6 +480,7 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   if (rc) return rc;
   if (!A) return -9;
   if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
   if (!U) return -11;
   if (ldu < k) return -12;
   if (!S) return -13;
@@ -473,6 +508,7 @@ int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int 
   if (rc) return rc;
   if (!A) return -9;
   if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
   if (!J) return -11;
   if (!T) return -12;
   if (ldt < n - k || ldt < 1) return -13;
@@ -499,6 +535,7 @@ int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   if (rc) return rc;
   if (!A) return -9;
   if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
   if (!Jc) return -11;
   if (!Jr) return -12;
   if (!Ucur) return -13;
@@ -545,8 +582,14 @@ int rsvd_philox(rsvd_handle_t h, uint64_t seed, uint32_t stream_id, uint32_t bat
 }
 
 size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int64_t l) {
-  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || m < 1 || n < 1 || l < 1) return 0;
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) || m < 1 || n < 1 || l < 1)
+    return 0;
   const int64_t M = trans ? n : m, K = trans ? m : n;
+  if (dtype == RSVD_BF16) {
+    if (l > MAX_L) return 0;
+    return gemm_bf16_part_bytes(plan_gemm_bf16(M, K, l, NCU_CAP)) + 256 +
+           (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
+  }
   return gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8) + 256;
 }
 
@@ -554,13 +597,14 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
               const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy,
               void* work, size_t work_bytes, void* stream) {
   if (!h) return -1;
-  if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
+  if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
   if (trans != 0 && trans != 1) return -3;
   if (m < 1) return -4;
   if (n < 1) return -5;
   if (l < 1) return -6;
   if (!A) return -7;
   if (lda < n) return -8;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -8;
   if (!X) return -9;
   if (ldx < l) return -10;
   if (!Y) return -11;
@@ -569,8 +613,17 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
   if (work_bytes > 256 && !work) return -13;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0, h};
-  return finish(pass(c, dtype == RSVD_F32, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy,
-                     work, work ? work_bytes : 0));
+  if (dtype == RSVD_BF16) {
+    if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+    const int64_t K = trans ? m : n;
+    const size_t xt_bytes = (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
+    char* wb = static_cast<char*>(work);
+    uint16_t* xt = reinterpret_cast<uint16_t*>(wb);
+    return finish(pass(c, 2, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy, wb + xt_bytes,
+                       work_bytes - xt_bytes, xt));
+  }
+  return finish(pass(c, dtype == RSVD_F32 ? 1 : 0, trans == 1, m, n, (int)l, A, lda, X, ldx, Y,
+                     ldy, work, work ? work_bytes : 0));
 }
 
 size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {

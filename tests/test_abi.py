@@ -54,7 +54,7 @@ def svd_call(lib, **kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(h=NULLP), -1), (dict(dtype=7), -2), (dict(m=0), -3), (dict(n=-1), -4),
+    (dict(h=NULLP), -1), (dict(dtype=7), -2), (dict(dtype=2, lda=81), -10), (dict(m=0), -3), (dict(n=-1), -4),
     (dict(k=0), -5), (dict(k=81), -5), (dict(p=-1), -6), (dict(q=-2), -7),
     (dict(A=NULLP), -9), (dict(lda=79), -10), (dict(U=NULLP), -11), (dict(ldu=9), -12),
     (dict(S=NULLP), -13), (dict(V=NULLP), -14), (dict(ldv=3), -15), (dict(work=NULLP), -16),

@@ -1,0 +1,99 @@
+"""Mixed-precision path (needs a GPU): A stored in BF16, passes on the BF16
+matrix cores with FP32 accumulation, everything after the passes in FP64.
+
+Oracle: the FP64 oracle run on the BF16 values of A converted exactly to
+FP64, so the comparison isolates the rounding of the range-finder operands
+to BF16 (and of the FP32 accumulation) from the rounding of A itself.
+Bar: passes exact on small integers; sigma within 1e-3 relative of the
+oracle's (the mixed-precision target); skeleton indices identical on the
+separated-skeleton input.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rsvd as O
+from paper_1502_05366_amd import workloads as W
+from tests.helpers import orth_err
+
+pytestmark = pytest.mark.gpu
+EPS32 = float(np.finfo(np.float32).eps)
+SEED = 0x5EED0000
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1502_05366_amd as R
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return R
+
+
+def bf16(x):
+    """BF16 tensor on the GPU (round to nearest even) and its exact FP64 value."""
+    t = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).to(torch.bfloat16)
+    return t.cuda(), t.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("m,n,l", [(333, 520, 30), (1000, 2000, 220), (130, 72, 1), (2047, 136, 256),
+                                   (257, 1003, 17)])
+def test_bf16_pass_exact_on_integers(R, m, n, l):
+    A = W.integer_matrix(m, n, seed=m + n)
+    Xn = W.integer_matrix(n, l, seed=l + 1)
+    Xm = W.integer_matrix(m, l, seed=l + 2)
+    Ad, _ = bf16(A)
+    Y = R.pass_(Ad, torch.as_tensor(Xn, dtype=torch.float32, device="cuda")).cpu().numpy()
+    Z = R.pass_(Ad, torch.as_tensor(Xm, dtype=torch.float32, device="cuda"), trans=True).cpu().numpy()
+    # small integers are exact in BF16 and every partial sum is exact in FP32
+    assert np.array_equal(Y.astype(np.float64), A @ Xn)
+    assert np.array_equal(Z.astype(np.float64), A.T @ Xm)
+
+
+def test_bf16_pass_random_bound(R):
+    g = np.random.default_rng(4)
+    m, n, l = 3001, 1777, 220
+    Ad, A = bf16(g.standard_normal((m, n)))
+    X = g.standard_normal((n, l)).astype(np.float32)
+    Xr = torch.as_tensor(X).to(torch.bfloat16).to(torch.float64).numpy()   # what the pass uses
+    Y = R.pass_(Ad, torch.as_tensor(X, device="cuda")).cpu().numpy().astype(np.float64)
+    # FP32 accumulation of exact BF16 x BF16 products
+    assert np.all(np.abs(Y - A @ Xr) <= 2 * n * EPS32 * (np.abs(A) @ np.abs(Xr)) + 1e-30)
+
+
+def test_bf16_decompose_vs_oracle(R):
+    m, n, k, p, q = 2000, 1000, 20, 10, 1
+    A, _ = W.c1_matrix()
+    Ad, Aq = bf16(A)
+    out = R.decompose(Ad, k, p, q, SEED)
+    S = out["S"].cpu().numpy()
+    U = out["U"].cpu().numpy().astype(np.float64)
+    V = out["V"].cpu().numpy().astype(np.float64)
+    assert int(out["info"].cpu()[0]) == 0
+    _, So, _ = O.rsvd(Aq, k, p, q, SEED)
+    rel = np.max(np.abs(S - So) / So)
+    print("BF16 C1: max sigma rel err vs FP64 oracle on the BF16 A: %.3e" % rel)
+    assert rel <= 1e-3
+    assert orth_err(U) < 1e-5 and orth_err(V) < 1e-5
+    # the factorization is as accurate as the oracle's, to BF16 level
+    e = np.linalg.norm(Aq - (U * S) @ V.T, 2)
+    eo = np.linalg.norm(Aq - (O.rsvd(Aq, k, p, q, SEED)[0] * So) @ O.rsvd(Aq, k, p, q, SEED)[2].T, 2)
+    assert e <= eo * (1 + 1e-2) + 1e-3 * So[0]
+
+
+def test_bf16_separated_skeleton(R):
+    m, n, r = 3000, 5000, 60
+    A, pi, d = W.separated_skeleton_matrix(m, n, r, seed=17)
+    Ad, _ = bf16(A)
+    J, T, info = R.id(Ad, 40, 20, 1, SEED)
+    assert list(J.cpu().numpy()[:40]) == list(pi[:40])
+
+
+def test_bf16_argument_checks(R):
+    import ctypes
+    from paper_1502_05366_amd import _lib, api
+    lib = _lib.load()
+    A = torch.zeros((64, 70), dtype=torch.bfloat16, device="cuda")     # lda = 70: not % 8
+    rc = lib.rsvd_svd(api.handle(A.device), api.BF16, 64, 70, 4, 2, 0, 1, ctypes.c_void_p(A.data_ptr()),
+                      70, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4,
+                      ctypes.c_void_p(16), 1 << 30, ctypes.c_void_p(16), None)
+    assert rc == -10
