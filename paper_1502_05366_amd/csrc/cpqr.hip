@@ -381,7 +381,9 @@ size_t cpqr_lds_bytes(int64_t cs, int rp, int k) {
 
 CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
   CpqrPlan p;
-  p.rp = (int)rup(r, 2);
+  // column stride of the LDS slab: rp = 16 (mod 32) doubles puts consecutive
+  // columns on opposite halves of the LDS banks
+  p.rp = (int)(rup(r + 16, 32) - 16);
   int64_t G = cdiv(c, 32);
   if (G > ncu) G = ncu;
   if (G < 1) G = 1;

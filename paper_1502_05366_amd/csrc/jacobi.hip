@@ -34,19 +34,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Rotation (c, s) that orthogonalizes a column pair with squared norms al, be
 // and inner product ga (the formulas in the header); false when the pair is
 // already orthogonal to within tol.
+// 1/x with one Newton step: enough for quantities that only set the rotation
+// angle (c and s are made consistent afterwards)
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol,
                                                 double& cs, double& sn) {
-  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
-  const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+  // |ga| > tol sqrt(al be), compared in squares
+  if (!(ga * ga > (tol * tol) * (al * be))) return false;
+  const double zeta = (be - al) * (0.5 * rcp_nr1(ga));
   const double az = fabs(zeta);
   double t;
   if (az < 1e150) {
     const double z2 = fma(zeta, zeta, 1.0);
-    t = rcp_nr(az + z2 * rsq_nr(z2));
+    t = rcp_nr1(az + z2 * rsq_nr(z2));
   } else {
-    t = 0.5 / az;
+    t = 0.5 * rcp_nr1(az);
   }
   t = zeta >= 0.0 ? t : -t;
+  // c = 1 / sqrt(1 + t^2) to full precision, so that c^2 + s^2 = 1 to rounding
   cs = rsq_nr(fma(t, t, 1.0));
   sn = cs * t;
   return true;
@@ -210,9 +219,12 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
 // 2BS x 2BS orthogonal J (two rows per lane), and the round ends with
 // V(:, pair blocks) <- V(:, pair blocks) J on the matrix cores.
 constexpr int JB_NT = 256;   // 4 waves x 4 pairs = BS pairs per step
-constexpr int JLD = 256;     // LDS column length of W (rows >= l hold zeros)
-constexpr int JRPL = JLD / 16;
+constexpr int JLD = 272;     // LDS column stride of W: 256 rows (rows >= l hold zeros) + 16
+                             // doubles, so columns q and q+1 start on opposite halves
+                             // of the LDS banks
+constexpr int JRPL = 256 / 16;
 constexpr int JJ = 2 * BS;   // order of J
+constexpr int JJS = 48;      // LDS column stride of J (alternating bank halves)
 
 __device__ __forceinline__ double row16_sum(double x) {
   x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
@@ -261,12 +273,12 @@ __device__ __forceinline__ void lds_col_store(double* base, int rl, const double
   for (int e = 0; e < JRPL; ++e) base[rl + 16 * e] = v[e];
 }
 __device__ __forceinline__ void lds_j_load(const double* Jl, int col, int rl, double (&v)[2]) {
-  v[0] = Jl[col * JJ + rl];
-  v[1] = Jl[col * JJ + rl + 16];
+  v[0] = Jl[col * JJS + rl];
+  v[1] = Jl[col * JJS + rl + 16];
 }
 __device__ __forceinline__ void lds_j_store(double* Jl, int col, int rl, const double (&v)[2]) {
-  Jl[col * JJ + rl] = v[0];
-  Jl[col * JJ + rl + 16] = v[1];
+  Jl[col * JJS + rl] = v[0];
+  Jl[col * JJS + rl + 16] = v[1];
 }
 
 __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   const int w = blockIdx.x;
   const int l = a.l;
   double* Wl = smem;                        // [2*BS][JLD]
-  double* Jl = smem + 2 * BS * JLD;         // [JJ][JJ], column-major
+  double* Jl = smem + 2 * BS * JLD;         // [JJ][JJS], column-major
   uint32_t done = 0;
   int sweep = 0;
   bool converged = false;
@@ -290,21 +302,24 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
       // load the two W blocks (columns >= l and rows >= l read as zero), each
       // thread issuing all its loads before its LDS writes; J = I
       {
-        constexpr int PER = 2 * BS * JLD / JB_NT;
+        constexpr int PER = 2 * BS * 256 / JB_NT;
         double vv[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JB_NT;
-          const int c = idx / JLD, i = idx % JLD;
+          const int c = idx / 256, i = idx % 256;
           const int gcol = gcol_of(c);
           vv[e] = (i < l && gcol < l) ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < PER; ++e) Wl[tid + e * JB_NT] = vv[e];
+        for (int e = 0; e < PER; ++e) {
+          const int idx = tid + e * JB_NT;
+          Wl[(idx / 256) * JLD + idx % 256] = vv[e];
+        }
 #pragma unroll
         for (int e = 0; e < JJ * JJ / JB_NT; ++e) {
           const int idx = tid + e * JB_NT;
-          Jl[idx] = (idx / JJ == idx % JJ) ? 1.0 : 0.0;
+          Jl[(idx / JJ) * JJS + idx % JJ] = (idx / JJ == idx % JJ) ? 1.0 : 0.0;
         }
       }
       __syncthreads();
@@ -343,13 +358,13 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
       __syncthreads();
       // W back to memory
       {
-        constexpr int PER = 2 * BS * JLD / JB_NT;
+        constexpr int PER = 2 * BS * 256 / JB_NT;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = tid + e * JB_NT;
-          const int c = idx / JLD, i = idx % JLD;
+          const int c = idx / 256, i = idx % 256;
           const int gcol = gcol_of(c);
-          if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[idx]);
+          if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * JLD + i]);
         }
       }
       // V(:, pair) <- V(:, pair) J: wave v takes row tiles v, v+4, v+8, v+12
@@ -371,7 +386,7 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
         for (int ct = 0; ct < JJ / 16; ++ct) {
           double bv[JJ / 4];
 #pragma unroll
-          for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJ + kk * 4 + lk];
+          for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJS + kk * 4 + lk];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
@@ -471,7 +486,7 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                      s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64 * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t shm = (2 * (size_t)BS * JLD + (size_t)JJ * JJ) * sizeof(double);
+  const size_t shm = (2 * (size_t)BS * JLD + (size_t)JJ * JJS) * sizeof(double);
   e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
