@@ -88,7 +88,8 @@ size_t rsvd_workspace_bytes(int ops, int dtype, int64_t m, int64_t n, int k, int
  *   Q = orth(Y);  B^T = A^T Q;  [Qh, Rh] = qr(B^T);  Rh = Uh diag(S) Vh^T;
  *   U = Q Vh(:, 1:k),  V = Qh Uh(:, 1:k).
  * A: m x n (lda >= n).  U: m x k (ldu >= k), V: n x k (ldv >= k), both of the
- * type of A.  S: k FP64 values, descending.  A ~ U diag(S) V^T. */
+ * type of A (FP32 for RSVD_BF16).  S: k FP64 values, descending.
+ * A ~ U diag(S) V^T. */
 int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
              uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
              void* V, int64_t ldv, void* work, size_t work_bytes, int32_t* info,
@@ -99,7 +100,9 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
  * and T = S11^{-1} S12 (Sec. 2.4).  J: n int64, J[k..n) are the remaining
  * columns in ascending order.  T: k x (n-k) FP64 (ldt >= n-k), its column j
  * belongs to column J[k+j] of A.  With V = P [I_k; T^T] (V[J[i], :] = e_i,
- * V[J[k+j], :] = T(:, j)^T), A ~ A(:, J[0..k)) V^T. */
+ * V[J[k+j], :] = T(:, j)^T), A ~ A(:, J[0..k)) V^T.  When the numerical rank
+ * is below k (RSVD_INFO_RANK), an exactly zero pivot of S11 gives a zero row
+ * of T. */
 int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
             uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
             void* work, size_t work_bytes, int32_t* info, void* stream);
@@ -151,9 +154,10 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
 
 /* orth (Sec. 2.1): Q (rows x l, type dtype) with orthonormal columns and
  * Y = Q R, by CholeskyQR2 in FP64; R (l x l FP64, upper triangular with a
- * positive diagonal, zero below; may be NULL).  Dependent columns of Y are
- * replaced by random vectors (RSVD_INFO_ORTH_FALLBACK); then Y = Q R holds
- * only on the range of Y.  rows >= l, l <= 256. */
+ * positive diagonal, zero below; may be NULL).  A column of Y that depends on
+ * the columns before it gets a fresh random direction in Q
+ * (RSVD_INFO_ORTH_FALLBACK) and a zero diagonal in R, so Y = Q R still holds
+ * to rounding.  rows >= l, l <= 256. */
 size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l);
 int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
               void* Q, int64_t ldq, double* R, int64_t ldr, uint64_t seed, void* work,

@@ -324,14 +324,19 @@ __global__ __launch_bounds__(256) void replace_kernel(TQ* __restrict__ Q, int64_
 }
 
 // C = A B for upper-triangular lp x lp A, B (C upper triangular, zero below).
+// C = A B for upper-triangular A, B; rows k of B with bdep[k] != 0 count as
+// zero (the unit rows that the Cholesky gives dependent columns stand for a
+// zero residual, so the product is the R of Y = Q R).
 __global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am, int64_t lda,
                                                    const double* __restrict__ Bm, int64_t ldb,
+                                                   const int32_t* __restrict__ bdep,
                                                    double* __restrict__ C, int64_t ldc, int lp) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)lp * lp) return;
   const int i = (int)(e / lp), j = (int)(e % lp);
   double s = 0.0;
-  for (int k = i; k <= j; ++k) s += Am[(int64_t)i * lda + k] * Bm[(int64_t)k * ldb + j];
+  for (int k = i; k <= j; ++k)
+    if (!bdep || bdep[k] == 0) s += Am[(int64_t)i * lda + k] * Bm[(int64_t)k * ldb + j];
   C[(int64_t)i * ldc + j] = (i <= j) ? s : 0.0;
 }
 
@@ -531,10 +536,10 @@ hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, co
   return hipGetLastError();
 }
 
-hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                             int64_t ldc, int lp, hipStream_t s) {
+hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb,
+                             const int32_t* bdep, double* C, int64_t ldc, int lp, hipStream_t s) {
   hipLaunchKernelGGL(trmm_kernel, dim3((unsigned)cdiv((int64_t)lp * lp, 256)), dim3(256), 0, s, A,
-                     lda, B, ldb, C, ldc, lp);
+                     lda, B, ldb, bdep, C, ldc, lp);
   return hipGetLastError();
 }
 

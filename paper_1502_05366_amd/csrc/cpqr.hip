@@ -345,7 +345,8 @@ __global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__
     for (int ll = 63; ll >= 0; --ll) {
       const int i = 64 * q + ll;
       if (i >= k) continue;
-      const double xi = __shfl(x[q], ll, 64) / S[(int64_t)i * s_r + (int64_t)i * s_c];
+      const double sii = S[(int64_t)i * s_r + (int64_t)i * s_c];
+      const double xi = (sii != 0.0) ? __shfl(x[q], ll, 64) / sii : 0.0;
       if (lane == ll) x[q] = xi;
 #pragma unroll
       for (int q2 = 0; q2 <= q; ++q2) {

@@ -77,9 +77,10 @@ hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64
 // overwrite the columns j with dep[j] != 0 of Q (M rows) by N(0, 1/M) values
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
                           uint64_t seed, uint32_t call, hipStream_t s);
-// C = A B for upper-triangular lp x lp matrices
-hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                             int64_t ldc, int lp, hipStream_t s);
+// C = A B for upper-triangular lp x lp matrices; rows k of B with bdep[k] != 0
+// (bdep may be null) are taken as zero
+hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb,
+                             const int32_t* bdep, double* C, int64_t ldc, int lp, hipStream_t s);
 hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s);
 
 // ---------------------------------------------------------------- jacobi --
@@ -110,6 +111,7 @@ size_t cpqr_work_bytes(const CpqrPlan& p);
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
                        const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
                        int64_t lds, double* pivn, int32_t* info, bool coop, hipStream_t s);
+// X = S^{-1} B by back substitution (k <= 256); a zero pivot S_ii gives x_i = 0
 hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const double* Bm,
                           int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,
                           int64_t x_c, hipStream_t s);

@@ -161,3 +161,47 @@ def test_decompose_matches_single_calls(R, c1):
     assert torch.equal(out["S"], S) and torch.equal(out["U"], U)
     assert torch.equal(out["J"], J) and torch.equal(out["T"], T)
     assert torch.equal(out["Jr"], Jr) and torch.equal(out["Ucur"], Uc)
+
+
+def test_zero_matrix(R):
+    # every sample column is dependent: orth replaces them all, sigma = 0,
+    # the pivoted QR reports numerical rank 0 and picks the lowest indices
+    A = np.zeros((300, 200))
+    out = R.decompose(dev(A), 5, 5, 1, SEED)
+    info = out["info"].cpu().numpy()
+    assert np.all(out["S"].cpu().numpy() == 0.0)
+    assert info[0] & R.INFO_ORTH_FALLBACK
+    assert info[0] & R.INFO_RANK and info[1] == 0
+    assert orth_err(out["U"].cpu().numpy()) < 1e-12
+    J = out["J"].cpu().numpy()
+    assert np.array_equal(np.sort(J), np.arange(200))
+    assert np.all(np.isfinite(out["T"].cpu().numpy()))
+
+
+def test_rank_one(R):
+    g = np.random.default_rng(11)
+    u, v = g.standard_normal(400), g.standard_normal(250)
+    A = np.outer(u, v)
+    U, S, V, info = R.svd(dev(A), 3, 4, 1, SEED)
+    S = S.cpu().numpy()
+    s1 = np.linalg.norm(u) * np.linalg.norm(v)
+    assert abs(S[0] - s1) <= 1e-13 * s1
+    assert np.all(S[1:] <= 1e-13 * s1)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(150, 900, 12, 6, 1), (900, 150, 12, 6, 2), (96, 96, 96, 0, 0),
+                                       (1, 40, 1, 3, 1), (40, 1, 1, 0, 0)])
+def test_shapes_id_cur(R, m, n, k, p, q):
+    A, s = W.logspace_type(m, n, 2, seed=m + 7 * n)
+    out = R.decompose(dev(A), k, p, q, SEED)
+    c = O.cur(A, k, p, q, SEED)
+    J, Jr = out["J"].cpu().numpy(), out["Jr"].cpu().numpy()
+    npre = pivot_prefix(c["pivot_norms"], c["second_norms"], 1e-8)
+    assert np.array_equal(J[:npre], c["J"][:npre])
+    assert np.array_equal(np.sort(J), np.arange(n))
+    if npre == k:
+        nr = pivot_prefix(c["row_pivot_norms"], c["row_second_norms"], 1e-8)
+        assert np.array_equal(Jr[:nr], c["Jr"][:nr])
+        if nr == k:
+            Uc = out["Ucur"].cpu().numpy()
+            assert np.abs(Uc - c["U"]).max() <= 1e-6 * max(1.0, np.abs(c["U"]).max())
