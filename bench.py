@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RSVD GFLOP/s + % HBM roofline; BF16 vs FP64 speedup at stated σ error"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
@@ -90,15 +91,18 @@ def cpu_baseline(A, k, p, q, seed, budget_s=20.0):
                       "%.1f s; GFLOP/s with the same RSVD flop count" % (ms, m, ms, n, k, p, q, t)}
 
 
-def bf16_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1):
-    """Time rsvd_decompose with A in BF16 and one BF16 pass over A."""
+def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf16):
+    """Time rsvd_decompose with A stored in BF16 (bf16=True) or FP32, and one
+    pass over A of that storage type."""
     import torch
     from paper_1502_05366_amd import api
 
     dev = A.device
-    Ab = A.to(torch.bfloat16)                     # round to nearest even
+    dt = api.BF16 if bf16 else api.F32
+    name = "BF16" if bf16 else "FP32"
+    Ab = A.to(torch.bfloat16 if bf16 else torch.float32)   # round to nearest even
     ops = api.OP_SVD | api.OP_ID | api.OP_CUR
-    wb = lib.rsvd_workspace_bytes(ops, api.BF16, m, n, k, p, q)
+    wb = lib.rsvd_workspace_bytes(ops, dt, m, n, k, p, q)
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     info = torch.zeros(2, dtype=torch.int32, device=dev)
     U = torch.empty((m, k), dtype=torch.float32, device=dev)
@@ -110,10 +114,10 @@ def bf16_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1):
     Uc = torch.empty((k, k), dtype=torch.float64, device=dev)
 
     def step():
-        rc = lib.rsvd_decompose(h, api.BF16, m, n, k, p, q, seed, P(Ab), n, P(U), k, P(S), P(V),
+        rc = lib.rsvd_decompose(h, dt, m, n, k, p, q, seed, P(Ab), n, P(U), k, P(S), P(V),
                                 k, P(J), P(T), n - k, P(Jr), P(Uc), k, P(work), wb, P(info), sp)
         if rc != 0:
-            raise RuntimeError("rsvd_decompose (BF16) returned %d" % rc)
+            raise RuntimeError("rsvd_decompose (%s) returned %d" % (name, rc))
 
     for _ in range(args.warmup):
         step()
@@ -124,41 +128,47 @@ def bf16_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    log("BF16: %.3f ms/step" % ms)
-    # one BF16 pass in each direction (X in FP32, rounded to BF16 inside)
+    log("%s: %.3f ms/step" % (name, ms))
+    # one pass in each direction (X in FP32; with BF16 A it is rounded inside)
     X = torch.randn((n, l), dtype=torch.float32, device=dev)
     Xm = torch.randn((m, l), dtype=torch.float32, device=dev)
     Y = torch.empty((m, l), dtype=torch.float32, device=dev)
     Z = torch.empty((n, l), dtype=torch.float32, device=dev)
-    pw = max(lib.rsvd_pass_workspace_bytes(api.BF16, 0, m, n, l),
-             lib.rsvd_pass_workspace_bytes(api.BF16, 1, m, n, l))
+    pw = max(lib.rsvd_pass_workspace_bytes(dt, 0, m, n, l),
+             lib.rsvd_pass_workspace_bytes(dt, 1, m, n, l))
     pwork = torch.empty(pw, dtype=torch.uint8, device=dev)
     pass_ms = {}
     for trans, Xt, Yt, name in ((0, X, Y, "A_X"), (1, Xm, Z, "At_X")):
         for _ in range(3):
-            lib.rsvd_pass(h, api.BF16, trans, m, n, l, P(Ab), n, P(Xt), l, P(Yt), l, P(pwork), pw,
-                          sp)
+            lib.rsvd_pass(h, dt, trans, m, n, l, P(Ab), n, P(Xt), l, P(Yt), l, P(pwork), pw, sp)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.pass_reps):
-            lib.rsvd_pass(h, api.BF16, trans, m, n, l, P(Ab), n, P(Xt), l, P(Yt), l, P(pwork), pw,
-                          sp)
+            lib.rsvd_pass(h, dt, trans, m, n, l, P(Ab), n, P(Xt), l, P(Yt), l, P(pwork), pw, sp)
         e1.record(stream)
         torch.cuda.synchronize()
         pass_ms[name] = e0.elapsed_time(e1) / args.pass_reps
     t_pass = 0.5 * (pass_ms["A_X"] + pass_ms["At_X"])
-    a_gbs = 2.0 * m * n / (t_pass * 1e-3) / 1e9
     st = info.cpu().numpy()
-    return {"ms_per_step": round(ms, 4),
-            "value_gflops": round(alg_flops(m, n, k, p, q) / (ms * 1e-3) / 1e9, 2),
-            "dtype": "bf16 passes (FP32 accumulation), f64 orth / Jacobi / pivoted QR",
-            "pass_ms": {kk: round(v, 4) for kk, v in pass_ms.items()},
-            "pass_roofline": {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": PEAK_HBM_GBS,
-                              "unit": "GB/s", "frac": round(a_gbs / PEAK_HBM_GBS, 4),
-                              "traffic": None,
-                              "note": "achieved = 2mn bytes of A per pass / mean pass time"},
-            "info": [int(st[0]), int(st[1])],
-            "S": S.cpu().numpy()}
+    out = {"ms_per_step": round(ms, 4),
+           "value_gflops": round(alg_flops(m, n, k, p, q) / (ms * 1e-3) / 1e9, 2),
+           "pass_ms": {kk: round(v, 4) for kk, v in pass_ms.items()},
+           "info": [int(st[0]), int(st[1])],
+           "S": S.cpu().numpy()}
+    if bf16:
+        a_gbs = 2.0 * m * n / (t_pass * 1e-3) / 1e9
+        out["dtype"] = "bf16 passes (FP32 accumulation), f64 orth / Jacobi / pivoted QR"
+        out["pass_roofline"] = {"bound": "hbm", "achieved": round(a_gbs, 1), "peak": PEAK_HBM_GBS,
+                                "unit": "GB/s", "frac": round(a_gbs / PEAK_HBM_GBS, 4),
+                                "traffic": None,
+                                "note": "achieved = 2mn bytes of A per pass / mean pass time"}
+    else:
+        tf = 2.0 * m * n * l / (t_pass * 1e-3) / 1e12
+        out["dtype"] = "f32 passes (FP32 MFMA), f64 orth / Jacobi / pivoted QR"
+        out["pass_roofline"] = {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS,
+                                "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                                "traffic": None}
+    return out
 
 
 def main():
@@ -278,10 +288,13 @@ def main():
     # the same step with A stored in BF16 (passes on the BF16 matrix cores,
     # FP32 accumulation, FP64 after the passes); A is converted once, untimed
     S64 = S.cpu().numpy()
-    bf = bf16_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1)
-    S16 = bf.pop("S")
-    bf["sigma_rel_err_vs_fp64"] = float(np.max(np.abs(S16 - S64) / S64))
-    bf["speedup_vs_fp64"] = round(ms / bf["ms_per_step"], 3)
+    lowp = {}
+    for key, is_bf16 in (("fp32", False), ("bf16", True)):
+        r = lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, is_bf16)
+        Sl = r.pop("S")
+        r["sigma_rel_err_vs_fp64"] = float(np.max(np.abs(Sl - S64) / S64))
+        r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
+        lowp[key] = r
 
     out = {
         "metric": METRIC,
@@ -310,7 +323,8 @@ def main():
         "end_to_end_frac_of_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS, 4),
         "info": [int(st[0]), int(st[1])],
     }
-    out["bf16"] = bf
+    out["fp32"] = lowp["fp32"]
+    out["bf16"] = lowp["bf16"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

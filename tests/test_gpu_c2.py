@@ -78,3 +78,29 @@ def test_c2_cur(c2):
     assert np.array_equal(Jr[:nr], c["Jr"][:nr])
     if nr == K:
         assert np.abs(Uc - c["U"]).max() <= 1e-7 * np.abs(c["U"]).max()
+
+
+def test_c2_fp32(c2):
+    """The same matrix stored in FP32 (passes on the FP32 matrix cores, FP64
+    after them), against the FP64 oracle on the FP64 matrix. Rounding A to
+    FP32 moves each sigma by at most ||A - fl32(A)||_2 <= 2^-24 ||A||_F
+    (~8e-8 here); the passes add O(sqrt(n) 2^-24 sigma_1). Bar 1e-5 sigma_1,
+    as for the small FP32 case."""
+    import paper_1502_05366_amd as R
+    A32 = c2["Ad"].float()
+    out = R.decompose(A32, K, P, Q, SEED)
+    torch.cuda.synchronize()
+    So = c2["So"]
+    S = out["S"].cpu().numpy()
+    assert int(out["info"].cpu()[0]) == 0
+    assert np.abs(S - So).max() <= 1e-5 * So[0]
+    U = out["U"].double()
+    V = out["V"].double()
+    assert orth_err(U.cpu().numpy()) < 1e-5 and orth_err(V.cpu().numpy()) < 1e-5
+    M = (U.T @ (A32.double() @ V)).cpu().numpy()
+    assert np.abs(M - np.diag(S)).max() <= 1e-5 * So[0]
+    c = c2["c"]
+    J = out["J"].cpu().numpy()
+    npre = pivot_prefix(c["pivot_norms"], c["second_norms"], 1e-4)
+    assert np.array_equal(J[:npre], c["J"][:npre])
+    assert np.array_equal(np.sort(J), np.arange(len(J)))
