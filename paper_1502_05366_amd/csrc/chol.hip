@@ -11,6 +11,15 @@
 //    Schur pivot is not above eta * G_jj (numerically dependent on the
 //    columns before it) gets a unit row in R, so it is removed from the
 //    factorization of the later columns and can be replaced afterwards.
+//  * chol_ni_kernel: the factor of the second pass's Gram matrix, which is
+//    I + E with E of the order of the unit roundoff times cond(Y)^2.  With
+//    R = I + F (F upper triangular), R^T R = I + E reads F = Phi(E - F^T F),
+//    Phi taking the strict upper triangle and half the diagonal, so
+//    F = Phi(E) + O(||E||^2) and R^{-1} = I - F + O(||F||^2).  When
+//    ||E||_F^2 <= NI_TAU2 (a quarter of the unit roundoff) both truncations
+//    sit below rounding: the kernel writes R = I + Phi(E) with the inverses
+//    of its diagonal blocks and sets a flag that makes chol_kernel return at
+//    once; otherwise chol_kernel factors G as in the first pass.
 //  * trsm_kernel: Q = Y R^{-1} for a tall Y, one wave per 16 rows, column
 //    block by column block (Q_c = (Y_c - sum_{b<c} Q_b R_bc) R_cc^{-1}).
 //  * replace_kernel: overwrites flagged columns of Q with fresh Gaussian
@@ -66,7 +75,9 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
                                                      int l, int lp, double eta,
                                                      double* __restrict__ R, int64_t ldr,
                                                      double* __restrict__ Rdinv,
-                                                     int32_t* __restrict__ dep, int32_t* info) {
+                                                     int32_t* __restrict__ dep, int32_t* info,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip != nullptr && __builtin_amdgcn_readfirstlane(*skip) != 0) return;
   const int nb = lp / 16;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -227,62 +238,120 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
   }
 }
 
-// Q = Y R^{-1}: one wave per 16 rows of Y.  Q_c = (Y_c - sum_{b<c} Q_b R_bc) Rinv_cc.
-template <typename TY, typename TQ>
+constexpr int NI_NT = 1024;
+constexpr double NI_TAU2 = 2.5e-17;   // bound on ||G - I||_F^2 (~ u / 4, u = 2^-53 ... 2^-52)
+
+__global__ __launch_bounds__(NI_NT) void chol_ni_kernel(const double* __restrict__ G, int64_t ldg,
+                                                        int l, int lp, double* __restrict__ R,
+                                                        int64_t ldr, double* __restrict__ Rdinv,
+                                                        int32_t* __restrict__ dep,
+                                                        int32_t* __restrict__ done) {
+  constexpr int NW = NI_NT / 64;
+  __shared__ double red[NW];
+  __shared__ double Fd[MAXNB * 16 * 17];   // diagonal blocks of F = Phi(G - I)
+  __shared__ int ok_s;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // ||G - I||_F^2 from the upper triangle (off-diagonal entries twice): wave
+  // w takes rows w, w + NW, ..., lanes run along the row; then waves in order
+  double s = 0.0;
+  for (int i = wave; i < l; i += NW) {
+    const double* gr = G + (int64_t)i * ldg;
+    for (int j = i + lane; j < l; j += 64) {
+      const double x = gr[j] - (i == j ? 1.0 : 0.0);
+      s = fma((i == j ? 1.0 : 2.0) * x, x, s);
+    }
+  }
+  s = wave_allsum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    const int ok = (t <= NI_TAU2) ? 1 : 0;     // false for NaN
+    ok_s = ok;
+    *done = ok;
+  }
+  __syncthreads();
+  if (!ok_s) return;
+  // R = I + Phi(G - I), zero below the diagonal, identity in the padding;
+  // the diagonal blocks of F go to LDS on the way
+  for (int i = wave; i < lp; i += NW) {
+    const double* gr = G + (int64_t)i * ldg;
+    double* rr = R + (int64_t)i * ldr;
+    for (int j = lane; j < lp; j += 64) {
+      double f = 0.0;
+      if (i < l && j < l && i <= j) f = (i == j) ? 0.5 * (gr[j] - 1.0) : gr[j];
+      rr[j] = (i == j ? 1.0 : 0.0) + f;
+      if ((i >> 4) == (j >> 4)) Fd[(i >> 4) * 272 + (i & 15) * 17 + (j & 15)] = f;
+    }
+  }
+  for (int j = tid; j < l; j += NI_NT) dep[j] = 0;
+  __syncthreads();
+  // inverses of the diagonal blocks: I - F_bb + F_bb^2
+  const int nb = lp / 16;
+  for (int e = tid; e < nb * 256; e += NI_NT) {
+    const int b = e >> 8, x = (e >> 4) & 15, y = e & 15;
+    const double* fb = Fd + b * 272;
+    double f2 = 0.0;
+    for (int t = x; t <= y; ++t) f2 = fma(fb[x * 17 + t], fb[t * 17 + y], f2);
+    Rdinv[(int64_t)b * 256 + x * 16 + y] = ((x == y) ? 1.0 : 0.0) - fb[x * 17 + y] + f2;
+  }
+}
+
+// Q = Y R^{-1}: one wave per 16 rows of Y, column block by column block, in
+// transposed form Q_c^T = R_cc^{-T} (Y_c^T - sum_{b<c} R_bc^T Q_b^T).  The
+// accumulator layout of a 16x16 product (lane (j, g) holds rows 4v + g of
+// column j) is also the B-operand layout of the next products, so every
+// Q_b^T stays in registers (4 doubles per lane) from the step that makes it
+// to the last column block, and the wave needs no LDS and no barrier.
+// R_bc^T and R_cc^{-T} are read as A operands straight from memory (L2).
+template <typename TY, typename TQ, int NB>
 __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int64_t ldy,
                                                    int64_t M, int l, int lp,
                                                    const double* __restrict__ R, int64_t ldr,
                                                    const double* __restrict__ Rdinv,
                                                    TQ* __restrict__ Q, int64_t ldq) {
-  __shared__ double Qs[4][16 * 257];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   if (row0 >= M) return;
-  double* qs = Qs[wave];
   const int nb = lp / 16;
-  for (int c = 0; c < nb; ++c) {
-    d4 acc;
+  const int64_t r = row0 + li;
+  const bool rok = r < M;
+  const TY* yr = Y + (rok ? r : 0) * ldy;
+  TQ* qr = Q + (rok ? r : 0) * ldq;
+  d4 qt[NB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = row0 + drow(lk, v);
-      const int col = c * 16 + li;
-      acc[v] = (r < M && col < l) ? (double)Y[r * ldy + col] : 0.0;
-    }
-    for (int b = 0; b < c; ++b) {
+  for (int c = 0; c < NB; ++c) {
+    if (c < nb) {
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = c * 16 + 4 * v + lk;
+        acc[v] = (rok && col < l) ? (double)yr[col] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < c; ++b) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double av = -R[(int64_t)(b * 16 + 4 * kk + lk) * ldr + c * 16 + li];  // R_bc[k][i]
+          acc = Mfma<double>::mma(av, qt[b][kk], acc);
+        }
+      }
+      d4 out = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int k = 4 * kk + lk;
-        const double av = -qs[li * 257 + b * 16 + k];                       // Q_b[li][k]
-        const double bv = R[(int64_t)(b * 16 + k) * ldr + c * 16 + li];     // R_bc[k][li]
-        acc = Mfma<double>::mma(av, bv, acc);
+        const double av = Rdinv[(int64_t)c * 256 + (4 * kk + lk) * 16 + li];  // Rinv_cc[k][i]
+        out = Mfma<double>::mma(av, acc[kk], out);
+      }
+      qt[c] = out;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = c * 16 + 4 * v + lk;
+        if (rok && col < l) qr[col] = (TQ)out[v];
       }
     }
-    // stage (Y_c - ...) to LDS, then multiply by Rinv_cc
-#pragma unroll
-    for (int v = 0; v < 4; ++v) qs[drow(lk, v) * 257 + c * 16 + li] = acc[v];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    d4 out = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kk + lk;
-      const double av = qs[li * 257 + c * 16 + k];
-      const double bv = Rdinv[(int64_t)c * 256 + k * 16 + li];
-      out = Mfma<double>::mma(av, bv, out);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int rr = drow(lk, v);
-      qs[rr * 257 + c * 16 + li] = out[v];
-      const int64_t r = row0 + rr;
-      const int col = c * 16 + li;
-      if (r < M && col < l) Q[r * ldq + col] = (TQ)out[v];
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
 }
 
@@ -343,156 +412,207 @@ __global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am
 __global__ void set_word_kernel(int32_t* w, int32_t v) { *w = v; }
 
 // Gram matrix G = Y^T Y (FP64) of a tall Y (rows x l), upper 16x16 tiles only.
-// Workgroup w reduces rows [w*rows/G, (w+1)*rows/G): 16-row chunks of Y are
-// staged in LDS (double-buffered, coalesced row loads) and each wave
-// accumulates its share of the upper tiles on the matrix cores; the partial
-// tiles go to part[w], and gram_reduce_kernel adds the G partials in
-// workgroup order (deterministic).
+// The column blocks are cut into segments of 4; a tile group is a pair of
+// segments (sa <= sb) and holds the at most 16 upper tiles between them, so a
+// workgroup of the group needs only the <= 128 columns of its two segments.
+// Each group owns a number of workgroups proportional to its tiles per wave
+// (1 or 2), and workgroup j of the group reduces the j-th of that many equal
+// row ranges.  16-row chunks of the group's columns are staged in LDS (row
+// stride 144 doubles, so the four row groups of a wave fall on different bank
+// halves), the next chunk is fetched into registers while the current one is
+// multiplied, and each tile accumulates on one wave's matrix cores.  Partial
+// tiles go to part[workgroup][slot]; gram_reduce_kernel adds a tile's
+// partials in workgroup order (deterministic).
 constexpr int GR_NT = 512;
 constexpr int GR_NW = GR_NT / 64;
+constexpr int GR_SEG = 4;                   // column blocks per segment
+constexpr int GR_MAXSEG = MAXNB / GR_SEG;   // 4
+constexpr int GR_MAXG = GR_MAXSEG * (GR_MAXSEG + 1) / 2;
+constexpr int GR_LDS = 144;                 // LDS row stride (doubles)
 
-template <typename TY, int TPW>
+struct GramPlan {
+  int nb, nseg, ngroups, total;
+  int sa[GR_MAXG], sb[GR_MAXG];
+  int off[GR_MAXG + 1];                     // first workgroup of each group
+};
+
+template <typename TY>
 __global__ __launch_bounds__(GR_NT) void gram_kernel(const TY* __restrict__ Y, int64_t ldy,
-                                                     int64_t rows, int l, int lp,
-                                                     double* __restrict__ part, int G) {
-  __shared__ double Ys[2][16 * 256];
+                                                     int64_t rows, int l, GramPlan gp,
+                                                     double* __restrict__ part) {
+  __shared__ double Ys[2][16 * GR_LDS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int nb = lp / 16;
-  const int ntiles = nb * (nb + 1) / 2;
-  const int64_t w = blockIdx.x;
-  const int64_t r0 = (w * rows) / G, r1 = ((w + 1) * rows) / G;
-  d4 acc[TPW];
+  const int x = blockIdx.x;
+  int g = 0;
+  while (g + 1 < gp.ngroups && gp.off[g + 1] <= x) ++g;
+  const int sa = gp.sa[g], sb = gp.sb[g];
+  const int ng = gp.off[g + 1] - gp.off[g], j = x - gp.off[g];
+  const int64_t r0 = ((int64_t)j * rows) / ng, r1 = ((int64_t)(j + 1) * rows) / ng;
+  const bool diag = sa == sb;
+  const int ncol = diag ? 64 : 128;
+  const int sh = diag ? 6 : 7;
+  // the (up to) two tiles of this wave: slot u = 4 * (ta - 4 sa) + (tb - 4 sb)
+  bool tv[2];
+  int ca[2], cb[2];
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 2; ++q) {
+    const int u = wave + GR_NW * q;
+    const int ta = GR_SEG * sa + (u >> 2), tb = GR_SEG * sb + (u & 3);
+    tv[q] = ta < gp.nb && tb < gp.nb && ta <= tb;
+    ca[q] = (u >> 2) * 16;
+    cb[q] = (diag ? 0 : 64) + (u & 3) * 16;
+  }
+  d4 acc[2];
+  acc[0] = d4{0.0, 0.0, 0.0, 0.0};
+  acc[1] = d4{0.0, 0.0, 0.0, 0.0};
   const int nch = (int)cdiv(r1 - r0, 16);
-  auto load = [&](int ch, int buf) {
+  double pre[4];
+  auto fetch = [&](int ch) {
     const int64_t base = r0 + (int64_t)ch * 16;
-    for (int e = tid; e < 16 * lp; e += GR_NT) {
-      const int k = e / lp, c = e - (e / lp) * lp;
-      const int64_t r = base + k;
-      Ys[buf][k * 256 + c] = (r < r1 && c < l) ? (double)Y[r * ldy + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + GR_NT * i;
+      const int rr = e >> sh, cc = e & (ncol - 1);
+      const int gcol = (cc < 64) ? sa * 64 + cc : sb * 64 + (cc - 64);
+      const int64_t r = base + rr;
+      pre[i] = (e < 16 * ncol && r < r1 && gcol < l) ? (double)Y[r * ldy + gcol] : 0.0;
     }
   };
-  if (nch > 0) load(0, 0);
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + GR_NT * i;
+      if (e < 16 * ncol) Ys[buf][(e >> sh) * GR_LDS + (e & (ncol - 1))] = pre[i];
+    }
+  };
+  if (nch > 0) {
+    fetch(0);
+    stash(0);
+  }
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nch) load(ch + 1, buf ^ 1);
+    if (ch + 1 < nch) fetch(ch + 1);
+    const double* ys = Ys[buf];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      const int t = wave + GR_NW * q;
-      if (t < ntiles) {
-        const int a = tile_row(t, nb), b = tile_col(t, nb);
+    for (int q = 0; q < 2; ++q) {
+      if (tv[q]) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + lk;
-          acc[q] = Mfma<double>::mma(Ys[buf][k * 256 + a * 16 + li], Ys[buf][k * 256 + b * 16 + li],
+          acc[q] = Mfma<double>::mma(ys[k * GR_LDS + ca[q] + li], ys[k * GR_LDS + cb[q] + li],
                                      acc[q]);
         }
       }
     }
+    if (ch + 1 < nch) stash(buf ^ 1);
     __syncthreads();
   }
-  double* P = part + w * (int64_t)ntiles * 256;
+  double* P = part + (int64_t)x * 16 * 256;
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int t = wave + GR_NW * q;
-    if (t < ntiles) {
+  for (int q = 0; q < 2; ++q) {
+    if (tv[q]) {
+      const int u = wave + GR_NW * q;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) P[(int64_t)t * 256 + drow(lk, v) * 16 + li] = acc[q][v];
+      for (int v = 0; v < 4; ++v) P[u * 256 + drow(lk, v) * 16 + li] = acc[q][v];
     }
   }
 }
 
-// Stage 1: block (x, y) sums partials y*GR_SPLIT .. of 256 elements;
-// stage 2 adds the GR_SPLIT sums in order.  Both orders are fixed.
-constexpr int GR_SPLIT = 16;
-
-__global__ __launch_bounds__(256) void gram_reduce1_kernel(const double* __restrict__ part, int G,
-                                                           int ntiles, double* __restrict__ mid) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)ntiles * 256;
-  if (e >= total) return;
-  const int w0 = (int)(((int64_t)blockIdx.y * G) / GR_SPLIT);
-  const int w1 = (int)(((int64_t)(blockIdx.y + 1) * G) / GR_SPLIT);
-  double s = 0.0;
-  for (int w = w0; w < w1; ++w) s += part[(int64_t)w * total + e];
-  mid[(int64_t)blockIdx.y * total + e] = s;
+// G_ab = sum over the workgroups of the group of (a, b) of their partial
+// tile, in workgroup order (four interleaved chains added in a fixed order).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part,
+                                                          GramPlan gp, double* __restrict__ Gm,
+                                                          int64_t ldg) {
+  const int t = blockIdx.x, e = threadIdx.x;
+  const int a = tile_row(t, gp.nb), b = tile_col(t, gp.nb);
+  const int sa = a / GR_SEG, sb = b / GR_SEG;
+  const int g = sa * gp.nseg - sa * (sa - 1) / 2 + (sb - sa);
+  const int u = 4 * (a - GR_SEG * sa) + (b - GR_SEG * sb);
+  const int w0 = gp.off[g], ng = gp.off[g + 1] - w0;
+  const double* p = part + ((int64_t)w0 * 16 + u) * 256 + e;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int w = 0;
+  for (; w + 4 <= ng; w += 4) {
+    s0 += p[(int64_t)(w + 0) * 4096];
+    s1 += p[(int64_t)(w + 1) * 4096];
+    s2 += p[(int64_t)(w + 2) * 4096];
+    s3 += p[(int64_t)(w + 3) * 4096];
+  }
+  for (; w < ng; ++w) s0 += p[(int64_t)w * 4096];
+  Gm[(int64_t)(a * 16 + (e >> 4)) * ldg + b * 16 + (e & 15)] = (s0 + s1) + (s2 + s3);
 }
 
-__global__ __launch_bounds__(256) void gram_reduce2_kernel(const double* __restrict__ mid, int lp,
-                                                           double* __restrict__ Gm, int64_t ldg) {
-  const int nb = lp / 16;
-  const int ntiles = nb * (nb + 1) / 2;
-  const int64_t total = (int64_t)ntiles * 256;
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  double s = 0.0;
-  for (int y = 0; y < GR_SPLIT; ++y) s += mid[(int64_t)y * total + e];
-  const int t = (int)(e >> 8), ij = (int)(e & 255);
-  const int a = tile_row(t, nb), b = tile_col(t, nb);
-  Gm[(int64_t)(a * 16 + (ij >> 4)) * ldg + b * 16 + (ij & 15)] = s;
+GramPlan plan_gram(int64_t rows, int lp, int ncu) {
+  GramPlan gp;
+  gp.nb = lp / 16;
+  gp.nseg = (int)cdiv(gp.nb, GR_SEG);
+  gp.ngroups = 0;
+  int wsum = 0;
+  int wt[GR_MAXG];
+  for (int sa = 0; sa < gp.nseg; ++sa)
+    for (int sb = sa; sb < gp.nseg; ++sb) {
+      const int na = std::min(GR_SEG, gp.nb - GR_SEG * sa);
+      const int nbb = std::min(GR_SEG, gp.nb - GR_SEG * sb);
+      const int tiles = (sa == sb) ? na * (na + 1) / 2 : na * nbb;
+      gp.sa[gp.ngroups] = sa;
+      gp.sb[gp.ngroups] = sb;
+      wt[gp.ngroups] = (int)cdiv(tiles, GR_NW);   // tiles per wave: 1 or 2
+      wsum += wt[gp.ngroups];
+      ++gp.ngroups;
+    }
+  // about two workgroups per CU in all, at least 64 rows per workgroup
+  const int64_t budget = 2 * (int64_t)ncu;
+  int64_t unit = budget / wsum;
+  const int64_t maxunit = std::max<int64_t>(1, rows / (64 * 2));
+  unit = std::max<int64_t>(1, std::min(unit, maxunit));
+  gp.off[0] = 0;
+  for (int g = 0; g < gp.ngroups; ++g) gp.off[g + 1] = gp.off[g] + (int)(unit * wt[g]);
+  gp.total = gp.off[gp.ngroups];
+  return gp;
 }
 
 }  // namespace
 
-int gram_groups(int64_t rows, int ncu) {
-  int64_t G = cdiv(rows, 48);
-  if (G > ncu) G = ncu;
-  if (G < 1) G = 1;
-  return (int)G;
-}
-
-size_t gram_part_bytes(int lp, int G) {
-  const int nb = lp / 16;
-  return (size_t)(G + GR_SPLIT) * (size_t)(nb * (nb + 1) / 2) * 256 * sizeof(double);
+size_t gram_part_bytes(int lp, int ncu) {
+  (void)lp;
+  return (size_t)2 * ncu * 16 * 256 * sizeof(double);
 }
 
 hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
-                       double* Gm, int64_t ldg, double* part, int G, hipStream_t s) {
+                       double* Gm, int64_t ldg, double* part, int ncu, hipStream_t s) {
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
-  const int nb = lp / 16;
-  const int ntiles = nb * (nb + 1) / 2;
-  const int tpw = (int)cdiv(ntiles, GR_NW);
-#define RSVD_GRAM(T)                                                                           \
-  do {                                                                                         \
-    if (y_f32)                                                                                 \
-      hipLaunchKernelGGL((gram_kernel<float, T>), dim3(G), dim3(GR_NT), 0, s, (const float*)Y, \
-                         ldy, rows, l, lp, part, G);                                           \
-    else                                                                                       \
-      hipLaunchKernelGGL((gram_kernel<double, T>), dim3(G), dim3(GR_NT), 0, s,                 \
-                         (const double*)Y, ldy, rows, l, lp, part, G);                         \
-  } while (0)
-  if (tpw <= 1) RSVD_GRAM(1);
-  else if (tpw <= 2) RSVD_GRAM(2);
-  else if (tpw <= 4) RSVD_GRAM(4);
-  else if (tpw <= 7) RSVD_GRAM(7);
-  else if (tpw <= 10) RSVD_GRAM(10);
-  else if (tpw <= 14) RSVD_GRAM(14);
-  else RSVD_GRAM(17);
-#undef RSVD_GRAM
+  const GramPlan gp = plan_gram(rows, lp, ncu);
+  if (y_f32)
+    hipLaunchKernelGGL(gram_kernel<float>, dim3(gp.total), dim3(GR_NT), 0, s, (const float*)Y,
+                       ldy, rows, l, gp, part);
+  else
+    hipLaunchKernelGGL(gram_kernel<double>, dim3(gp.total), dim3(GR_NT), 0, s, (const double*)Y,
+                       ldy, rows, l, gp, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned nblk = (unsigned)cdiv((int64_t)ntiles * 256, 256);
-  double* mid = part + (int64_t)G * ntiles * 256;
-  hipLaunchKernelGGL(gram_reduce1_kernel, dim3(nblk, GR_SPLIT), dim3(256), 0, s, part, G, ntiles,
-                     mid);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_reduce2_kernel, dim3(nblk), dim3(256), 0, s, mid, lp, Gm, ldg);
+  const int ntiles = gp.nb * (gp.nb + 1) / 2;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(ntiles), dim3(256), 0, s, part, gp, Gm, ldg);
   return hipGetLastError();
 }
 
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
-                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s) {
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s,
+                       int32_t* near_identity) {
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
   const int nb = lp / 16;
   const int tpw = (int)cdiv(nb * (nb + 1) / 2, CH_NW);
+  if (near_identity != nullptr) {
+    hipLaunchKernelGGL(chol_ni_kernel, dim3(1), dim3(NI_NT), 0, s, G, ldg, l, lp, R, ldr, Rdinv,
+                       dep, near_identity);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
 #define RSVD_CHOL(T)                                                                          \
   hipLaunchKernelGGL(chol_kernel<T>, dim3(1), dim3(CH_NT), 0, s, G, ldg, l, lp, eta, R, ldr, \
-                     Rdinv, dep, info)
+                     Rdinv, dep, info, near_identity)
   if (tpw <= 1) RSVD_CHOL(1);
   else if (tpw <= 2) RSVD_CHOL(2);
   else if (tpw <= 4) RSVD_CHOL(4);
@@ -504,24 +624,38 @@ hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, 
   return hipGetLastError();
 }
 
+template <int NB>
+hipError_t launch_trsm_nb(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
+                          int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
+                          int64_t ldq, hipStream_t s) {
+  const dim3 grid((unsigned)cdiv(M, 64));
+  if (!y_f32 && !q_f32)
+    hipLaunchKernelGGL((trsm_kernel<double, double, NB>), grid, dim3(256), 0, s,
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
+  else if (y_f32 && q_f32)
+    hipLaunchKernelGGL((trsm_kernel<float, float, NB>), grid, dim3(256), 0, s,
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
+  else if (y_f32 && !q_f32)
+    hipLaunchKernelGGL((trsm_kernel<float, double, NB>), grid, dim3(256), 0, s,
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
+  else
+    hipLaunchKernelGGL((trsm_kernel<double, float, NB>), grid, dim3(256), 0, s,
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
+  return hipGetLastError();
+}
+
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
                        int64_t ldq, hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  const dim3 grid((unsigned)cdiv(M, 64));
-  if (!y_f32 && !q_f32)
-    hipLaunchKernelGGL((trsm_kernel<double, double>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
-  else if (y_f32 && q_f32)
-    hipLaunchKernelGGL((trsm_kernel<float, float>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
-  else if (y_f32 && !q_f32)
-    hipLaunchKernelGGL((trsm_kernel<float, double>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
-  else
-    hipLaunchKernelGGL((trsm_kernel<double, float>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
-  return hipGetLastError();
+  if (lp > 256 || lp % 16) return hipErrorInvalidValue;
+  const int nb = lp / 16;
+  if (nb <= 2) return launch_trsm_nb<2>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+  if (nb <= 4) return launch_trsm_nb<4>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+  if (nb <= 8) return launch_trsm_nb<8>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+  if (nb <= 12)
+    return launch_trsm_nb<12>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+  return launch_trsm_nb<16>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
 }
 
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,

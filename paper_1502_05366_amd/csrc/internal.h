@@ -61,15 +61,20 @@ namespace rsvd {
 // One Cholesky factorization of an lp x lp Gram matrix (lp <= 256, lp % 16 == 0,
 // only rows/columns < l are read).  R upper triangular (zero below), Rdinv the
 // inverses of its 16x16 diagonal blocks (lp/16 blocks of 256 doubles), dep[j]
-// = 1 for columns declared dependent (pivot <= eta * G_jj).
+// = 1 for columns declared dependent (pivot <= eta * G_jj).  With
+// near_identity (one device int), G is first tested for ||G - I||_F^2 below a
+// quarter of the unit roundoff; if it passes, R = I + Phi(G - I) is written by
+// a one-workgroup kernel, *near_identity = 1 and the full factorization
+// returns at once; otherwise *near_identity = 0 and G is factored.
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
-                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s);
-// G = Y^T Y (upper 16x16 tiles of an lp x lp matrix) in FP64 for a tall Y;
-// `part` holds gram_part_bytes(lp, G) bytes, G = gram_groups(rows, ncu).
-int gram_groups(int64_t rows, int ncu);
-size_t gram_part_bytes(int lp, int G);
+                       int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s,
+                       int32_t* near_identity = nullptr);
+// G = Y^T Y (upper 16x16 tiles of an lp x lp matrix) in FP64 for a tall Y,
+// sized for ncu compute units; `part` holds gram_part_bytes(lp, ncu_cap)
+// bytes for any ncu <= ncu_cap.
+size_t gram_part_bytes(int lp, int ncu_cap);
 hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
-                       double* Gm, int64_t ldg, double* part, int G, hipStream_t s);
+                       double* Gm, int64_t ldg, double* part, int ncu, hipStream_t s);
 // Q = Y R^{-1} (M x l); Y and Q may be FP32 or FP64; arithmetic in FP64.
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,

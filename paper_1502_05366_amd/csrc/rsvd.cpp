@@ -78,11 +78,13 @@ Shape make_shape(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) 
 
 // buffers of one orth (CholeskyQR2) call
 struct OrthBufs {
-  double *G, *R1, *R2, *Rd1, *Rd2, *Qa;
-  int32_t *dep, *dep2;
-  void* part;
-  size_t part_bytes;
-  double* gpart;          // partial Gram tiles, gram_part_bytes(lp, NCU_CAP)
+  double *G = nullptr, *R1 = nullptr, *R2 = nullptr, *Rd1 = nullptr, *Rd2 = nullptr,
+         *Qa = nullptr;
+  int32_t *dep = nullptr, *dep2 = nullptr;
+  int32_t* ni = nullptr;  // one int: the second Gram matrix passed the near-identity test
+  void* part = nullptr;
+  size_t part_bytes = 0;
+  double* gpart = nullptr;  // partial Gram tiles, gram_part_bytes(lp, NCU_CAP)
 };
 
 struct Bufs {
@@ -131,6 +133,7 @@ OrthBufs take_orth(Arena& a, int64_t rows, int lp, size_t part_bytes) {
   ob.Qa = a.take<double>((size_t)rows * lp);
   ob.dep = a.take<int32_t>(lp);
   ob.dep2 = a.take<int32_t>(lp);
+  ob.ni = a.take<int32_t>(1);
   ob.part_bytes = part_bytes;
   ob.part = a.take<char>(part_bytes);
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
@@ -209,7 +212,7 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
                 int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
                 int64_t ldr) {
   const int lp = (int)rup(l, 16);
-  const int gG = gram_groups(rows, std::min(c.ncu, NCU_CAP));
+  const int gG = std::min(c.ncu, NCU_CAP);
   // pass 1: G = Y^T Y, G = R1^T R1, Qa = Y R1^{-1}, dependent columns replaced
   RSVD_TRY(launch_gram(y_f32, Y, ldy, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, c.st));
@@ -217,7 +220,8 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
   RSVD_TRY(launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st));
   // pass 2 on Qa
   RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
-  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st));
+  RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st,
+                       ob.ni));
   RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st));
   if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, ob.dep, Rout, ldr, lp, c.st));
   return hipSuccess;
@@ -632,7 +636,7 @@ size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {
   Arena a(nullptr);
   a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
   a.take<double>((size_t)rows * lp);
-  a.take<int32_t>(2 * (size_t)lp);
+  a.take<int32_t>(2 * (size_t)lp + 1);
   a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
   return a.off;
 }
@@ -665,8 +669,9 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   ob.Rd1 = blk + 4 * (size_t)lp * lp;
   ob.Rd2 = ob.Rd1 + (size_t)lp * 16;
   ob.Qa = a.take<double>((size_t)rows * lp);
-  ob.dep = a.take<int32_t>(2 * (size_t)lp);
+  ob.dep = a.take<int32_t>(2 * (size_t)lp + 1);
   ob.dep2 = ob.dep + lp;
+  ob.ni = ob.dep + 2 * (size_t)lp;
   ob.part = nullptr;
   ob.part_bytes = 0;
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));

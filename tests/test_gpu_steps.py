@@ -92,7 +92,8 @@ def test_pass_random_vs_oracle(R, m, n, l):
 
 # ---------------------------------------------------------------- orth ----
 
-@pytest.mark.parametrize("rows,l,decay", [(1000, 30, 3), (20000, 220, 2), (50, 50, 1), (333, 17, 0)])
+@pytest.mark.parametrize("rows,l,decay", [(1000, 30, 3), (20000, 220, 2), (50, 50, 1), (333, 17, 0),
+                                          (2000, 64, 5), (3000, 100, 6)])
 def test_orth_cholqr2(R, rows, l, decay):
     g = np.random.default_rng(rows + l)
     Y = g.standard_normal((rows, l)) @ np.diag(np.logspace(0, -decay, l)) @ \
