@@ -17,9 +17,10 @@
 //    Phi taking the strict upper triangle and half the diagonal, so
 //    F = Phi(E) + O(||E||^2) and R^{-1} = I - F + O(||F||^2).  When
 //    ||E||_F^2 <= NI_TAU2 (a quarter of the unit roundoff) both truncations
-//    sit below rounding: the kernel writes R = I + Phi(E) with the inverses
-//    of its diagonal blocks and sets a flag that makes chol_kernel return at
-//    once; otherwise chol_kernel factors G as in the first pass.
+//    sit below rounding.  The kernel writes R = I + Phi(E) with the inverses
+//    of its diagonal blocks and the parts of ||E||_F^2; chol_kernel adds the
+//    parts and returns at once when the test passes, and otherwise factors G
+//    as in the first pass, overwriting R.
 //  * trsm_kernel: Q = Y R^{-1} for a tall Y, one wave per 16 rows, column
 //    block by column block (Q_c = (Y_c - sum_{b<c} Q_b R_bc) R_cc^{-1}).
 //  * replace_kernel: overwrites flagged columns of Q with fresh Gaussian
@@ -31,6 +32,8 @@
 namespace rsvd {
 namespace {
 
+constexpr int NI_NT = 256;
+constexpr double NI_TAU2 = 2.5e-17;   // bound on ||G - I||_F^2 (about a quarter of 2^-52)
 constexpr int CH_NT = 512;
 constexpr int CH_NW = CH_NT / 64;  // waves
 constexpr int MAXNB = 16;          // lp <= 256
@@ -76,9 +79,15 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
                                                      double* __restrict__ R, int64_t ldr,
                                                      double* __restrict__ Rdinv,
                                                      int32_t* __restrict__ dep, int32_t* info,
-                                                     const int32_t* __restrict__ skip) {
-  if (skip != nullptr && __builtin_amdgcn_readfirstlane(*skip) != 0) return;
+                                                     const double* __restrict__ ni_part) {
   const int nb = lp / 16;
+  if (ni_part != nullptr) {
+    // the near-identity test: the blocks' parts of ||G - I||_F^2, added in a
+    // fixed order by every wave (each lane holds at most one part)
+    const int ln = threadIdx.x & 63;
+    const double e2 = wave_allsum(ln < nb ? ni_part[ln] : 0.0);
+    if (e2 <= NI_TAU2) return;   // false for NaN
+  }
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -238,64 +247,56 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
   }
 }
 
-constexpr int NI_NT = 1024;
-constexpr double NI_TAU2 = 2.5e-17;   // bound on ||G - I||_F^2 (~ u / 4, u = 2^-53 ... 2^-52)
 
+// Workgroup c takes rows 16c .. 16c+15: it writes those rows of R = I + Phi(G - I)
+// (zero below the diagonal, identity in the padding), the inverse
+// I - F_cc + F_cc^2 of the diagonal block, clear flags for those columns, and
+// its part of ||G - I||_F^2 (upper triangle, off-diagonal entries twice) to
+// part[c].  The writes are speculative: chol_kernel adds the parts in order
+// and, when the sum exceeds NI_TAU2, overwrites all of them.
 __global__ __launch_bounds__(NI_NT) void chol_ni_kernel(const double* __restrict__ G, int64_t ldg,
                                                         int l, int lp, double* __restrict__ R,
                                                         int64_t ldr, double* __restrict__ Rdinv,
                                                         int32_t* __restrict__ dep,
-                                                        int32_t* __restrict__ done) {
+                                                        double* __restrict__ part) {
   constexpr int NW = NI_NT / 64;
   __shared__ double red[NW];
-  __shared__ double Fd[MAXNB * 16 * 17];   // diagonal blocks of F = Phi(G - I)
-  __shared__ int ok_s;
+  __shared__ double Fd[16 * 17];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // ||G - I||_F^2 from the upper triangle (off-diagonal entries twice): wave
-  // w takes rows w, w + NW, ..., lanes run along the row; then waves in order
+  const int c = blockIdx.x;
   double s = 0.0;
-  for (int i = wave; i < l; i += NW) {
-    const double* gr = G + (int64_t)i * ldg;
-    for (int j = i + lane; j < l; j += 64) {
-      const double x = gr[j] - (i == j ? 1.0 : 0.0);
-      s = fma((i == j ? 1.0 : 2.0) * x, x, s);
-    }
-  }
-  s = wave_allsum(s);
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < NW; ++w) t += red[w];
-    const int ok = (t <= NI_TAU2) ? 1 : 0;     // false for NaN
-    ok_s = ok;
-    *done = ok;
-  }
-  __syncthreads();
-  if (!ok_s) return;
-  // R = I + Phi(G - I), zero below the diagonal, identity in the padding;
-  // the diagonal blocks of F go to LDS on the way
-  for (int i = wave; i < lp; i += NW) {
+  // wave w takes rows 16c + w, 16c + w + NW, ...; lanes run along the row
+  for (int ii = wave; ii < 16; ii += NW) {
+    const int i = c * 16 + ii;
     const double* gr = G + (int64_t)i * ldg;
     double* rr = R + (int64_t)i * ldr;
     for (int j = lane; j < lp; j += 64) {
       double f = 0.0;
-      if (i < l && j < l && i <= j) f = (i == j) ? 0.5 * (gr[j] - 1.0) : gr[j];
+      if (i < l && j < l && i <= j) {
+        const double x = gr[j] - (i == j ? 1.0 : 0.0);
+        s = fma((i == j ? 1.0 : 2.0) * x, x, s);
+        f = (i == j) ? 0.5 * x : x;
+      }
       rr[j] = (i == j ? 1.0 : 0.0) + f;
-      if ((i >> 4) == (j >> 4)) Fd[(i >> 4) * 272 + (i & 15) * 17 + (j & 15)] = f;
+      if ((j >> 4) == c) Fd[ii * 17 + (j & 15)] = f;
     }
   }
-  for (int j = tid; j < l; j += NI_NT) dep[j] = 0;
+  s = wave_allsum(s);
+  if (lane == 0) red[wave] = s;
+  if (tid < 16 && c * 16 + tid < l) dep[c * 16 + tid] = 0;
   __syncthreads();
-  // inverses of the diagonal blocks: I - F_bb + F_bb^2
-  const int nb = lp / 16;
-  for (int e = tid; e < nb * 256; e += NI_NT) {
-    const int b = e >> 8, x = (e >> 4) & 15, y = e & 15;
-    const double* fb = Fd + b * 272;
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    part[c] = t;
+  }
+  // inverse of the diagonal block: I - F_cc + F_cc^2
+  {
+    const int x = tid >> 4, y = tid & 15;
     double f2 = 0.0;
-    for (int t = x; t <= y; ++t) f2 = fma(fb[x * 17 + t], fb[t * 17 + y], f2);
-    Rdinv[(int64_t)b * 256 + x * 16 + y] = ((x == y) ? 1.0 : 0.0) - fb[x * 17 + y] + f2;
+    for (int t = x; t <= y; ++t) f2 = fma(Fd[x * 17 + t], Fd[t * 17 + y], f2);
+    Rdinv[(int64_t)c * 256 + x * 16 + y] = ((x == y) ? 1.0 : 0.0) - Fd[x * 17 + y] + f2;
   }
 }
 
@@ -380,9 +381,19 @@ template <typename TQ>
 __global__ __launch_bounds__(256) void replace_kernel(TQ* __restrict__ Q, int64_t ldq, int64_t M,
                                                       int l, const int32_t* __restrict__ dep,
                                                       uint64_t seed, uint32_t call) {
+  // the flagged columns, listed once per workgroup (usually none)
+  __shared__ int list[256];
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < l; j += blockDim.x)
+    if (dep[j]) list[atomicAdd(&cnt, 1)] = j;
+  __syncthreads();
+  const int nd = cnt;
+  if (nd == 0) return;
   const double scale = 1.0 / sqrt((double)M);
-  for (int j = 0; j < l; ++j) {
-    if (!dep[j]) continue;
+  for (int q = 0; q < nd; ++q) {
+    const int j = list[q];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
       const double z = normal_at((uint32_t)seed, (uint32_t)(seed >> 32), 7u, call,
@@ -392,21 +403,35 @@ __global__ __launch_bounds__(256) void replace_kernel(TQ* __restrict__ Q, int64_
   }
 }
 
-// C = A B for upper-triangular lp x lp A, B (C upper triangular, zero below).
-// C = A B for upper-triangular A, B; rows k of B with bdep[k] != 0 count as
-// zero (the unit rows that the Cholesky gives dependent columns stand for a
-// zero residual, so the product is the R of Y = Q R).
+// C = A B for upper-triangular lp x lp A, B (C upper triangular, zero below);
+// rows k of B with bdep[k] != 0 count as zero (the unit rows that the
+// Cholesky gives dependent columns stand for a zero residual, so the product
+// is the R of Y = Q R).  One wave per 16 x 16 tile of C, on the matrix cores.
 __global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am, int64_t lda,
                                                    const double* __restrict__ Bm, int64_t ldb,
                                                    const int32_t* __restrict__ bdep,
                                                    double* __restrict__ C, int64_t ldc, int lp) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)lp * lp) return;
-  const int i = (int)(e / lp), j = (int)(e % lp);
-  double s = 0.0;
-  for (int k = i; k <= j; ++k)
-    if (!bdep || bdep[k] == 0) s += Am[(int64_t)i * lda + k] * Bm[(int64_t)k * ldb + j];
-  C[(int64_t)i * ldc + j] = (i <= j) ? s : 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nb = lp / 16;
+  const int t = blockIdx.x * 4 + wave;
+  if (t >= nb * nb) return;
+  const int a = t / nb, b = t - (t / nb) * nb;
+  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = a; q <= b; ++q) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kx = q * 16 + 4 * kk + lk;
+      const double av = Am[(int64_t)(a * 16 + li) * lda + kx];
+      const double bv = (bdep != nullptr && bdep[kx] != 0) ? 0.0 : Bm[(int64_t)kx * ldb + b * 16 + li];
+      acc = Mfma<double>::mma(av, bv, acc);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = a * 16 + drow(lk, v), col = b * 16 + li;
+    C[(int64_t)row * ldc + col] = (row <= col) ? acc[v] : 0.0;
+  }
 }
 
 __global__ void set_word_kernel(int32_t* w, int32_t v) { *w = v; }
@@ -600,19 +625,19 @@ hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int
 
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
                        int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s,
-                       int32_t* near_identity) {
+                       double* ni_part) {
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
   const int nb = lp / 16;
   const int tpw = (int)cdiv(nb * (nb + 1) / 2, CH_NW);
-  if (near_identity != nullptr) {
-    hipLaunchKernelGGL(chol_ni_kernel, dim3(1), dim3(NI_NT), 0, s, G, ldg, l, lp, R, ldr, Rdinv,
-                       dep, near_identity);
+  if (ni_part != nullptr) {
+    hipLaunchKernelGGL(chol_ni_kernel, dim3(nb), dim3(NI_NT), 0, s, G, ldg, l, lp, R, ldr, Rdinv,
+                       dep, ni_part);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 #define RSVD_CHOL(T)                                                                          \
   hipLaunchKernelGGL(chol_kernel<T>, dim3(1), dim3(CH_NT), 0, s, G, ldg, l, lp, eta, R, ldr, \
-                     Rdinv, dep, info, near_identity)
+                     Rdinv, dep, info, ni_part)
   if (tpw <= 1) RSVD_CHOL(1);
   else if (tpw <= 2) RSVD_CHOL(2);
   else if (tpw <= 4) RSVD_CHOL(4);
@@ -660,6 +685,7 @@ hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64
 
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
                           uint64_t seed, uint32_t call, hipStream_t s) {
+  if (l > 256) return hipErrorInvalidValue;
   const int grid = (int)(cdiv(M, 256) < 1024 ? cdiv(M, 256) : 1024);
   if (q_f32)
     hipLaunchKernelGGL(replace_kernel<float>, dim3(grid), dim3(256), 0, s, (float*)Q, ldq, M, l,
@@ -672,8 +698,10 @@ hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, co
 
 hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb,
                              const int32_t* bdep, double* C, int64_t ldc, int lp, hipStream_t s) {
-  hipLaunchKernelGGL(trmm_kernel, dim3((unsigned)cdiv((int64_t)lp * lp, 256)), dim3(256), 0, s, A,
-                     lda, B, ldb, bdep, C, ldc, lp);
+  if (lp > 256 || lp % 16) return hipErrorInvalidValue;
+  const int nb = lp / 16;
+  hipLaunchKernelGGL(trmm_kernel, dim3((unsigned)cdiv(nb * nb, 4)), dim3(256), 0, s, A, lda, B,
+                     ldb, bdep, C, ldc, lp);
   return hipGetLastError();
 }
 

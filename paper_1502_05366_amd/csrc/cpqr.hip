@@ -321,44 +321,92 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   }
 }
 
-// Upper-triangular solve with many right-hand sides, by back substitution
-// (x_i = (b_i - sum_{j>i} S_ij x_j) / S_ii, i = k-1 .. 0); one wave per
-// right-hand side.  Strided access: S(i, j) = S[i*s_r + j*s_c],
-// right-hand side `col` element i = Bm[col*b_c + i*b_r],
-// solution X(i, col) = X[i*x_r + col*x_c].  k <= 256.
+// Upper-triangular solve X = S^{-1} B with many right-hand sides (k <= 256),
+// by block back substitution over 16 x 16 blocks:
+//   X_c = M_c (B_c - sum_{b>c} S_cb X_b),  c = nb-1 .. 0,
+// where M_c is the solve with the diagonal block S_cc under the rule that a
+// zero pivot gives a zero unknown (x_i = 0 when S_ii = 0); that rule is
+// linear in the right-hand side, so M_c is the matrix of 16 such solves with
+// the unit vectors, formed in LDS by every workgroup.  One wave takes 16
+// right-hand sides; as in the orth triangular solve, the 16 x 16 product
+// in accumulator layout (lane (j, g) holds rows 4v + g of column j) is the
+// B operand of the later products, so each X_b stays in registers.  Strided
+// access: S(i, j) = S[i*s_r + j*s_c], right-hand side `col` element i =
+// Bm[col*b_c + i*b_r], X(i, col) = X[i*x_r + col*x_c].
+constexpr int BSB_MAXNB = 16;
+
+template <int NB>
 __global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__ S, int64_t s_r,
                                                       int64_t s_c, const double* __restrict__ Bm,
                                                       int64_t b_r, int64_t b_c, int k,
                                                       int64_t nrhs, double* __restrict__ X,
                                                       int64_t x_r, int64_t x_c) {
-  const int lane = threadIdx.x & 63;
-  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (col >= nrhs) return;
-  double x[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = 64 * q + lane;
-    x[q] = (i < k) ? Bm[col * b_c + (int64_t)i * b_r] : 0.0;
+  __shared__ double Sd[BSB_MAXNB][16 * 17];   // diagonal blocks of S
+  __shared__ double Md[BSB_MAXNB][16 * 17];   // their solve matrices M_c
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nb = (int)cdiv(k, 16);
+  for (int e = tid; e < nb * 256; e += 256) {
+    const int c = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    const int gi = c * 16 + i, gj = c * 16 + j;
+    Sd[c][i * 17 + j] = (gi < k && gj < k && i <= j) ? S[gi * s_r + gj * s_c] : 0.0;
   }
+  __syncthreads();
+  if (tid < nb * 16) {
+    // column j of M_c: back substitution with the unit vector e_j
+    const int c = tid >> 4, j = tid & 15;
+    const double* sd = Sd[c];
+    double x[16];
 #pragma unroll
-  for (int q = 3; q >= 0; --q) {
-    for (int ll = 63; ll >= 0; --ll) {
-      const int i = 64 * q + ll;
-      if (i >= k) continue;
-      const double sii = S[(int64_t)i * s_r + (int64_t)i * s_c];
-      const double xi = (sii != 0.0) ? __shfl(x[q], ll, 64) / sii : 0.0;
-      if (lane == ll) x[q] = xi;
+    for (int i = 15; i >= 0; --i) {
+      double t = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-      for (int q2 = 0; q2 <= q; ++q2) {
-        const int i2 = 64 * q2 + lane;
-        if (i2 < i) x[q2] -= S[(int64_t)i2 * s_r + (int64_t)i * s_c] * xi;
+      for (int q = i + 1; q < 16; ++q) t -= sd[i * 17 + q] * x[q];
+      const double sii = sd[i * 17 + i];
+      x[i] = (sii != 0.0) ? t / sii : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Md[c][i * 17 + j] = x[i];
+  }
+  __syncthreads();
+  const int64_t col0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (col0 >= nrhs) return;
+  const int64_t col = col0 + li;
+  const bool cok = col < nrhs;
+  const double* bc = Bm + (cok ? col : 0) * b_c;
+  double* xc = X + (cok ? col : 0) * x_c;
+  d4 xt[NB];
+#pragma unroll
+  for (int c = NB - 1; c >= 0; --c) {
+    if (c < nb) {
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = c * 16 + 4 * v + lk;
+        acc[v] = (cok && i < k) ? bc[i * b_r] : 0.0;
+      }
+#pragma unroll
+      for (int b = c + 1; b < NB; ++b) {
+        if (b < nb) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int i = c * 16 + li, j = b * 16 + 4 * kk + lk;
+            const double av = (i < k && j < k) ? -S[i * s_r + j * s_c] : 0.0;   // S_cb[li][k]
+            acc = Mfma<double>::mma(av, xt[b][kk], acc);
+          }
+        }
+      }
+      d4 out = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        out = Mfma<double>::mma(Md[c][li * 17 + 4 * kk + lk], acc[kk], out);
+      xt[c] = out;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = c * 16 + 4 * v + lk;
+        if (cok && i < k) xc[i * x_r] = out[v];
       }
     }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = 64 * q + lane;
-    if (i < k) X[(int64_t)i * x_r + col * x_c] = x[q];
   }
 }
 
@@ -434,8 +482,17 @@ hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const doubl
                           int64_t x_c, hipStream_t s) {
   if (nrhs <= 0 || k <= 0) return hipSuccess;
   if (k > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(backsub_kernel, dim3((unsigned)cdiv(nrhs, 4)), dim3(256), 0, s, S, s_r, s_c,
-                     Bm, b_r, b_c, k, nrhs, X, x_r, x_c);
+  const dim3 grid((unsigned)cdiv(nrhs, 64));
+  const int nb = (int)cdiv(k, 16);
+#define RSVD_BSB(NBV)                                                                           \
+  hipLaunchKernelGGL(backsub_kernel<NBV>, grid, dim3(256), 0, s, S, s_r, s_c, Bm, b_r, b_c, k, \
+                     nrhs, X, x_r, x_c)
+  if (nb <= 2) RSVD_BSB(2);
+  else if (nb <= 4) RSVD_BSB(4);
+  else if (nb <= 8) RSVD_BSB(8);
+  else if (nb <= 13) RSVD_BSB(13);
+  else RSVD_BSB(16);
+#undef RSVD_BSB
   return hipGetLastError();
 }
 

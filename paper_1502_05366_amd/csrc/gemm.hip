@@ -287,7 +287,12 @@ GemmPlan plan_gemm(int64_t M, int64_t K, int64_t L, int ncu, int force_G) {
   } else if (p.KI <= 32 && T >= ncu / 2) {
     p.G = T;                        // short reductions: one whole tile each
   } else {
-    p.G = p.U < ncu ? p.U : ncu;
+    // at least ~16 k-steps per workgroup, so that few output tiles over a
+    // long reduction do not leave a fix-up of hundreds of partial tiles
+    int64_t G = p.U / 16;
+    if (G < T) G = T;
+    if (G > ncu) G = ncu;
+    p.G = G;
   }
   p.bm = BM;
   p.bn = BN;

@@ -61,14 +61,14 @@ namespace rsvd {
 // One Cholesky factorization of an lp x lp Gram matrix (lp <= 256, lp % 16 == 0,
 // only rows/columns < l are read).  R upper triangular (zero below), Rdinv the
 // inverses of its 16x16 diagonal blocks (lp/16 blocks of 256 doubles), dep[j]
-// = 1 for columns declared dependent (pivot <= eta * G_jj).  With
-// near_identity (one device int), G is first tested for ||G - I||_F^2 below a
-// quarter of the unit roundoff; if it passes, R = I + Phi(G - I) is written by
-// a one-workgroup kernel, *near_identity = 1 and the full factorization
-// returns at once; otherwise *near_identity = 0 and G is factored.
+// = 1 for columns declared dependent (pivot <= eta * G_jj).  With ni_part
+// (lp/16 doubles of scratch), G is first taken as I + E: R = I + Phi(E) is
+// written by one workgroup per 16 rows together with the parts of
+// ||E||_F^2, and the full factorization returns at once when their sum is
+// below a quarter of the unit roundoff (and otherwise overwrites R).
 hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, double* R,
                        int64_t ldr, double* Rdinv, int32_t* dep, int32_t* info, hipStream_t s,
-                       int32_t* near_identity = nullptr);
+                       double* ni_part = nullptr);
 // G = Y^T Y (upper 16x16 tiles of an lp x lp matrix) in FP64 for a tall Y,
 // sized for ncu compute units; `part` holds gram_part_bytes(lp, ncu_cap)
 // bytes for any ncu <= ncu_cap.

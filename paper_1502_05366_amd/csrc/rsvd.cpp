@@ -81,7 +81,7 @@ struct OrthBufs {
   double *G = nullptr, *R1 = nullptr, *R2 = nullptr, *Rd1 = nullptr, *Rd2 = nullptr,
          *Qa = nullptr;
   int32_t *dep = nullptr, *dep2 = nullptr;
-  int32_t* ni = nullptr;  // one int: the second Gram matrix passed the near-identity test
+  double* nip = nullptr;  // lp/16 parts of ||G - I||_F^2 of the second Gram matrix
   void* part = nullptr;
   size_t part_bytes = 0;
   double* gpart = nullptr;  // partial Gram tiles, gram_part_bytes(lp, NCU_CAP)
@@ -133,7 +133,7 @@ OrthBufs take_orth(Arena& a, int64_t rows, int lp, size_t part_bytes) {
   ob.Qa = a.take<double>((size_t)rows * lp);
   ob.dep = a.take<int32_t>(lp);
   ob.dep2 = a.take<int32_t>(lp);
-  ob.ni = a.take<int32_t>(1);
+  ob.nip = a.take<double>(16);
   ob.part_bytes = part_bytes;
   ob.part = a.take<char>(part_bytes);
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
@@ -221,7 +221,7 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
   // pass 2 on Qa
   RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st,
-                       ob.ni));
+                       ob.nip));
   RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st));
   if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, ob.dep, Rout, ldr, lp, c.st));
   return hipSuccess;
@@ -636,7 +636,8 @@ size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {
   Arena a(nullptr);
   a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
   a.take<double>((size_t)rows * lp);
-  a.take<int32_t>(2 * (size_t)lp + 1);
+  a.take<int32_t>(2 * (size_t)lp);
+  a.take<double>(16);
   a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
   return a.off;
 }
@@ -669,9 +670,9 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   ob.Rd1 = blk + 4 * (size_t)lp * lp;
   ob.Rd2 = ob.Rd1 + (size_t)lp * 16;
   ob.Qa = a.take<double>((size_t)rows * lp);
-  ob.dep = a.take<int32_t>(2 * (size_t)lp + 1);
+  ob.dep = a.take<int32_t>(2 * (size_t)lp);
   ob.dep2 = ob.dep + lp;
-  ob.ni = ob.dep + 2 * (size_t)lp;
+  ob.nip = a.take<double>(16);
   ob.part = nullptr;
   ob.part_bytes = 0;
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
