@@ -141,13 +141,19 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
       double x[4], y[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) { x[v] = Dss[drow(g, v) * 17 + c]; y[v] = 0.0; }
+      // lane c holds the dependence threshold of column c of the block; the
+      // column flags are collected in two wave-uniform masks and written
+      // after the block
+      const double thr = eta * diag0[s * 16 + c];
+      uint32_t okm = 0u, nfm = 0u;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int vj = j >> 2, gj = j & 3;
         const double d = readlane_d(x[vj], 16 * gj + j);      // Schur pivot G'[j][j]
-        const int gcol = s * 16 + j;
         const bool finite = isfinite(d);
-        const bool ok = finite && d > eta * diag0[gcol];
+        const bool ok = finite && d > readlane_d(thr, j);
+        okm |= ok ? (1u << j) : 0u;
+        nfm |= finite ? 0u : (1u << j);
         const double inv = ok ? rsq_nr(d) : 1.0;             // 1 / R[j][j]
         const double rjj = ok ? d * inv : 1.0;
         if (g == gj) {
@@ -182,13 +188,19 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane == 0) {
-          depblk[j] = ok ? 0 : 1;
-          if (gcol < l) {
-            dep[gcol] = ok ? 0 : 1;
-            if (!ok) info_or(info, finite ? INFO_ORTH_FALLBACK : INFO_NONFINITE);
-          }
-        }
+      }
+      if (lane < 16) {
+        const int gcol = s * 16 + lane;
+        const int dj = ((okm >> lane) & 1u) ? 0 : 1;
+        depblk[lane] = dj;
+        if (gcol < l) dep[gcol] = dj;
+      }
+      if (lane == 0) {
+        // columns of the block below l that failed the test
+        const uint32_t lmask = (l - s * 16 >= 16) ? 0xFFFFu : ((1u << (l - s * 16)) - 1u);
+        const uint32_t bad = ~okm & lmask;
+        if ((bad & nfm) != 0u) info_or(info, INFO_NONFINITE);
+        if ((bad & ~nfm) != 0u) info_or(info, INFO_ORTH_FALLBACK);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
