@@ -38,7 +38,9 @@ PHILOX_W1 = 0xBB67AE85
 MASK32 = 0xFFFFFFFF
 TWO_PI = 6.283185307179586  # nearest double to 2*pi
 
-STREAM_SKETCH = 0
+STREAM_SKETCH = 0      # Omega (n x l) of the range finder
+STREAM_QB = 5          # Omega_i (n x b) of block i of the blocked QB (batch = i)
+STREAM_LEFT = 6        # Omega~^T (m x l) of the left-sketch ID
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

@@ -16,6 +16,9 @@ bench's cpu_baseline leg may use it.
 ``two_sided_id``  Sec. 2.5 / Alg. 2: row ID of C = A(:, J(1:k)).
 ``cur``           Sec. 2.5 / Alg. 3 and Sec. 3.6: C = A(:, Jc), R = A(Jr, :),
                   U = V^T R^dagger with R^dagger from the QR of R^T.
+``id_left``       Sec. 3.5 / Alg. 6: ID from the left sample Y = Omega~ A with
+                  the power scheme of eq. (Ypower) orthonormalized between
+                  products; k steps of column-pivoted QR of Y, T = S11^{-1} S12.
 """
 
 import numpy as np
@@ -165,3 +168,32 @@ def cur(A, k, p, q, seed, Q=None):
                row_pivot_norms=fr['pivot_norms'],
                row_second_norms=fr['second_norms'])
     return out
+
+
+def id_left(A, k, p, q, seed):
+    """Randomized column ID with the Gaussian sketch on the left (Alg. 6).
+
+    Omega~ is (k+p) x m; its transpose is drawn like the range finder's
+    sketch but from stream philox.STREAM_LEFT (Omega~^T[i, j] = normal
+    number j*m + i).  The sample is eq. (Ypower), Y = Omega~ A (A^T A)^q,
+    with the columns orthonormalized before every product (the listing
+    after eq. (Ypower)):
+        Y^T = A^T Omega~^T;  q times { Y^T = A orth(Y^T);  Y^T = A^T orth(Y^T) }.
+    Then k steps of the column-pivoted QR of Y (l x n) give J and
+    T = S11^{-1} S12 as in qb_id (Alg. 6 keeps the first k of the l pivots,
+    which are those of k greedy steps).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    l = sample_size(m, n, k, p)
+    Ot = philox.sketch(seed, m, l, sid=philox.STREAM_LEFT)
+    Yt = A.T @ Ot
+    for _ in range(q):
+        Yt = A @ orth(Yt)
+        Yt = A.T @ orth(Yt)
+    Y = Yt.T.copy()
+    f = cpqr(Y, k)
+    T = solve_upper(f['S11'], f['S12'])
+    return dict(J=f['J'], T=T, frank=f['frank'], Y=Y,
+                pivot_norms=f['pivot_norms'], second_norms=f['second_norms'],
+                S22norm_F=f['S22norm_F'], S11=f['S11'], S12=f['S12'])
