@@ -91,6 +91,52 @@ def cpu_baseline(A, k, p, q, seed, budget_s=20.0):
                       "%.1f s; GFLOP/s with the same RSVD flop count" % (ms, m, ms, n, k, p, q, t)}
 
 
+def id_left_flops(m, n, k, p, q):
+    """Algorithmic flops of the left-sketch ID (Alg. 6 with eq. (Ypower)):
+    2q+1 passes over A and 2q orthonormalizations at the Householder count
+    (the pivoted QR of the l x n sample and T are not credited)."""
+    l = min(k + p, m, n)
+    return (2 * (2 * q + 1) * m * n * l + q * (2 * m * l * l - 2 * l ** 3 / 3)
+            + q * (2 * n * l * l - 2 * l ** 3 / 3))
+
+
+def id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1):
+    """Time rsvd_id_left (FP64 A resident in HBM) at the benchmark's shape."""
+    import torch
+    from paper_1502_05366_amd import api
+
+    dev = A.device
+    wb = lib.rsvd_id_left_workspace_bytes(api.F64, m, n, k, p, q)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    J = torch.empty(n, dtype=torch.int64, device=dev)
+    T = torch.empty((k, n - k), dtype=torch.float64, device=dev)
+
+    def step():
+        rc = lib.rsvd_id_left(h, api.F64, m, n, k, p, q, seed, P(A), n, P(J), P(T), n - k,
+                              P(work), wb, P(info), sp)
+        if rc != 0:
+            raise RuntimeError("rsvd_id_left returned %d" % rc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log("id_left: %.3f ms/call" % ms)
+    st = info.cpu().numpy()
+    return {"ms_per_call": round(ms, 4),
+            "value_gflops": round(id_left_flops(m, n, k, p, q) / (ms * 1e-3) / 1e9, 2),
+            "passes": 2 * q + 1,
+            "info": [int(st[0]), int(st[1])],
+            "note": "rsvd_id_left, FP64 A, same k, p, q and seed; GFLOP/s = 2(2q+1)mnl + "
+                    "q(2ml^2 - 2l^3/3) + q(2nl^2 - 2l^3/3) per call"}
+
+
 def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf16):
     """Time rsvd_decompose with A stored in BF16 (bf16=True) or FP32, and one
     pass over A of that storage type."""
@@ -296,6 +342,8 @@ def main():
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
+    idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
+
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
@@ -325,6 +373,7 @@ def main():
     }
     out["fp32"] = lowp["fp32"]
     out["bf16"] = lowp["bf16"]
+    out["id_left"] = idl
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

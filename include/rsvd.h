@@ -107,6 +107,20 @@ int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int 
             uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
             void* work, size_t work_bytes, int32_t* info, void* stream);
 
+/* Rank-k column ID with the Gaussian sketch on the left (Sec. 3.5, Alg. 6):
+ * the sample Y = Omega~ A (A^T A)^q of eq. (Ypower), (k+p) x n, formed with the
+ * columns orthonormalized before every product (the listing after that
+ * equation):  Y^T = A^T Omega~^T;  q times { Y^T = A orth(Y^T);
+ * Y^T = A^T orth(Y^T) };  then k steps of column-pivoted QR of Y and
+ * T = S11^{-1} S12.  Omega~^T (m x (k+p)) holds normal number j*m + i of
+ * Philox stream 6 at (i, j).  Arguments, outputs (J, T) and errors as for
+ * rsvd_id; the workspace is rsvd_id_left_workspace_bytes(...) bytes.  Passes
+ * over A: 2q + 1. */
+size_t rsvd_id_left_workspace_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q);
+int rsvd_id_left(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                 uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
+                 void* work, size_t work_bytes, int32_t* info, void* stream);
+
 /* Rank-k CUR from the two-sided ID (Sec. 2.5, Alg. 3; Sec. 3.6): Jc = skeleton
  * columns of the ID above, Jr = the k rows chosen by k steps of column-pivoted
  * QR of C^T (C = A(:, Jc)), and Ucur = V^T R^dagger (k x k FP64, lduc >= k),

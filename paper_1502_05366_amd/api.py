@@ -184,6 +184,28 @@ def id(A, k, p, q, seed):  # noqa: A001  (named after the C entry point)
     return J, T[:, :n - k], info
 
 
+def id_left(A, k, p, q, seed):
+    """Rank-k column ID from the left sample Y = Omega~ A (A^T A)^q (Alg. 6):
+    J (n; skeleton J[:k]), T (k x (n-k)), info."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    wb = lib.rsvd_id_left_workspace_bytes(dt, m, n, k, p, q)
+    if wb == 0:
+        raise RsvdError("invalid sizes")
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    J = torch.empty(n, dtype=torch.int64, device=dev)
+    ldt = max(n - k, 1)
+    T = torch.empty((k, ldt), dtype=torch.float64, device=dev)
+    rc = lib.rsvd_id_left(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(J),
+                          _ptr(T), ldt, _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_id_left")
+    return J, T[:, :n - k], info
+
+
 def cur(A, k, p, q, seed):
     """Rank-k CUR: Jc (k), Jr (k), U (k x k FP64), info; A ~ A[:, Jc] U A[Jr, :]."""
     lib = _lib.load()

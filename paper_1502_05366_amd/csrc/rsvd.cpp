@@ -347,6 +347,64 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
   return hipSuccess;
 }
 
+// ---- left-sketch ID (Alg. 6 with the power scheme of eq. (Ypower)) -------
+constexpr uint32_t STREAM_LEFT = 6;   // Philox stream of Omega~^T
+
+struct LeftBufs {
+  void *Ot, *Yt, *Ym, *Qm, *Qn;
+  uint16_t* Xt;
+  OrthBufs ob;
+  void* cq_work;
+  double *S11t, *S12t, *pivn;
+};
+
+size_t layout_left(const Shape& s, void* base, LeftBufs* out) {
+  Arena a(base);
+  LeftBufs b;
+  const int64_t rmax = std::max(s.m, s.n);
+  b.Ot = a.take<char>((size_t)s.m * s.lp * s.dsz);
+  b.Yt = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  b.Ym = a.take<char>((size_t)s.m * s.lp * s.dsz);
+  b.Qm = a.take<char>((size_t)s.m * s.lp * s.dsz);
+  b.Qn = a.take<char>((size_t)s.n * s.lp * s.dsz);
+  b.Xt = s.bf16 ? a.take<uint16_t>((size_t)s.lp * rup(rmax, 8)) : nullptr;
+  b.ob = take_orth(a, rmax, s.lp, max_part(s));
+  b.cq_work = a.take<char>(cpqr_work_bytes(plan_cpqr(s.l, s.n, s.k, NCU_CAP)));
+  b.S11t = a.take<double>((size_t)s.k * s.kp);
+  b.S12t = a.take<double>((size_t)(s.n - s.k + 1) * s.kp);
+  b.pivn = a.take<double>(s.k);
+  if (out) *out = b;
+  return a.off;
+}
+
+// Y^T = A^T Omega~^T;  q times { Y^T = A orth(Y^T);  Y^T = A^T orth(Y^T) };
+// k steps of column-pivoted QR of Y (its columns are the rows of Y^T);
+// T = S11^{-1} S12.
+hipError_t run_id_left(Ctx& c, const Shape& s, const LeftBufs& b, const void* A, int64_t lda,
+                       int64_t* J, double* T, int64_t ldt) {
+  const bool f32 = s.f32;
+  const int l = s.l, lp = s.lp, k = s.k, at = s.atype;
+  const int64_t m = s.m, n = s.n;
+  RSVD_TRY(launch_set_word(c.info, 0, c.st));
+  RSVD_TRY(launch_set_word(c.info + 1, 0, c.st));
+  RSVD_TRY(launch_sketch(f32, c.seed, STREAM_LEFT, 0, m, l, b.Ot, lp, c.st));
+  RSVD_TRY(pass(c, at, true, m, n, l, A, lda, b.Ot, lp, b.Yt, lp, b.ob.part, b.ob.part_bytes,
+                b.Xt));
+  for (int j = 0; j < s.q; ++j) {
+    RSVD_TRY(orth(c, b.ob, f32, b.Yt, lp, n, l, b.Qn, f32, lp, nullptr, 0));
+    RSVD_TRY(pass(c, at, false, m, n, l, A, lda, b.Qn, lp, b.Ym, lp, b.ob.part,
+                  b.ob.part_bytes, b.Xt));
+    RSVD_TRY(orth(c, b.ob, f32, b.Ym, lp, m, l, b.Qm, f32, lp, nullptr, 0));
+    // with a BF16 A the last basis enters in two BF16 parts, as for B^T
+    RSVD_TRY(pass(c, at, true, m, n, l, A, lda, b.Qm, lp, b.Yt, lp, b.ob.part, b.ob.part_bytes,
+                  b.Xt, j == s.q - 1));
+  }
+  const CpqrPlan cp = plan_cpqr(l, n, k, std::min(c.ncu, NCU_CAP));
+  RSVD_TRY(launch_cpqr(f32, b.Yt, lp, l, n, k, cp, b.cq_work, J, b.S11t, b.S12t, s.kp, b.pivn,
+                       c.info, true, c.st));
+  return launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st);
+}
+
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
   if (!h) return -1;
   if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
@@ -529,6 +587,36 @@ int rsvd_id(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int 
   std::memset(&o, 0, sizeof(o));
   o.J = J; o.T = T; o.ldt = ldt;
   return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+size_t rsvd_id_left_workspace_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) || m < 1 || n < 1 || k < 1 ||
+      k > std::min(m, n) || p < 0 || q < 0)
+    return 0;
+  return layout_left(make_shape(RSVD_OP_ID, dtype, m, n, k, p, q), nullptr, nullptr);
+}
+
+int rsvd_id_left(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                 uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
+                 void* work, size_t work_bytes, int32_t* info, void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
+  if (!J) return -11;
+  if (!T) return -12;
+  if (ldt < n - k || ldt < 1) return -13;
+  if (!work) return -14;
+  if (!info) return -16;
+  const Shape s = make_shape(RSVD_OP_ID, dtype, m, n, k, p, q);
+  if (s.l > MAX_L || !plan_cpqr(s.l, n, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
+  LeftBufs b;
+  const size_t need = layout_left(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
+  return finish(run_id_left(c, s, b, A, lda, J, T, ldt));
 }
 
 int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,

@@ -104,3 +104,21 @@ def test_c2_fp32(c2):
     npre = pivot_prefix(c["pivot_norms"], c["second_norms"], 1e-4)
     assert np.array_equal(J[:npre], c["J"][:npre])
     assert np.array_equal(np.sort(J), np.arange(len(J)))
+
+
+def test_c2_id_left(c2):
+    """The left-sketch ID (Alg. 6, eq. (Ypower)) at full size against the
+    oracle's: skeleton up to the first near-tie of the pivot norms, T where
+    all pivots agree."""
+    import paper_1502_05366_amd as R
+    J, T, info = R.id_left(c2["Ad"], K, P, Q, SEED)
+    torch.cuda.synchronize()
+    J, T = J.cpu().numpy(), T.cpu().numpy()
+    d = O.id_left(c2["A"], K, P, Q, SEED)
+    assert np.array_equal(np.sort(J), np.arange(len(J)))
+    npre = pivot_prefix(d["pivot_norms"], d["second_norms"], 1e-8)
+    assert npre >= 1
+    assert np.array_equal(J[:npre], d["J"][:npre])
+    if npre == K:
+        assert np.array_equal(J, d["J"])
+        assert np.abs(T - d["T"]).max() <= 1e-8 * max(1.0, np.abs(d["T"]).max())
