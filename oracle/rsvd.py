@@ -19,6 +19,8 @@ bench's cpu_baseline leg may use it.
 ``id_left``       Sec. 3.5 / Alg. 6: ID from the left sample Y = Omega~ A with
                   the power scheme of eq. (Ypower) orthonormalized between
                   products; k steps of column-pivoted QR of Y, T = S11^{-1} S12.
+``qb_blocked``    Sec. 3.3 / Alg. 7: blocked adaptive QB with deflation of A
+                  and a tolerance on the residual.
 """
 
 import numpy as np
@@ -197,3 +199,37 @@ def id_left(A, k, p, q, seed):
     return dict(J=f['J'], T=T, frank=f['frank'], Y=Y,
                 pivot_norms=f['pivot_norms'], second_norms=f['second_norms'],
                 S22norm_F=f['S22norm_F'], S11=f['S11'], S12=f['S12'])
+
+
+def qb_blocked(A, b, M, tol, q, seed):
+    """Blocked adaptive QB decomposition (Alg. 7, scheme QB_2 of Sec. 3.3).
+
+    For i = 1..M: Omega_i (n x b) is the sketch of philox.STREAM_QB with
+    batch index i - 1; Q_i = orth(A Omega_i); q times { Q_i = orth(A^T Q_i);
+    Q_i = orth(A Q_i) }; Q_i = orth(Q_i - sum_{j<i} Q_j Q_j^T Q_i);
+    B_i = Q_i^T A; A = A - Q_i B_i; stop when ||A||_F < tol.  A here is a
+    copy that the loop deflates, so the products of block i see
+    (I - Qbar Qbar^T) A.  Returns dict(Q (m x bi), B (bi x n), nblocks = i,
+    norms (||A||_F after each block), R = the deflated A).
+    """
+    A = np.array(A, dtype=np.float64, copy=True)
+    m, n = A.shape
+    Qs, Bs, norms = [], [], []
+    for i in range(M):
+        Om = philox.sketch(seed, n, b, sid=philox.STREAM_QB, batch=i)
+        Qi = orth(A @ Om)
+        for _ in range(q):
+            Qi = orth(A.T @ Qi)
+            Qi = orth(A @ Qi)
+        if Qs:
+            Qbar = np.hstack(Qs)
+            Qi = Qi - Qbar @ (Qbar.T @ Qi)
+        Qi = orth(Qi)
+        Bi = Qi.T @ A
+        A = A - Qi @ Bi
+        Qs.append(Qi)
+        Bs.append(Bi)
+        norms.append(np.linalg.norm(A))
+        if norms[-1] < tol:
+            break
+    return dict(Q=np.hstack(Qs), B=np.vstack(Bs), nblocks=len(Qs), norms=np.array(norms), R=A)

@@ -75,3 +75,51 @@ def test_id_left_sketch_stream():
     b = philox.sketch(1, 40, 6)
     assert a.shape == (40, 6) and not np.allclose(a, b)
     assert np.array_equal(a, philox.sketch(1, 40, 6, sid=6))
+
+
+# ---------------------------------------------------------- blocked QB ----
+# Alg. 7 / Sec. 3.3: the deflated A after block i is (I - Qbar_i Qbar_i^T) A
+# (the lemma of Sec. 3.3 carried to blocks), the blocks are orthonormal to
+# each other, so B = Q^T A and ||A - Q B||_F is the deflated norm; the loop
+# stops at the first block whose residual is below tol; no rank-bi result
+# beats the tail of the spectrum (Eckart-Young).
+
+def test_qb_identities():
+    A, s = W.logspace_type(200, 150, 2, seed=13)
+    d = O.qb_blocked(A, 8, 5, 0.0, 1, seed=21)
+    Q, B = d["Q"], d["B"]
+    assert d["nblocks"] == 5 and Q.shape == (200, 40) and B.shape == (40, 150)
+    assert np.abs(Q.T @ Q - np.eye(40)).max() < 1e-13
+    assert np.abs(B - Q.T @ A).max() < 1e-12 * s[0]
+    assert np.abs(d["R"] - (A - Q @ B)).max() < 1e-12 * s[0]
+    assert abs(np.linalg.norm(A - Q @ B) - d["norms"][-1]) < 1e-12 * np.linalg.norm(A)
+
+
+def test_qb_exact_rank_stops():
+    A, s, _, _ = W.exact_rank_matrix(180, 120, 20, seed=5)
+    nA = np.linalg.norm(A)
+    d = O.qb_blocked(A, 8, 10, 1e-10 * nA, 1, seed=2)
+    assert d["nblocks"] == 3                     # ceil(20 / 8) blocks span range(A)
+    assert d["norms"][-1] < 1e-12 * nA
+    assert np.all(d["norms"][:-1] >= 1e-10 * nA)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_qb_tail_bounds(q):
+    m, n, b = 300, 200, 10
+    A, s = W.logspace_type(m, n, 2, seed=8)
+    d = O.qb_blocked(A, b, 6, 0.0, q, seed=4)
+    for i, r in enumerate(d["norms"]):
+        tail = np.sqrt(np.sum(s[b * (i + 1):] ** 2))
+        assert r >= tail * (1.0 - 1e-12)
+        if q >= 1:
+            assert r <= 1.5 * tail
+
+
+def test_qb_tolerance_is_first_crossing():
+    A, s = W.logspace_type(250, 250, 3, seed=30)
+    tol = 0.05 * np.linalg.norm(A)
+    d = O.qb_blocked(A, 12, 20, tol, 1, seed=6)
+    assert d["norms"][-1] < tol
+    assert np.all(d["norms"][:-1] >= tol)
+    assert d["Q"].shape[1] == 12 * d["nblocks"]
