@@ -121,6 +121,27 @@ int rsvd_id_left(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p,
                  uint64_t seed, const void* A, int64_t lda, int64_t* J, double* T, int64_t ldt,
                  void* work, size_t work_bytes, int32_t* info, void* stream);
 
+/* Blocked adaptive QB decomposition (Sec. 3.3, Alg. 7), FP64 only.  For
+ * block i = 0, 1, ..: Omega_i (n x b) = normal numbers of Philox stream 5
+ * with batch index i (Omega_i[r][j] = number j*n + r);
+ *   Q_i = orth(A Omega_i);  q times { Q_i = orth(A^T Q_i); Q_i = orth(A Q_i) };
+ *   Q_i = orth(Q_i - Qbar Qbar^T Q_i)  (Qbar = Q_0 .. Q_{i-1});
+ *   B_i = Q_i^T A;  A = A - Q_i B_i;
+ * and the loop stops after block i when ||A||_F < tol, or after M blocks.
+ * A (m x n, lda >= n) is overwritten by the deflated residual A - Q B.
+ * Q: m x (b*M) (ldq >= b*M) and B: (b*M) x n (ldb >= n), FP64; their first
+ * b * (*nblocks) columns / rows hold the result, A_in ~ Q B.
+ * *nblocks (host) = blocks used; *resid (host, may be NULL) = ||A - Q B||_F.
+ * 1 <= b <= 256, b*M <= min(m, n), q >= 0, tol >= 0.  The call synchronizes
+ * `stream` once per block to test the stopping rule.  Workspace:
+ * rsvd_qb_workspace_bytes(...) bytes (0 for invalid sizes); FP32 and BF16
+ * return RSVD_ERR_UNSUPPORTED. */
+size_t rsvd_qb_workspace_bytes(int dtype, int64_t m, int64_t n, int b, int M, int q);
+int rsvd_qb(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int b, int M, int q, double tol,
+            uint64_t seed, void* A, int64_t lda, double* Q, int64_t ldq, double* B, int64_t ldb,
+            int32_t* nblocks, double* resid, void* work, size_t work_bytes, int32_t* info,
+            void* stream);
+
 /* Rank-k CUR from the two-sided ID (Sec. 2.5, Alg. 3; Sec. 3.6): Jc = skeleton
  * columns of the ID above, Jr = the k rows chosen by k steps of column-pivoted
  * QR of C^T (C = A(:, Jc)), and Ucur = V^T R^dagger (k x k FP64, lduc >= k),

@@ -206,6 +206,33 @@ def id_left(A, k, p, q, seed):
     return J, T[:, :n - k], info
 
 
+def qb(A, b, M, q, tol, seed):
+    """Blocked adaptive QB (Alg. 7) of an FP64 A, which is not modified (the
+    library deflates a copy): Q (m x b*nblocks), B (b*nblocks x n), the
+    residual ||A - Q B||_F, the deflated copy R = A - Q B, info."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    wb = lib.rsvd_qb_workspace_bytes(dt, m, n, b, M, q)
+    if wb == 0:
+        raise RsvdError("invalid sizes or type")
+    R = A.clone()
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    Q = torch.empty((m, b * M), dtype=torch.float64, device=dev)
+    B = torch.empty((b * M, n), dtype=torch.float64, device=dev)
+    nb = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    rc = lib.rsvd_qb(handle(dev), dt, m, n, b, M, q, float(tol), seed, _ptr(R), R.stride(0),
+                     _ptr(Q), Q.stride(0), _ptr(B), B.stride(0), ctypes.byref(nb),
+                     ctypes.byref(res), _ptr(work), work.numel(), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_qb")
+    k = b * nb.value
+    return Q[:, :k], B[:k], res.value, R, info
+
+
 def cur(A, k, p, q, seed):
     """Rank-k CUR: Jc (k), Jr (k), U (k x k FP64), info; A ~ A[:, Jc] U A[Jr, :]."""
     lib = _lib.load()

@@ -121,6 +121,20 @@ hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const doubl
                           int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,
                           int64_t x_c, hipStream_t s);
 
+// -------------------------------------------------------------------- qb --
+// A -= Q Bt^T (A m x n in place, Q m x b, Bt n x b; b <= 256) and
+// *norm2 = ||A||_F^2 of the result; part holds qb_update_tiles(m, n) doubles.
+int64_t qb_update_tiles(int64_t m, int64_t n);
+hipError_t launch_qb_update(double* A, int64_t lda, int64_t m, int64_t n, const double* Q,
+                            int64_t ldq, const double* Bt, int64_t ldbt, int b, double* part,
+                            double* norm2, hipStream_t s);
+// B[t][c] = Bt[c][t] (t < b, c < n)
+hipError_t launch_transpose(const double* Bt, int64_t ldbt, int64_t n, int b, double* B,
+                            int64_t ldb, hipStream_t s);
+// X -= Y (rows x cols)
+hipError_t launch_sub(double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t rows,
+                      int cols, hipStream_t s);
+
 // ------------------------------------------------------------------- cur --
 // atype: element type of A, 0 FP64, 1 FP32, 2 BF16
 hipError_t launch_gather_cols(int atype, const void* A, int64_t lda, int64_t m, int64_t n,

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "rsvd.h"
@@ -405,6 +406,95 @@ hipError_t run_id_left(Ctx& c, const Shape& s, const LeftBufs& b, const void* A,
   return launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st);
 }
 
+// ---- blocked adaptive QB (Alg. 7) -----------------------------------------
+constexpr uint32_t STREAM_QB = 5;     // Philox stream of Omega_i (batch = block index)
+
+struct QbBufs {
+  double *Om, *Ya, *Za, *Zb, *Yb, *W, *P, *Bt, *part, *norm2;
+  OrthBufs ob;
+};
+
+size_t qb_gemm_part_bytes(int64_t m, int64_t n, int b, int M) {
+  const int ncu = NCU_CAP;
+  const int64_t ib = std::max<int64_t>((int64_t)b * (M - 1), 1);
+  size_t r = 0;
+  r = std::max(r, gemm_part_bytes(plan_gemm(m, n, b, ncu, 0), 8));
+  r = std::max(r, gemm_part_bytes(plan_gemm(n, m, b, ncu, 0), 8));
+  r = std::max(r, gemm_part_bytes(plan_gemm(ib, m, b, ncu, 0), 8));
+  r = std::max(r, gemm_part_bytes(plan_gemm(m, ib, b, ncu, 0), 8));
+  return r;
+}
+
+size_t layout_qb(int64_t m, int64_t n, int b, int M, void* base, QbBufs* out) {
+  Arena a(base);
+  QbBufs q;
+  const int bp = (int)rup(b, 16);
+  q.Om = a.take<double>((size_t)n * bp);
+  q.Ya = a.take<double>((size_t)m * bp);
+  q.Za = a.take<double>((size_t)n * bp);
+  q.Zb = a.take<double>((size_t)n * bp);
+  q.Yb = a.take<double>((size_t)m * bp);
+  q.W = a.take<double>((size_t)b * M * bp);
+  q.P = a.take<double>((size_t)m * bp);
+  q.Bt = a.take<double>((size_t)n * bp);
+  q.part = a.take<double>((size_t)qb_update_tiles(m, n));
+  q.norm2 = a.take<double>(1);
+  q.ob = take_orth(a, std::max(m, n), bp, qb_gemm_part_bytes(m, n, b, M));
+  if (out) *out = q;
+  return a.off;
+}
+
+// Block i: Omega_i; Q_i = orth(A Omega_i); q times { Q_i = orth(A^T Q_i);
+// Q_i = orth(A Q_i) }; Q_i = orth(Q_i - Qbar (Qbar^T Q_i)); B_i = Q_i^T A;
+// A -= Q_i B_i; stop when ||A||_F < tol.  The host reads ||A||_F^2 after
+// every block (one stream synchronization per block).
+hipError_t run_qb(Ctx& c, const QbBufs& w, int64_t m, int64_t n, int b, int M, int q, double tol,
+                  double* A, int64_t lda, double* Q, int64_t ldq, double* B, int64_t ldb,
+                  int32_t* nblocks, double* resid) {
+  const int bp = (int)rup(b, 16);
+  const int ncu = std::min(c.ncu, NCU_CAP);
+  const OrthBufs& ob = w.ob;
+  RSVD_TRY(launch_set_word(c.info, 0, c.st));
+  RSVD_TRY(launch_set_word(c.info + 1, 0, c.st));
+  int nb = 0;
+  double r2 = 0.0;
+  for (int i = 0; i < M; ++i) {
+    double* Qi = Q + (int64_t)i * b;                 // columns i*b .. of Q
+    RSVD_TRY(launch_sketch(false, c.seed, STREAM_QB, (uint32_t)i, n, b, w.Om, bp, c.st));
+    RSVD_TRY(pass(c, 0, false, m, n, b, A, lda, w.Om, bp, w.Ya, bp, ob.part, ob.part_bytes));
+    RSVD_TRY(orth(c, ob, false, w.Ya, bp, m, b, w.Yb, false, bp, nullptr, 0));
+    for (int j = 0; j < q; ++j) {
+      RSVD_TRY(pass(c, 0, true, m, n, b, A, lda, w.Yb, bp, w.Za, bp, ob.part, ob.part_bytes));
+      RSVD_TRY(orth(c, ob, false, w.Za, bp, n, b, w.Zb, false, bp, nullptr, 0));
+      RSVD_TRY(pass(c, 0, false, m, n, b, A, lda, w.Zb, bp, w.Ya, bp, ob.part, ob.part_bytes));
+      RSVD_TRY(orth(c, ob, false, w.Ya, bp, m, b, w.Yb, false, bp, nullptr, 0));
+    }
+    if (i > 0) {
+      // Yb -= Qbar (Qbar^T Yb), Qbar = the first i*b columns of Q
+      const int64_t ib = (int64_t)i * b;
+      const GemmPlan pw = plan_gemm(ib, m, b, ncu, 0);
+      RSVD_TRY(launch_gemm(GEMM_DDDD, true, Q, ldq, w.Yb, bp, w.W, bp, ib, m, b, pw, ob.part,
+                           ob.part_bytes, c.st));
+      const GemmPlan pp = plan_gemm(m, ib, b, ncu, 0);
+      RSVD_TRY(launch_gemm(GEMM_DDDD, false, Q, ldq, w.W, bp, w.P, bp, m, ib, b, pp, ob.part,
+                           ob.part_bytes, c.st));
+      RSVD_TRY(launch_sub(w.Yb, bp, w.P, bp, m, b, c.st));
+    }
+    RSVD_TRY(orth(c, ob, false, w.Yb, bp, m, b, Qi, false, ldq, nullptr, 0));
+    // B_i^T = A^T Q_i (n x b), B_i = its transpose, A -= Q_i B_i
+    RSVD_TRY(pass(c, 0, true, m, n, b, A, lda, Qi, ldq, w.Bt, bp, ob.part, ob.part_bytes));
+    RSVD_TRY(launch_transpose(w.Bt, bp, n, b, B + (int64_t)i * b * ldb, ldb, c.st));
+    RSVD_TRY(launch_qb_update(A, lda, m, n, Qi, ldq, w.Bt, bp, b, w.part, w.norm2, c.st));
+    RSVD_TRY(hipMemcpyAsync(&r2, w.norm2, sizeof(double), hipMemcpyDeviceToHost, c.st));
+    RSVD_TRY(hipStreamSynchronize(c.st));
+    nb = i + 1;
+    if (std::sqrt(r2) < tol) break;
+  }
+  if (nblocks) *nblocks = nb;
+  if (resid) *resid = std::sqrt(r2);
+  return hipSuccess;
+}
+
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
   if (!h) return -1;
   if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
@@ -617,6 +707,43 @@ int rsvd_id_left(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p,
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   return finish(run_id_left(c, s, b, A, lda, J, T, ldt));
+}
+
+size_t rsvd_qb_workspace_bytes(int dtype, int64_t m, int64_t n, int b, int M, int q) {
+  if (dtype != RSVD_F64 || m < 1 || n < 1 || b < 1 || b > MAX_L || M < 1 || q < 0 ||
+      (int64_t)b * M > std::min(m, n))
+    return 0;
+  return layout_qb(m, n, b, M, nullptr, nullptr);
+}
+
+int rsvd_qb(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int b, int M, int q, double tol,
+            uint64_t seed, void* A, int64_t lda, double* Q, int64_t ldq, double* B, int64_t ldb,
+            int32_t* nblocks, double* resid, void* work, size_t work_bytes, int32_t* info,
+            void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64) return dtype == RSVD_F32 || dtype == RSVD_BF16 ? RSVD_ERR_UNSUPPORTED : -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (b < 1 || b > MAX_L) return -5;
+  if (M < 1 || (int64_t)b * M > std::min(m, n)) return -6;
+  if (q < 0) return -7;
+  if (!(tol >= 0.0)) return -8;
+  if (!A) return -10;
+  if (lda < n) return -11;
+  if (!Q) return -12;
+  if (ldq < (int64_t)b * M) return -13;
+  if (!B) return -14;
+  if (ldb < n) return -15;
+  if (!nblocks) return -16;
+  if (!work) return -18;
+  if (!info) return -20;
+  QbBufs w;
+  const size_t need = layout_qb(m, n, b, M, work, &w);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
+  return finish(run_qb(c, w, m, n, b, M, q, tol, static_cast<double*>(A), lda, Q, ldq, B, ldb,
+                       nblocks, resid));
 }
 
 int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,

@@ -1,11 +1,14 @@
 """Parity of the paper's variants with the FP64 oracle on the same A and seed
 (needs a GPU): the left-sketch randomized ID (Alg. 6 with the power scheme of
-eq. (Ypower)).
+eq. (Ypower)) and the blocked adaptive QB (Alg. 7).
 
 Bar, as for the ID from B: skeleton indices identical up to the first near-tie
 of the oracle's pivot norms (margin 1e-8), T within a rounding-level
 tolerance where all k pivots agree, J a permutation, exact results where the
-mathematics fixes them (exact rank, separated skeleton).
+mathematics fixes them (exact rank, separated skeleton).  Blocked QB: the same
+number of blocks as the oracle, Q and B equal to the oracle's to 1e-9 (both
+orthonormalize with the positive-diagonal QR, so each Q_i is unique), the
+residual norm to 1e-9 relative, and the deflation identities.
 """
 
 import numpy as np
@@ -94,3 +97,43 @@ def test_id_left_args(R):
     A = dev(np.zeros((100, 50)))
     with pytest.raises(R.RsvdError):
         R.id_left(A, 10, 5, -1, SEED)
+
+
+# ---------------------------------------------------------- blocked QB ----
+
+@pytest.mark.parametrize("m,n,b,M,q,tolf", [(600, 400, 16, 6, 1, 0.0), (2000, 1000, 10, 5, 1, 0.0),
+                                            (333, 517, 7, 9, 0, 0.02), (512, 512, 32, 8, 2, 0.01)])
+def test_qb_vs_oracle(R, m, n, b, M, q, tolf):
+    if (m, n) == (2000, 1000):
+        A, _ = W.c1_matrix()
+    else:
+        A, _ = W.logspace_type(m, n, 2, seed=m + n)
+    tol = tolf * np.linalg.norm(A)
+    Q, B, res, Rd, info = R.qb(dev(A), b, M, q, tol, SEED)
+    Q, B, Rd = Q.cpu().numpy(), B.cpu().numpy(), Rd.cpu().numpy()
+    d = O.qb_blocked(A, b, M, tol, q, SEED)
+    assert Q.shape[1] == d["Q"].shape[1], (Q.shape, d["nblocks"])
+    nA = np.linalg.norm(A)
+    assert np.abs(Q - d["Q"]).max() <= 1e-9
+    assert np.abs(B - d["B"]).max() <= 1e-9 * nA
+    assert abs(res - d["norms"][-1]) <= 1e-9 * nA
+    assert np.abs(Rd - (A - Q @ B)).max() <= 1e-11 * nA
+    assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-12
+
+
+def test_qb_exact_rank(R):
+    A, s, _, _ = W.exact_rank_matrix(1200, 700, 20, seed=9)
+    nA = np.linalg.norm(A)
+    Q, B, res, Rd, info = R.qb(dev(A), 8, 10, 1, 1e-10 * nA, SEED)
+    assert Q.shape[1] == 24
+    assert res < 1e-12 * nA
+    Q = Q.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(24)).max() < 1e-12
+
+
+def test_qb_args(R):
+    lib = R.api._lib.load()
+    assert lib.rsvd_qb_workspace_bytes(0, 100, 50, 16, 4, 1) == 0      # b*M > min(m, n)
+    assert lib.rsvd_qb_workspace_bytes(1, 100, 50, 8, 4, 1) == 0       # FP32 not built
+    with pytest.raises(R.RsvdError):
+        R.qb(dev(np.zeros((100, 50)), torch.float32), 8, 4, 1, 0.0, SEED)
