@@ -137,6 +137,64 @@ def id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1):
                     "q(2ml^2 - 2l^3/3) + q(2nl^2 - 2l^3/3) per call"}
 
 
+QB_B, QB_M, QB_Q, QB_TOL = 32, 10, 1, 0.07
+
+
+def qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1):
+    """Time rsvd_qb (blocked adaptive QB, FP64) on a fresh copy of A per call
+    (the call deflates its A in place; the copy is outside the timed region).
+    b = 32, at most 10 blocks, q = 1, tol = 0.07: on sigma_j = 1/j the residual
+    is 0.0704 after 7 blocks and drops below tol with the 8th."""
+    import ctypes
+    import torch
+    from paper_1502_05366_amd import api
+
+    dev = A.device
+    b, M, q, tol = QB_B, QB_M, QB_Q, QB_TOL
+    wb = lib.rsvd_qb_workspace_bytes(api.F64, m, n, b, M, q)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    Q = torch.empty((m, b * M), dtype=torch.float64, device=dev)
+    B = torch.empty((b * M, n), dtype=torch.float64, device=dev)
+    Aw = torch.empty_like(A)
+    nb = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+
+    def call():
+        rc = lib.rsvd_qb(h, api.F64, m, n, b, M, q, tol, seed, P(Aw), n, P(Q), b * M, P(B), n,
+                         ctypes.byref(nb), ctypes.byref(res), P(work), wb, P(info), sp)
+        if rc != 0:
+            raise RuntimeError("rsvd_qb returned %d" % rc)
+
+    tot = 0.0
+    reps = max(1, min(args.steps, 5))
+    for it in range(args.warmup + reps):
+        Aw.copy_(A)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            tot += e0.elapsed_time(e1)
+    ms = tot / reps
+    k = nb.value
+    # per block: 2q+2 passes over A (2mnb flops each), the deflation (2mnb),
+    # and the projection on the earlier blocks (4 m (ib) b)
+    flops = sum((2 * q + 3) * 2.0 * m * n * b + 4.0 * m * (i * b) * b for i in range(k))
+    abytes = k * ((2 * q + 2) * 8.0 * m * n + 16.0 * m * n)
+    log("qb: %.3f ms/call, %d blocks, resid %.4g" % (ms, k, res.value))
+    st = info.cpu().numpy()
+    return {"ms_per_call": round(ms, 4), "blocks": k, "block_size": b, "q": q, "tol": tol,
+            "resid_fro": res.value,
+            "value_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+            "a_traffic_GBs": round(abytes / (ms * 1e-3) / 1e9, 1),
+            "info": [int(st[0]), int(st[1])],
+            "note": "rsvd_qb on a fresh FP64 copy of A; flops = sum over blocks of "
+                    "(2q+3) 2mnb + 4m(ib)b; a_traffic = (2q+2) reads of A + one read and "
+                    "write per block, per second"}
+
+
 def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf16):
     """Time rsvd_decompose with A stored in BF16 (bf16=True) or FP32, and one
     pass over A of that storage type."""
@@ -343,6 +401,7 @@ def main():
         lowp[key] = r
 
     idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
+    qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
 
     out = {
         "metric": METRIC,
@@ -374,6 +433,7 @@ def main():
     out["fp32"] = lowp["fp32"]
     out["bf16"] = lowp["bf16"]
     out["id_left"] = idl
+    out["qb"] = qbr
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

@@ -122,3 +122,20 @@ def test_c2_id_left(c2):
     if npre == K:
         assert np.array_equal(J, d["J"])
         assert np.abs(T - d["T"]).max() <= 1e-8 * max(1.0, np.abs(d["T"]).max())
+
+
+def test_c2_qb(c2):
+    """Blocked adaptive QB (Alg. 7) at full size, b = 32, q = 1, tol = 0.07, at
+    most 10 blocks (on sigma_j = 1/j the residual crosses tol with the 8th):
+    the same blocks, Q, B and residual as the oracle's."""
+    import paper_1502_05366_amd as R
+    A = c2["A"]
+    Q, B, res, Rd, info = R.qb(c2["Ad"], 32, 10, 1, 0.07, SEED)
+    Q, B = Q.cpu().numpy(), B.cpu().numpy()
+    del Rd
+    d = O.qb_blocked(A, 32, 10, 0.07, 1, SEED)
+    assert d["nblocks"] < 10 and d["norms"][-1] < 0.07
+    assert Q.shape[1] == d["Q"].shape[1]
+    assert np.abs(Q - d["Q"]).max() <= 1e-9
+    assert np.abs(B - d["B"]).max() <= 1e-9
+    assert abs(res - d["norms"][-1]) <= 1e-9
