@@ -12,7 +12,7 @@ GFLOP/s counts the algorithmic work of the RSVD only:
 (passes, Householder-count orthonormalization, U and V); the ID and CUR work
 is timed but not credited.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 """
 
 import argparse
@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "9921d9cd6b63dd684232ac6ec45a6ffb6822c60b5ee97c34a85fdbe0cfb3b21e",
-                "bytes": 4164107650}
+PASS_TRAFFIC = {"sources": "f56ac1f83047f386a32e3b0a036aca68094252e798aca62884df0e94999843df",
+                "bytes": 4588240000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 
 
@@ -282,6 +282,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32, BF16, left-sketch ID and blocked QB sections "
+                         "(for counter runs of the FP64 step and pass)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
@@ -393,15 +396,17 @@ def main():
     # FP32 accumulation, FP64 after the passes); A is converted once, untimed
     S64 = S.cpu().numpy()
     lowp = {}
-    for key, is_bf16 in (("fp32", False), ("bf16", True)):
+    for key, is_bf16 in (() if args.no_extras else (("fp32", False), ("bf16", True))):
         r = lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, is_bf16)
         Sl = r.pop("S")
         r["sigma_rel_err_vs_fp64"] = float(np.max(np.abs(Sl - S64) / S64))
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
-    idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
-    qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
+    idl = qbr = None
+    if not args.no_extras:
+        idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
+        qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
 
     out = {
         "metric": METRIC,
@@ -430,10 +435,11 @@ def main():
         "end_to_end_frac_of_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS, 4),
         "info": [int(st[0]), int(st[1])],
     }
-    out["fp32"] = lowp["fp32"]
-    out["bf16"] = lowp["bf16"]
-    out["id_left"] = idl
-    out["qb"] = qbr
+    if not args.no_extras:
+        out["fp32"] = lowp["fp32"]
+        out["bf16"] = lowp["bf16"]
+        out["id_left"] = idl
+        out["qb"] = qbr
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)
