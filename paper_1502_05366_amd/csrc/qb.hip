@@ -6,7 +6,7 @@
 //    matrix cores (K = b), subtracts them from A in place and adds the
 //    squares of the new entries; the workgroup's sum goes to part[tile].
 //    The kernel streams A once in and once out: it is bound by HBM.
-//  * sum_kernel: ||A||_F^2 = the partial sums added in tile order.
+//  * sum_kernel: ||A||_F^2 = the partial sums added in a fixed order.
 //  * transpose_kernel, sub_kernel: B_i rows from Bt, and X -= Y.
 #include "common.h"
 #include "internal.h"
@@ -28,6 +28,18 @@ __global__ __launch_bounds__(QB_NT) void qb_update_kernel(double* __restrict__ A
   const int li = lane & 15, lk = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.y * 64 + wave * 16;
   const int64_t c0 = (int64_t)blockIdx.x * 64;
+  // the wave's 16 x 64 entries of A are loaded first, so that they stream
+  // in from HBM while Q_i B_i is formed
+  double a0[4][4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int64_t col = c0 + ct * 16 + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + drow(lk, v);
+      a0[ct][v] = (row < m && col < n) ? A[row * lda + col] : 0.0;
+    }
+  }
   d4 acc[4];
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
@@ -50,9 +62,8 @@ __global__ __launch_bounds__(QB_NT) void qb_update_kernel(double* __restrict__ A
     for (int v = 0; v < 4; ++v) {
       const int64_t row = r0 + drow(lk, v);
       if (row < m && col < n) {
-        double* p = A + row * lda + col;
-        const double x = *p - acc[ct][v];
-        *p = x;
+        const double x = a0[ct][v] - acc[ct][v];
+        A[row * lda + col] = x;
         s = fma(x, x, s);
       }
     }
@@ -64,17 +75,30 @@ __global__ __launch_bounds__(QB_NT) void qb_update_kernel(double* __restrict__ A
     part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// out[0] = sum of part[0 .. np), thread t taking t, t + 256, ... in order
-__global__ __launch_bounds__(QB_NT) void sum_kernel(const double* __restrict__ part, int64_t np,
-                                                    double* __restrict__ out) {
-  __shared__ double red[QB_NT / 64];
+// out[0] = sum of part[0 .. np): thread t adds entries t, t + SUM_NT, ... in
+// four interleaved chains, then the chains, the waves and the threads are
+// added in a fixed order
+constexpr int SUM_NT = 1024;
+
+__global__ __launch_bounds__(SUM_NT) void sum_kernel(const double* __restrict__ part, int64_t np,
+                                                     double* __restrict__ out) {
+  __shared__ double red[SUM_NT / 64];
   const int tid = threadIdx.x;
-  double s = 0.0;
-  for (int64_t i = tid; i < np; i += QB_NT) s += part[i];
-  s = wave_allsum(s);
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = tid;
+  for (; i + 3 * SUM_NT < np; i += 4 * SUM_NT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] += part[i + u * SUM_NT];
+  }
+  for (; i < np; i += SUM_NT) c[0] += part[i];
+  double s = wave_allsum((c[0] + c[1]) + (c[2] + c[3]));
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  if (tid == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < SUM_NT / 64; ++w) t += red[w];
+    out[0] = t;
+  }
 }
 
 // B[t][c] = Bt[c][t] for t < b, c < n
@@ -110,7 +134,7 @@ hipError_t launch_qb_update(double* A, int64_t lda, int64_t m, int64_t n, const 
                      part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(QB_NT), 0, s, part, qb_update_tiles(m, n), norm2);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(SUM_NT), 0, s, part, qb_update_tiles(m, n), norm2);
   return hipGetLastError();
 }
 
