@@ -95,9 +95,11 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
     TC ra[4];
     TC rx[CBW];
 
-    // next-step loads with clamped addresses: every load is issued without a
-    // branch around it, and out-of-range elements are zeroed only when they
-    // are written to LDS, so no wait for the loads comes before that
+    // Next-step loads.  FP64 (CLAMP): clamped addresses, so every load is
+    // issued without a branch around it, and out-of-range elements are
+    // zeroed only when they are written to LDS (no wait for the loads comes
+    // before that).  FP32: guarded loads, which measured faster there.
+    constexpr bool CLAMP = sizeof(TC) == 8;
     bool oka[4], okx[CBW];
     auto gload = [&](int64_t kt) {
       const int64_t k0 = kt * BK;
@@ -109,7 +111,8 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
         for (int c = 0; c < 4; ++c) {
           const int64_t gk = k0 + a_c + c;
           oka[c] = rok && gk < g.K;
-          ra[c] = (TC)A[gic * g.lda + (gk < g.K ? gk : g.K - 1)];
+          if (CLAMP) ra[c] = (TC)A[gic * g.lda + (gk < g.K ? gk : g.K - 1)];
+          else ra[c] = oka[c] ? (TC)A[gi * g.lda + gk] : TC(0);
         }
       } else {
         const int64_t gk = k0 + a_r;
@@ -119,7 +122,8 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = row0 + a_c + c;
           oka[c] = kok && gi < g.M;
-          ra[c] = (TC)A[gkc * g.lda + (gi < g.M ? gi : g.M - 1)];
+          if (CLAMP) ra[c] = (TC)A[gkc * g.lda + (gi < g.M ? gi : g.M - 1)];
+          else ra[c] = oka[c] ? (TC)A[gk * g.lda + gi] : TC(0);
         }
       }
       const int64_t gk = k0 + x_r;
@@ -129,14 +133,17 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
       for (int c = 0; c < CBW; ++c) {
         const int64_t gj = col0 + x_c + c;
         okx[c] = kok && gj < g.L;
-        rx[c] = (TC)X[gkc * g.ldx + (gj < g.L ? gj : g.L - 1)];
+        if (CLAMP) rx[c] = (TC)X[gkc * g.ldx + (gj < g.L ? gj : g.L - 1)];
+        else rx[c] = okx[c] ? (TC)X[gk * g.ldx + gj] : TC(0);
       }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) As[buf][a_r * ALD + a_c + c] = oka[c] ? ra[c] : TC(0);
+      for (int c = 0; c < 4; ++c)
+        As[buf][a_r * ALD + a_c + c] = (CLAMP && !oka[c]) ? TC(0) : ra[c];
 #pragma unroll
-      for (int c = 0; c < CBW; ++c) Xs[buf][x_r * BN + x_c + c] = okx[c] ? rx[c] : TC(0);
+      for (int c = 0; c < CBW; ++c)
+        Xs[buf][x_r * BN + x_c + c] = (CLAMP && !okx[c]) ? TC(0) : rx[c];
     };
 
     gload(kb);
@@ -145,11 +152,13 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
     int buf = 0;
     for (int64_t kt = kb; kt < ke; ++kt) {
       const bool more = kt + 1 < ke;
+      if (!CLAMP && more) gload(kt + 1);
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        // issued inside the unrolled k loop, which lets the scheduler spread
-        // the loads among the first MFMAs (measured: Y = AX 1.75 -> 1.62 ms)
-        if (kk == 0 && more) gload(kt + 1);
+        // FP64: issued inside the unrolled k loop, which lets the scheduler
+        // spread the loads among the first MFMAs (measured: Y = AX 1.75 ->
+        // 1.62 ms)
+        if (CLAMP && kk == 0 && more) gload(kt + 1);
         const int k = kk * 4 + lk;
         TC av[2];
 #pragma unroll
