@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "f56ac1f83047f386a32e3b0a036aca68094252e798aca62884df0e94999843df",
-                "bytes": 4588240000}
+PASS_TRAFFIC = {"sources": "82fec966bfb40cab49e9d49221198db3c2ecdb25038d585385e2ecedba212a73",
+                "bytes": 4588130000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 
 
