@@ -12,7 +12,7 @@ import textwrap
 import numpy as np
 import pytest
 
-from oracle import dense, philox, rsvd as O
+from oracle import dense, grad as G, philox, rsvd as O
 from paper_1502_05366_amd import workloads as W
 
 
@@ -27,7 +27,7 @@ def _mutated(func, old, new):
 
 def _install(monkeypatch, func, old, new):
     mut = _mutated(func, old, new)
-    for mod in (dense, philox, O):
+    for mod in (dense, philox, O, G):
         if getattr(mod, func.__name__, None) is func:
             monkeypatch.setattr(mod, func.__name__, mut)
     return mut
@@ -117,7 +117,36 @@ def pin_cur_normal_equations():
     assert np.abs((res['U'] @ R - V.T) @ R.T).max() < 1e-12
 
 
+def pin_grad():
+    # central difference of the whole randomized SVD, q = 1, cotangents on
+    # U, sigma and V (the signs of the unperturbed singular pairs are kept
+    # for the perturbed ones)
+    m, n, k, p = 40, 30, 5, 3
+    A, _ = W.logspace_type(m, n, 1, seed=5)
+    g = np.random.default_rng(7)
+    dU, dS, dV = g.standard_normal((m, k)), g.standard_normal(k), g.standard_normal((n, k))
+    f0 = G.rsvd_forward_tape(A, k, p, 1, 11)
+
+    def align(U, V):
+        d = np.sign(np.sum(U * f0["U"], axis=0))
+        return U * d, V * d
+    dA, _ = G.rsvd_grad(A, k, p, 1, 11, dU, dS, dV)
+    E = g.standard_normal((m, n))
+    h = 1e-6
+
+    def L(M):
+        r = G.rsvd_forward_tape(M, k, p, 1, 11)
+        u, v = align(r["U"], r["V"])
+        return np.sum(dU * u) + np.sum(dS * r["S"]) + np.sum(dV * v)
+    fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
+    assert abs(fd - np.sum(dA * E)) < 1e-6 * max(1.0, abs(fd))
+
+
 MUTANTS = [
+    (G.qr_adjoint, "C = dQ + Q @ copyltu(M)", "C = dQ + Q @ np.tril(M)", pin_grad),
+    (G.qr_adjoint, "M = -(dQ.T @ Q)", "M = dQ.T @ Q", pin_grad),
+    (G.svd_adjoint, "F[off] = 1.0 / D[off]", "F[off] = -1.0 / D[off]", pin_grad),
+    (G.rsvd_grad, "dA += Qy @ dZ.T", "pass", pin_grad),
     (dense.householder_qr, "beta = 2.0 / np.dot(v, v)", "beta = 1.0 / np.dot(v, v)", pin_qr),
     (dense.householder_qr, "Q[j:, j:] -= np.outer(beta * v, w)", "Q[j:, j:] += np.outer(beta * v, w)", pin_qr),
     (dense.jacobi_svd, "sn = cs * t", "sn = -cs * t", pin_jacobi),
