@@ -195,6 +195,80 @@ def qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1):
                     "write per block, per second"}
 
 
+GRAD_K, GRAD_P, GRAD_Q, GRAD_SEED = 64, 16, 2, 0x5EED0005
+
+
+def grad_step(lib, h, args, stream, sp, P, e0, e1):
+    """Time rsvd_svd_grad on the 8192 x 4096 sigma_j = 1/j Kronecker-Haar A
+    (k = 64, p = 16, q = 2) in FP64: the recomputed forward alone (U, S, V and
+    ||A - Q Q^T A||_F^2), and forward + adjoint for the two losses sum sigma_i
+    and ||A - Q Q^T A||_F^2 (cotangents dS = 1, dres = 1)."""
+    import torch
+    from paper_1502_05366_amd import api, workloads as W
+
+    dev = torch.device("cuda:0")
+    k, p, q, seed = GRAD_K, GRAD_P, GRAD_Q, GRAD_SEED
+    A_np, _ = W.c5_matrix()
+    m, n = A_np.shape
+    l = min(k + p, m, n)
+    A = torch.from_numpy(A_np).to(dev)
+    del A_np
+    wb = lib.rsvd_svd_grad_workspace_bytes(api.F64, m, n, k, p, q)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    U = torch.empty((m, k), dtype=torch.float64, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty((n, k), dtype=torch.float64, device=dev)
+    r2 = torch.empty(1, dtype=torch.float64, device=dev)
+    dS = torch.ones(k, dtype=torch.float64, device=dev)
+    dres = torch.ones(1, dtype=torch.float64, device=dev)
+    dA = torch.empty((m, n), dtype=torch.float64, device=dev)
+
+    def call(backward):
+        rc = lib.rsvd_svd_grad(h, api.F64, m, n, k, p, q, seed, P(A), n, None, k, P(dS), None, k,
+                               P(dres), P(dA) if backward else None, n, P(U), k, P(S), P(V), k,
+                               P(r2), P(work), wb, P(info), sp)
+        if rc != 0:
+            raise RuntimeError("rsvd_svd_grad returned %d" % rc)
+
+    res = {}
+    reps = max(1, min(args.steps, 10))
+    for key, bwd in (("forward", False), ("forward_backward", True)):
+        for _ in range(max(1, args.warmup)):
+            call(bwd)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            call(bwd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[key] = e0.elapsed_time(e1) / reps
+    ms_f, ms_fb = res["forward"], res["forward_backward"]
+    # reads of A: forward 2q+2 passes + the residual; adjoint 2q+1 passes +
+    # the 2 dres A term; one write of dA
+    a_bytes = 8.0 * m * n
+    fb_bytes = a_bytes * ((2 * q + 3) + (2 * q + 2) + 1)
+    fb_flops = 2.0 * m * n * l * ((2 * q + 3) + (2 * q + 1) + (2 * q + 2))
+    st = info.cpu().numpy()
+    log("grad: forward %.3f ms, forward+adjoint %.3f ms" % (ms_f, ms_fb))
+    out = {"ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
+           "ms_adjoint": round(ms_fb - ms_f, 4),
+           "value_gflops": round(fb_flops / (ms_fb * 1e-3) / 1e9, 2),
+           "a_traffic_GBs": round(fb_bytes / (ms_fb * 1e-3) / 1e9, 1),
+           "sigma_1": float(S[0].item()), "resid2": float(r2.item()),
+           "info": [int(st[0]), int(st[1])],
+           "workload": "FP64 A %dx%d, sigma_j=1/j, Kronecker-Haar factors, k=%d p=%d q=%d; "
+                       "losses sum sigma_i and ||A - QQ^T A||_F^2 (dS = 1, dres = 1)"
+                       % (m, n, k, p, q),
+           "note": "one rsvd_svd_grad call per step (recomputed forward, then the adjoint); "
+                   "flops = 2mnl ((2q+3) forward + (2q+1) adjoint passes + (2q+2) rank-l "
+                   "terms of dA); a_traffic = (4q+6) reads of A + one write of dA, per "
+                   "second"}
+    del A, dA, work
+    torch.cuda.empty_cache()
+    return out
+
+
 def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf16):
     """Time rsvd_decompose with A stored in BF16 (bf16=True) or FP32, and one
     pass over A of that storage type."""
@@ -283,7 +357,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32, BF16, left-sketch ID and blocked QB sections "
+                    help="skip the FP32, BF16, left-sketch ID, blocked QB and gradient sections "
                          "(for counter runs of the FP64 step and pass)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -403,10 +477,11 @@ def main():
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
-    idl = qbr = None
+    idl = qbr = grd = None
     if not args.no_extras:
         idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
         qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
+        grd = grad_step(lib, h, args, stream, sp, P, e0, e1)
 
     out = {
         "metric": METRIC,
@@ -440,6 +515,7 @@ def main():
         out["bf16"] = lowp["bf16"]
         out["id_left"] = idl
         out["qb"] = qbr
+        out["grad"] = grd
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

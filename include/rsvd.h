@@ -142,6 +142,36 @@ int rsvd_qb(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int b, int M, int 
             int32_t* nblocks, double* resid, void* work, size_t work_bytes, int32_t* info,
             void* stream);
 
+/* Reverse-mode derivative of the rank-k randomized SVD with the Gaussian sketch
+ * held fixed (FP64 only; q <= 8).  The forward map is the one of rsvd_svd
+ * (Alg. 5, re-orthonormalization after every product as in Sec. 3.2; the small
+ * SVD as in Sec. 3.2 from the QR of B^T): the call recomputes it, keeping its
+ * bases and triangular factors in the workspace, so a caller stores only A.
+ *
+ * Cotangents (device pointers, each may be NULL for zero): dU (m x k, lddu),
+ * dS (k), dV (n x k, lddv), dres (one double: the cotangent of
+ * resid2 = ||A - Q Q^T A||_F^2, Q the basis of the range finder).  With dA
+ * non-NULL (m x n, ldda >= n) the call writes
+ *   dA = d/dA [ <dU, U> + <dS, S> + <dV, V> + dres * resid2 ],
+ * the adjoint of every product with A (dA += dC X^T, dX = A^T dC), of every
+ * thin QR Y = Q R (dY = (dQ + Q copyltu(R dR^T - dQ^T Q)) R^{-T}) and of the
+ * SVD of the l x l factor (the 1 / (s_j^2 - s_i^2) formula).  The map is
+ * differentiable where the Y's have full rank and the l singular values of the
+ * small factor are distinct and non-zero; elsewhere dA is not finite.
+ * Forward outputs, each optional: U (m x k, ldu), S (k), V (n x k, ldv) (the
+ * same values as rsvd_svd with this seed) and resid2 (one double, formed as
+ * the sum of squares of A - Q B).  At least one of dA, U, S, V, resid2 must
+ * be non-NULL.  A is not modified; it must not overlap dA.
+ * F32 / BF16: RSVD_ERR_UNSUPPORTED.  Workspace: rsvd_svd_grad_workspace_bytes
+ * (0 for invalid sizes). */
+size_t rsvd_svd_grad_workspace_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q);
+int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                  uint64_t seed, const double* A, int64_t lda, const double* dU, int64_t lddu,
+                  const double* dS, const double* dV, int64_t lddv, const double* dres,
+                  double* dA, int64_t ldda, double* U, int64_t ldu, double* S, double* V,
+                  int64_t ldv, double* resid2, void* work, size_t work_bytes, int32_t* info,
+                  void* stream);
+
 /* Rank-k CUR from the two-sided ID (Sec. 2.5, Alg. 3; Sec. 3.6): Jc = skeleton
  * columns of the ID above, Jr = the k rows chosen by k steps of column-pivoted
  * QR of C^T (C = A(:, Jc)), and Ucur = V^T R^dagger (k x k FP64, lduc >= k),

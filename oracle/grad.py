@@ -84,12 +84,19 @@ def rsvd_forward_tape(A, k, p, q, seed):
     Qh, Rh = householder_qr(Bt)
     Uh, s, Vh, _, _ = jacobi_svd(Rh)
     return dict(A=A, Om=Om, tape=tape, Q=Q, Rq=Rq, Qh=Qh, Rh=Rh, Uh=Uh, s=s, Vh=Vh, k=k,
-                U=Q @ Vh[:, :k], S=s[:k].copy(), V=Qh @ Uh[:, :k])
+                U=Q @ Vh[:, :k], S=s[:k].copy(), V=Qh @ Uh[:, :k],
+                resid2=float(np.sum((A - Q @ Bt.T) ** 2)))
 
 
-def rsvd_grad(A, k, p, q, seed, dU=None, dS=None, dV=None):
-    """dA = the gradient of <dU, U_k> + <dS, sigma> + <dV, V_k> with respect to
-    A (cotangents left out count as zero).  Returns (dA, forward dict)."""
+def rsvd_grad(A, k, p, q, seed, dU=None, dS=None, dV=None, dres=None):
+    """dA = the gradient of <dU, U_k> + <dS, sigma> + <dV, V_k>
+    + dres ||A - Q Q^T A||_F^2 with respect to A (cotangents left out count as
+    zero).  Returns (dA, forward dict).
+
+    The residual term uses ||A - Q Q^T A||_F^2 = ||A||_F^2 - ||Q^T A||_F^2
+    (Q^T Q = I) and ||Q^T A||_F = ||B^T||_F = ||Rh||_F, whose square is the sum
+    of all l squared singular values of Rh: its cotangent is 2 dres A directly
+    plus ds_i = -2 dres s_i through the chain."""
     f = rsvd_forward_tape(A, k, p, q, seed)
     A = f["A"]
     m, n = A.shape
@@ -108,6 +115,8 @@ def rsvd_grad(A, k, p, q, seed, dU=None, dS=None, dV=None):
         dUh[:, :k] = Qh.T @ dV
     if dS is not None:
         ds[:k] = dS
+    if dres is not None:
+        ds -= 2.0 * dres * s
     dRh = svd_adjoint(Uh, s, Vh, dUh, ds, dVh)
     dBt = qr_adjoint(Qh, f["Rh"], dQh, dRh)
     dA = Q @ dBt.T                     # B^T = A^T Q
@@ -119,4 +128,6 @@ def rsvd_grad(A, k, p, q, seed, dU=None, dS=None, dV=None):
         dA += Qy @ dZ.T                # Z = A^T Qy
         dY = qr_adjoint(Qy, Ry, A @ dZ)
     dA += dY @ f["Om"].T               # Y_0 = A Omega
+    if dres is not None:
+        dA += 2.0 * dres * A
     return dA, f

@@ -9,13 +9,15 @@ used for device memory and streams.  Names follow the C entry points:
     id_left(A, k, p, q, seed)    -> J, T, info         (ID from Y = Omega~ A, Alg. 6)
     qb(A, b, M, q, tol, seed)    -> Q, B, resid, R, info (blocked adaptive QB, Alg. 7)
     cur(A, k, p, q, seed)        -> Jc, Jr, U, info    (CUR from the two-sided ID)
+    svd_grad(A, k, p, q, seed, dU, dS, dV, dres) -> dA (adjoint, sketch fixed)
+    svd_diff(A, k, p, q, seed)   -> U, S, V, resid2    (torch.autograd.Function)
     decompose(A, k, p, q, seed)  -> dict with all three from one range finder
 
 and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
 """
 
 from .api import (  # noqa: F401
-    RsvdError, handle, svd, id, id_left, qb, cur, decompose, workspace_bytes, sketch, philox, pass_, orth,
-    small_svd, cpqr, INFO_ORTH_FALLBACK, INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER,
+    RsvdError, handle, svd, id, id_left, qb, cur, svd_grad, svd_diff, decompose, workspace_bytes,
+    sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK, INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER,
     F64, F32,
 )

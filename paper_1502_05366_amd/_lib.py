@@ -32,6 +32,11 @@ SIGNATURES = {
     "rsvd_qb": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, ctypes.c_double, c_u64,
                         c_ptr, c_i64, c_ptr, c_i64, c_ptr, c_i64, c_ptr, c_ptr, c_ptr, c_size,
                         c_ptr, c_ptr]),
+    "rsvd_svd_grad_workspace_bytes": (c_size, [c_int, c_i64, c_i64, c_int, c_int, c_int]),
+    "rsvd_svd_grad": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr,
+                              c_i64, c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_ptr, c_i64,
+                              c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_ptr, c_size, c_ptr,
+                              c_ptr]),
     "rsvd_id_left_workspace_bytes": (c_size, [c_int, c_i64, c_i64, c_int, c_int, c_int]),
     "rsvd_id_left": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr,
                              c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_size, c_ptr, c_ptr]),

@@ -233,6 +233,84 @@ def qb(A, b, M, q, tol, seed):
     return Q[:, :k], B[:k], res.value, R, info
 
 
+def svd_grad(A, k, p, q, seed, dU=None, dS=None, dV=None, dres=None, outputs=False):
+    """Reverse-mode derivative of the randomized SVD of an FP64 A (sketch fixed).
+
+    dU (m x k), dS (k), dV (n x k) and dres (a 0-dim or 1-element tensor, the
+    cotangent of ||A - Q Q^T A||_F^2) may be None for zero.  Returns dA, and
+    with outputs=True the tuple (dA, U, S, V, resid2) of the recomputed
+    forward.  With all cotangents None and outputs=True only the forward runs
+    (dA is None)."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    wb = lib.rsvd_svd_grad_workspace_bytes(dt, m, n, k, p, q)
+    if wb == 0:
+        raise RsvdError("invalid sizes or type")
+
+    def cot(t, shape):
+        if t is None:
+            return None
+        t = t.to(device=dev, dtype=torch.float64).reshape(shape)
+        return t.contiguous()
+
+    dU = cot(dU, (m, k))
+    dS = cot(dS, (k,))
+    dV = cot(dV, (n, k))
+    dres = cot(dres, (1,))
+    want_grad = any(t is not None for t in (dU, dS, dV, dres))
+    dA = torch.empty((m, n), dtype=torch.float64, device=dev) if want_grad else None
+    U = S = V = r2 = None
+    if outputs:
+        U = torch.empty((m, k), dtype=torch.float64, device=dev)
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        V = torch.empty((n, k), dtype=torch.float64, device=dev)
+        r2 = torch.empty(1, dtype=torch.float64, device=dev)
+    if dA is None and not outputs:
+        raise RsvdError("nothing to compute: no cotangent and outputs=False")
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    rc = lib.rsvd_svd_grad(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(dU),
+                           k, _ptr(dS), _ptr(dV), k, _ptr(dres), _ptr(dA), n, _ptr(U), k, _ptr(S),
+                           _ptr(V), k, _ptr(r2), _ptr(work), work.numel(), _ptr(info),
+                           _stream(dev))
+    _check(rc, "rsvd_svd_grad")
+    if outputs:
+        return dA, U, S, V, r2.reshape(())
+    return dA
+
+
+class _SvdFunction(torch.autograd.Function):
+    """U, S, V and ||A - Q Q^T A||_F^2 of the randomized SVD as a
+    differentiable function of A; the backward recomputes the forward."""
+
+    @staticmethod
+    def forward(ctx, A, k, p, q, seed):
+        _, U, S, V, r2 = svd_grad(A, k, p, q, seed, outputs=True)
+        ctx.save_for_backward(A)
+        ctx.cfg = (k, p, q, seed)
+        ctx.set_materialize_grads(False)
+        return U, S, V, r2
+
+    @staticmethod
+    def backward(ctx, dU, dS, dV, dr2):
+        (A,) = ctx.saved_tensors
+        if all(t is None for t in (dU, dS, dV, dr2)):
+            return None, None, None, None, None
+        k, p, q, seed = ctx.cfg
+        dA = svd_grad(A, k, p, q, seed, dU=dU, dS=dS, dV=dV, dres=dr2)
+        return dA.to(A.dtype), None, None, None, None
+
+
+def svd_diff(A, k, p, q, seed):
+    """Differentiable randomized SVD of an FP64 A: (U, S, V, resid2) with
+    resid2 = ||A - Q Q^T A||_F^2; gradients flow to A through the library's
+    adjoint (sketch fixed)."""
+    return _SvdFunction.apply(A, k, p, q, seed)
+
+
 def cur(A, k, p, q, seed):
     """Rank-k CUR: Jc (k), Jr (k), U (k x k FP64), info; A ~ A[:, Jc] U A[Jr, :]."""
     lib = _lib.load()

@@ -128,12 +128,42 @@ int64_t qb_update_tiles(int64_t m, int64_t n);
 hipError_t launch_qb_update(double* A, int64_t lda, int64_t m, int64_t n, const double* Q,
                             int64_t ldq, const double* Bt, int64_t ldbt, int b, double* part,
                             double* norm2, hipStream_t s);
+// *norm2 = ||A - Q Bt^T||_F^2 without writing A (part as above)
+hipError_t launch_resid2(const double* A, int64_t lda, int64_t m, int64_t n, const double* Q,
+                         int64_t ldq, const double* Bt, int64_t ldbt, int b, double* part,
+                         double* norm2, hipStream_t s);
 // B[t][c] = Bt[c][t] (t < b, c < n)
 hipError_t launch_transpose(const double* Bt, int64_t ldbt, int64_t n, int b, double* B,
                             int64_t ldb, hipStream_t s);
 // X -= Y (rows x cols)
 hipError_t launch_sub(double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t rows,
                       int cols, hipStream_t s);
+
+// ------------------------------------------------------------------ grad --
+// Reverse-mode pieces of the randomized SVD (FP64).
+constexpr int OUTER_MAX = 18;   // 2q + 2 terms for q <= 8
+struct OuterTerms {
+  const double* X[OUTER_MAX];   // m x l each (ld ldx)
+  const double* W[OUTER_MAX];   // n x l each (ld ldw)
+  int64_t ldx, ldw;
+  int count, l;
+};
+// out = (F o (Pu - Pu^T)) S + diag(ds) + S (F o (Pv - Pv^T)), F_ij = 1/(s_j^2 - s_i^2),
+// ds_i = dS_i (i < k; dS may be null) - 2 dres[0] s_i (dres, a device scalar, may be null)
+hipError_t launch_svd_inner(const double* Pu, const double* Pv, int64_t ldp, const double* s,
+                            const double* dS, int k, const double* dres, int l, double* out,
+                            int64_t ldo, hipStream_t st);
+// Mc = copyltu(-P + Qm) (Qm may be NULL), l x l, P and Qm with leading dimension ld
+hipError_t launch_copyltu(const double* P, const double* Qm, int64_t ld, int l, double* Mc,
+                          int64_t ldm, hipStream_t st);
+// X = 0 (rows x cols)
+hipError_t launch_zero(double* X, int64_t ldx, int64_t rows, int cols, hipStream_t st);
+// X += Y (rows x cols)
+hipError_t launch_add(double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t rows,
+                      int cols, hipStream_t st);
+// dA = sum_t X_t W_t^T (+ 2 dres[0] A when dres is not null), m x n
+hipError_t launch_outer(const OuterTerms& t, int64_t m, int64_t n, const double* A, int64_t lda,
+                        const double* dres, double* dA, int64_t ldda, hipStream_t st);
 
 // ------------------------------------------------------------------- cur --
 // atype: element type of A, 0 FP64, 1 FP32, 2 BF16

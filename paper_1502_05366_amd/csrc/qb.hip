@@ -5,7 +5,9 @@
 //    64 x 64 tile of A; wave w forms rows 16w .. 16w+15 of Q_i B_i on the
 //    matrix cores (K = b), subtracts them from A in place and adds the
 //    squares of the new entries; the workgroup's sum goes to part[tile].
-//    The kernel streams A once in and once out: it is bound by HBM.
+//    The kernel streams A once in and once out: it is bound by HBM.  Without
+//    STORE it only forms ||A - Q_i B_i||_F^2 (the residual of a QB
+//    factorization), reading A once.
 //  * sum_kernel: ||A||_F^2 = the partial sums added in a fixed order.
 //  * transpose_kernel, sub_kernel: B_i rows from Bt, and X -= Y.
 #include "common.h"
@@ -16,6 +18,7 @@ namespace {
 
 constexpr int QB_NT = 256;
 
+template <bool STORE>
 __global__ __launch_bounds__(QB_NT) void qb_update_kernel(double* __restrict__ A, int64_t lda,
                                                           int64_t m, int64_t n,
                                                           const double* __restrict__ Q,
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(QB_NT) void qb_update_kernel(double* __restrict__ A
       const int64_t row = r0 + drow(lk, v);
       if (row < m && col < n) {
         const double x = a0[ct][v] - acc[ct][v];
-        A[row * lda + col] = x;
+        if (STORE) A[row * lda + col] = x;
         s = fma(x, x, s);
       }
     }
@@ -130,8 +133,22 @@ hipError_t launch_qb_update(double* A, int64_t lda, int64_t m, int64_t n, const 
                             double* norm2, hipStream_t s) {
   if (m <= 0 || n <= 0 || b < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
-  hipLaunchKernelGGL(qb_update_kernel, grid, dim3(QB_NT), 0, s, A, lda, m, n, Q, ldq, Bt, ldbt, b,
-                     part);
+  hipLaunchKernelGGL(qb_update_kernel<true>, grid, dim3(QB_NT), 0, s, A, lda, m, n, Q, ldq, Bt,
+                     ldbt, b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(SUM_NT), 0, s, part, qb_update_tiles(m, n), norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid2(const double* A, int64_t lda, int64_t m, int64_t n, const double* Q,
+                         int64_t ldq, const double* Bt, int64_t ldbt, int b, double* part,
+                         double* norm2, hipStream_t s) {
+  if (m <= 0 || n <= 0 || b < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
+  // the kernel does not write A when STORE is false
+  hipLaunchKernelGGL(qb_update_kernel<false>, grid, dim3(QB_NT), 0, s, const_cast<double*>(A), lda,
+                     m, n, Q, ldq, Bt, ldbt, b, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(SUM_NT), 0, s, part, qb_update_tiles(m, n), norm2);

@@ -495,6 +495,200 @@ hipError_t run_qb(Ctx& c, const QbBufs& w, int64_t m, int64_t n, int b, int M, i
   return hipSuccess;
 }
 
+// ---- reverse-mode derivative of the randomized SVD (sketch fixed) --------
+// The forward map is recomputed with its bases and triangular factors kept
+// (the caller stores only A): Y_0 = A Omega; for j < q: Qy_j Ry_j = Y_j,
+// Z_j = A^T Qy_j, Qz_j Rz_j = Z_j, Y_{j+1} = A Qz_j; Q Rq = Y_q; B^T = A^T Q;
+// Qh Rh = B^T; Rh = Uh diag(s) Vh^T (all l values).  The adjoint then walks
+// these steps backwards; dA collects one rank-l term per product with A.
+constexpr int GRAD_MAX_Q = (OUTER_MAX - 2) / 2;
+
+struct GradBufs {
+  double *Om, *Yt, *Zt, *Q, *Rq, *Qh, *Rh, *Wj, *sv, *Uh, *Vh;
+  double *Qy[GRAD_MAX_Q], *Ry[GRAD_MAX_Q], *Qz[GRAD_MAX_Q], *Rz[GRAD_MAX_Q];
+  double *dQ, *dQh, *dBt, *dY[GRAD_MAX_Q + 1], *dZ[GRAD_MAX_Q], *Cm, *G;
+  double *dUh, *dVh, *Pu, *Pv, *inner, *T1, *T2, *dRh, *Pm, *Rm, *Mc;
+  double *rpart;
+  OrthBufs ob;
+};
+
+size_t grad_part_bytes(const Shape& s) {
+  const int ncu = NCU_CAP;
+  size_t r = max_part(s);
+  auto upd = [&](int64_t M, int64_t K, int64_t L) {
+    if (M > 0 && K > 0 && L > 0) r = std::max(r, gemm_part_bytes(plan_gemm(M, K, L, ncu, 0), 8));
+  };
+  for (int64_t rows : {s.m, s.n}) {
+    upd(rows, s.k, s.l);      // dQ = dU Vh_k^T, dQh = dV Uh_k^T
+    upd(s.l, rows, s.k);      // Q^T dU, Qh^T dV
+    upd(s.l, rows, s.l);      // dQ^T Q
+    upd(rows, s.l, s.l);      // Q Mc
+    upd(rows, s.l, s.k);      // U = Q Vh_k, V = Qh Uh_k
+  }
+  upd(s.l, s.l, s.l);
+  return r;
+}
+
+size_t layout_grad(const Shape& s, void* base, GradBufs* out) {
+  Arena a(base);
+  GradBufs g;
+  std::memset(&g, 0, sizeof(g));
+  const int64_t m = s.m, n = s.n, lp = s.lp, rmax = std::max(m, n);
+  const size_t sq = (size_t)lp * lp;
+  g.Om = a.take<double>((size_t)n * lp);
+  g.Yt = a.take<double>((size_t)m * lp);
+  g.Zt = a.take<double>((size_t)n * lp);
+  for (int j = 0; j < s.q; ++j) {
+    g.Qy[j] = a.take<double>((size_t)m * lp);
+    g.Qz[j] = a.take<double>((size_t)n * lp);
+    g.Ry[j] = a.take<double>(sq);
+    g.Rz[j] = a.take<double>(sq);
+    g.dZ[j] = a.take<double>((size_t)n * lp);
+  }
+  for (int j = 0; j <= s.q; ++j) g.dY[j] = a.take<double>((size_t)m * lp);
+  g.Q = a.take<double>((size_t)m * lp);
+  g.Rq = a.take<double>(sq);
+  g.Qh = a.take<double>((size_t)n * lp);
+  g.Rh = a.take<double>(sq);
+  g.Wj = a.take<double>(jacobi_work_bytes(s.l) / sizeof(double) + 1);
+  g.sv = a.take<double>(lp);
+  g.Uh = a.take<double>(sq);
+  g.Vh = a.take<double>(sq);
+  g.dQ = a.take<double>((size_t)m * lp);
+  g.dQh = a.take<double>((size_t)n * lp);
+  g.dBt = a.take<double>((size_t)n * lp);
+  g.Cm = a.take<double>((size_t)rmax * lp);
+  g.G = a.take<double>((size_t)rmax * lp);
+  for (double** t : {&g.dUh, &g.dVh, &g.Pu, &g.Pv, &g.inner, &g.T1, &g.T2, &g.dRh, &g.Pm, &g.Rm,
+                     &g.Mc})
+    *t = a.take<double>(sq);
+  g.rpart = a.take<double>((size_t)qb_update_tiles(m, n) + 1);
+  g.ob = take_orth(a, rmax, s.lp, grad_part_bytes(s));
+  if (out) *out = g;
+  return a.off;
+}
+
+// C (M x L) = op(A) X for the small FP64 products of the adjoint
+hipError_t small_gemm(Ctx& c, const OrthBufs& ob, bool trans, const double* A, int64_t lda,
+                      const double* X, int64_t ldx, double* C, int64_t ldc, int64_t M, int64_t K,
+                      int64_t L) {
+  const GemmPlan p = plan_gemm(M, K, L, std::min(c.ncu, NCU_CAP), 0);
+  return launch_gemm(GEMM_DDDD, trans, A, lda, X, ldx, C, ldc, M, K, L, p, ob.part, ob.part_bytes,
+                     c.st);
+}
+
+// Adjoint of the thin QR Y = Qm R (rows x l):
+// dY = (dQm + Qm copyltu(R dR^T - dQm^T Qm)) R^{-T}   (dR may be null)
+hipError_t qr_adjoint(Ctx& c, const GradBufs& g, int lp, const double* Qm, const double* R,
+                      const double* dQm, const double* dR, int64_t rows, int l, double* dY) {
+  const OrthBufs& ob = g.ob;
+  RSVD_TRY(small_gemm(c, ob, true, dQm, lp, Qm, lp, g.Pm, lp, l, rows, l));   // dQm^T Qm
+  if (dR) {
+    RSVD_TRY(launch_transpose(dR, lp, l, l, g.T2, lp, c.st));
+    RSVD_TRY(small_gemm(c, ob, false, R, lp, g.T2, lp, g.Rm, lp, l, l, l));      // R dR^T
+  }
+  RSVD_TRY(launch_copyltu(g.Pm, dR ? g.Rm : nullptr, lp, l, g.Mc, lp, c.st));
+  RSVD_TRY(small_gemm(c, ob, false, Qm, lp, g.Mc, lp, g.Cm, lp, rows, l, l));
+  RSVD_TRY(launch_add(g.Cm, lp, dQm, lp, rows, l, c.st));
+  // dY R^T = Cm  <=>  R dY^T = Cm^T
+  return launch_backsub(R, lp, 1, g.Cm, 1, lp, l, rows, dY, 1, lp, c.st);
+}
+
+struct GradIO {
+  const double *dU, *dS, *dV, *dres;
+  int64_t lddu, lddv;
+  double* dA; int64_t ldda;
+  double *U, *S, *V, *resid2;
+  int64_t ldu, ldv;
+};
+
+hipError_t run_grad(Ctx& c, const Shape& s, const GradBufs& g, const double* A, int64_t lda,
+                    const GradIO& io) {
+  const int l = s.l, lp = s.lp, k = s.k, q = s.q;
+  const int64_t m = s.m, n = s.n;
+  const OrthBufs& ob = g.ob;
+  RSVD_TRY(launch_set_word(c.info, 0, c.st));
+  RSVD_TRY(launch_set_word(c.info + 1, 0, c.st));
+  // forward, with the bases and factors kept
+  RSVD_TRY(launch_sketch(false, c.seed, 0, 0, n, l, g.Om, lp, c.st));
+  RSVD_TRY(pass(c, 0, false, m, n, l, A, lda, g.Om, lp, g.Yt, lp, ob.part, ob.part_bytes));
+  for (int j = 0; j < q; ++j) {
+    RSVD_TRY(orth(c, ob, false, g.Yt, lp, m, l, g.Qy[j], false, lp, g.Ry[j], lp));
+    RSVD_TRY(pass(c, 0, true, m, n, l, A, lda, g.Qy[j], lp, g.Zt, lp, ob.part, ob.part_bytes));
+    RSVD_TRY(orth(c, ob, false, g.Zt, lp, n, l, g.Qz[j], false, lp, g.Rz[j], lp));
+    RSVD_TRY(pass(c, 0, false, m, n, l, A, lda, g.Qz[j], lp, g.Yt, lp, ob.part, ob.part_bytes));
+  }
+  RSVD_TRY(orth(c, ob, false, g.Yt, lp, m, l, g.Q, false, lp, g.Rq, lp));
+  RSVD_TRY(pass(c, 0, true, m, n, l, A, lda, g.Q, lp, g.Zt, lp, ob.part, ob.part_bytes));
+  RSVD_TRY(orth(c, ob, false, g.Zt, lp, n, l, g.Qh, false, lp, g.Rh, lp));
+  RSVD_TRY(launch_jacobi(g.Rh, lp, l, l, g.Wj, g.sv, g.Uh, lp, g.Vh, lp, JACOBI_MAX_SWEEPS,
+                         c.info, nullptr, true, c.st));
+  if (io.U) RSVD_TRY(small_gemm(c, ob, false, g.Q, lp, g.Vh, lp, io.U, io.ldu, m, l, k));
+  if (io.V) RSVD_TRY(small_gemm(c, ob, false, g.Qh, lp, g.Uh, lp, io.V, io.ldv, n, l, k));
+  if (io.S)
+    RSVD_TRY(hipMemcpyAsync(io.S, g.sv, sizeof(double) * k, hipMemcpyDeviceToDevice, c.st));
+  if (io.resid2)
+    RSVD_TRY(launch_resid2(A, lda, m, n, g.Q, lp, g.Zt, lp, l, g.rpart, io.resid2, c.st));
+  if (!io.dA) return hipSuccess;
+
+  // U_k = Q Vh_k, V_k = Qh Uh_k
+  RSVD_TRY(launch_zero(g.dVh, lp, l, l, c.st));
+  RSVD_TRY(launch_zero(g.dUh, lp, l, l, c.st));
+  if (io.dU) {
+    RSVD_TRY(launch_transpose(g.Vh, lp, l, k, g.T1, lp, c.st));                  // Vh_k^T
+    RSVD_TRY(small_gemm(c, ob, false, io.dU, io.lddu, g.T1, lp, g.dQ, lp, m, k, l));
+    RSVD_TRY(small_gemm(c, ob, true, g.Q, lp, io.dU, io.lddu, g.dVh, lp, l, m, k));
+  } else {
+    RSVD_TRY(launch_zero(g.dQ, lp, m, l, c.st));
+  }
+  if (io.dV) {
+    RSVD_TRY(launch_transpose(g.Uh, lp, l, k, g.T1, lp, c.st));                  // Uh_k^T
+    RSVD_TRY(small_gemm(c, ob, false, io.dV, io.lddv, g.T1, lp, g.dQh, lp, n, k, l));
+    RSVD_TRY(small_gemm(c, ob, true, g.Qh, lp, io.dV, io.lddv, g.dUh, lp, l, n, k));
+  } else {
+    RSVD_TRY(launch_zero(g.dQh, lp, n, l, c.st));
+  }
+  // Rh = Uh S Vh^T
+  RSVD_TRY(small_gemm(c, ob, true, g.Uh, lp, g.dUh, lp, g.Pu, lp, l, l, l));
+  RSVD_TRY(small_gemm(c, ob, true, g.Vh, lp, g.dVh, lp, g.Pv, lp, l, l, l));
+  RSVD_TRY(launch_svd_inner(g.Pu, g.Pv, lp, g.sv, io.dS, k, io.dres, l, g.inner, lp, c.st));
+  RSVD_TRY(small_gemm(c, ob, false, g.Uh, lp, g.inner, lp, g.T1, lp, l, l, l));
+  RSVD_TRY(launch_transpose(g.Vh, lp, l, l, g.T2, lp, c.st));
+  RSVD_TRY(small_gemm(c, ob, false, g.T1, lp, g.T2, lp, g.dRh, lp, l, l, l));
+  // B^T = Qh Rh
+  RSVD_TRY(qr_adjoint(c, g, lp, g.Qh, g.Rh, g.dQh, g.dRh, n, l, g.dBt));
+  // B^T = A^T Q: dA += Q dBt^T, dQ += A dBt
+  OuterTerms t;
+  std::memset(&t, 0, sizeof(t));
+  t.ldx = lp; t.ldw = lp; t.l = l;
+  auto term = [&](const double* X, const double* W) {
+    t.X[t.count] = X;
+    t.W[t.count] = W;
+    ++t.count;
+  };
+  term(g.Q, g.dBt);
+  RSVD_TRY(pass(c, 0, false, m, n, l, A, lda, g.dBt, lp, g.G, lp, ob.part, ob.part_bytes));
+  RSVD_TRY(launch_add(g.dQ, lp, g.G, lp, m, l, c.st));
+  // Y_q = Q Rq
+  RSVD_TRY(qr_adjoint(c, g, lp, g.Q, g.Rq, g.dQ, nullptr, m, l, g.dY[q]));
+  for (int j = q - 1; j >= 0; --j) {
+    // Y_{j+1} = A Qz_j
+    term(g.dY[j + 1], g.Qz[j]);
+    RSVD_TRY(pass(c, 0, true, m, n, l, A, lda, g.dY[j + 1], lp, g.G, lp, ob.part,
+                  ob.part_bytes));
+    // Z_j = Qz_j Rz_j
+    RSVD_TRY(qr_adjoint(c, g, lp, g.Qz[j], g.Rz[j], g.G, nullptr, n, l, g.dZ[j]));
+    // Z_j = A^T Qy_j
+    term(g.Qy[j], g.dZ[j]);
+    RSVD_TRY(pass(c, 0, false, m, n, l, A, lda, g.dZ[j], lp, g.G, lp, ob.part, ob.part_bytes));
+    // Y_j = Qy_j Ry_j
+    RSVD_TRY(qr_adjoint(c, g, lp, g.Qy[j], g.Ry[j], g.G, nullptr, m, l, g.dY[j]));
+  }
+  // Y_0 = A Omega
+  term(g.dY[0], g.Om);
+  return launch_outer(t, m, n, A, lda, io.dres, io.dA, io.ldda, c.st);
+}
+
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
   if (!h) return -1;
   if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
@@ -744,6 +938,51 @@ int rsvd_qb(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int b, int M, int 
   Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   return finish(run_qb(c, w, m, n, b, M, q, tol, static_cast<double*>(A), lda, Q, ldq, B, ldb,
                        nblocks, resid));
+}
+
+size_t rsvd_svd_grad_workspace_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  if (dtype != RSVD_F64 || m < 1 || n < 1 || k < 1 || k > std::min(m, n) || p < 0 || q < 0 ||
+      q > GRAD_MAX_Q)
+    return 0;
+  return layout_grad(make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q), nullptr, nullptr);
+}
+
+int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                  uint64_t seed, const double* A, int64_t lda, const double* dU, int64_t lddu,
+                  const double* dS, const double* dV, int64_t lddv, const double* dres,
+                  double* dA, int64_t ldda, double* U, int64_t ldu, double* S, double* V,
+                  int64_t ldv, double* resid2, void* work, size_t work_bytes, int32_t* info,
+                  void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_F64) return dtype == RSVD_F32 || dtype == RSVD_BF16 ? RSVD_ERR_UNSUPPORTED : -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (k < 1 || k > std::min(m, n)) return -5;
+  if (p < 0) return -6;
+  if (q < 0) return -7;
+  if (q > GRAD_MAX_Q) return RSVD_ERR_UNSUPPORTED;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (dU && lddu < k) return -12;
+  if (dV && lddv < k) return -15;
+  if (dA && ldda < n) return -18;
+  if (U && ldu < k) return -20;
+  if (V && ldv < k) return -23;
+  if (!dA && !U && !S && !V && !resid2) return -17;
+  if (!work) return -25;
+  if (!info) return -27;
+  const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
+  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  GradBufs g;
+  const size_t need = layout_grad(s, work, &g);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
+  GradIO io;
+  io.dU = dU; io.dS = dS; io.dV = dV; io.dres = dres; io.lddu = lddu; io.lddv = lddv;
+  io.dA = dA; io.ldda = ldda;
+  io.U = U; io.S = S; io.V = V; io.resid2 = resid2; io.ldu = ldu; io.ldv = ldv;
+  return finish(run_grad(c, s, g, A, lda, io));
 }
 
 int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,

@@ -104,6 +104,18 @@ def c2_matrix(seed=0xC0FFEE01, noise_std=1e-6):
     return A, s
 
 
+C5_SHAPE = (8192, 4096)
+
+
+def c5_matrix(seed=0xC0FFEE05):
+    """8192 x 4096, sigma_j = 1/j (j = 1..4096), Kronecker-Haar factors
+    U = U1[:, :64] kron U2 (U1 128^2, U2 64^2) and V = V1 kron V2 (64^2 each):
+    the workload of the differentiated randomized SVD."""
+    m, n = C5_SHAPE
+    s = 1.0 / np.arange(1, n + 1)
+    return kron_haar_matrix(128, 64, 64, 64, 64, s, seed), s
+
+
 def exact_rank_matrix(m, n, r, seed, decay=0.5):
     """Rank-r A = U diag(s) V^T with s_j = decay^j (j = 0..r-1)."""
     s = decay ** np.arange(r)

@@ -104,3 +104,37 @@ def test_step_workspace_queries(lib):
     assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 200) > 0
     assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 300) == 0
     assert lib.rsvd_pass_workspace_bytes(0, 0, 20000, 10000, 220) > 0
+
+
+def grad_call(lib, **kw):
+    a = dict(h=FAKE, dtype=0, m=100, n=80, k=10, p=5, q=1, seed=1, A=PTR, lda=80, dU=PTR, lddu=10,
+             dS=PTR, dV=PTR, lddv=10, dres=PTR, dA=PTR, ldda=80, U=NULLP, ldu=10, S=NULLP,
+             V=NULLP, ldv=10, r2=NULLP, work=PTR, wb=1 << 40, info=PTR, stream=NULLP)
+    a.update(kw)
+    return lib.rsvd_svd_grad(a['h'], a['dtype'], a['m'], a['n'], a['k'], a['p'], a['q'],
+                             a['seed'], a['A'], a['lda'], a['dU'], a['lddu'], a['dS'], a['dV'],
+                             a['lddv'], a['dres'], a['dA'], a['ldda'], a['U'], a['ldu'], a['S'],
+                             a['V'], a['ldv'], a['r2'], a['work'], a['wb'], a['info'],
+                             a['stream'])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(h=NULLP), -1), (dict(dtype=7), -2), (dict(dtype=1), 3), (dict(dtype=2), 3),
+    (dict(m=0), -3), (dict(n=0), -4), (dict(k=81), -5), (dict(p=-1), -6), (dict(q=-1), -7),
+    (dict(q=9), 3), (dict(A=NULLP), -9), (dict(lda=79), -10), (dict(lddu=9), -12),
+    (dict(lddv=9), -15), (dict(ldda=79), -18), (dict(U=PTR, ldu=9), -20),
+    (dict(V=PTR, ldv=9), -23), (dict(dA=NULLP), -17), (dict(work=NULLP), -25),
+    (dict(info=NULLP), -27), (dict(wb=16), 2),
+    (dict(k=250, p=10, m=400, n=300, lda=300, ldda=300, lddu=250, lddv=250), 3),
+])
+def test_svd_grad_argument_codes(lib, kw, code):
+    assert grad_call(lib, **kw) == code
+
+
+def test_svd_grad_workspace_query(lib):
+    w = lib.rsvd_svd_grad_workspace_bytes
+    assert w(0, 300, 200, 10, 6, 2) > w(0, 300, 200, 10, 6, 1) > 0
+    assert w(1, 300, 200, 10, 6, 1) == 0        # FP64 only
+    assert w(0, 300, 200, 10, 6, 9) == 0        # q <= 8
+    # the FP64 8192 x 4096, k = 64, p = 16, q = 2 case
+    assert w(0, 8192, 4096, 64, 16, 2) < 256 << 20

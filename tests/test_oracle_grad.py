@@ -91,3 +91,23 @@ def test_copyltu():
     M = np.arange(9.0).reshape(3, 3)
     C = G.copyltu(M)
     assert np.array_equal(C, C.T) and np.array_equal(np.tril(C), np.tril(M))
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_rsvd_grad_residual_central_difference(q):
+    """The residual term: ||A - Q Q^T A||_F^2 is formed directly from Q and A
+    in the forward, while its gradient goes through the singular values and
+    2 A; central differences of the direct sum check the two agree."""
+    m, n, k, p, seed = 50, 40, 5, 3, 21
+    A, _ = W.logspace_type(m, n, 1, seed=6)
+    g = np.random.default_rng(10 + q)
+    dres = 0.7
+    dA, f = G.rsvd_grad(A, k, p, q, seed, dres=dres)
+    E = g.standard_normal((m, n))
+    h = 1e-6
+    fp = G.rsvd_forward_tape(A + h * E, k, p, q, seed)["resid2"]
+    fm = G.rsvd_forward_tape(A - h * E, k, p, q, seed)["resid2"]
+    fd = dres * (fp - fm) / (2 * h)
+    assert abs(fd - np.sum(dA * E)) < 1e-6 * max(1.0, abs(fd))
+    # the identity behind it: resid2 = ||A||^2 - sum of all l squared values
+    assert abs(f["resid2"] - (np.sum(A * A) - np.sum(f["s"] ** 2))) < 1e-12 * np.sum(A * A)
