@@ -13,6 +13,7 @@ GFLOP/s counts the algorithmic work of the RSVD only:
 is timed but not credited.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+                       [--grad-only]
 """
 
 import argparse
@@ -359,6 +360,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32, BF16, left-sketch ID, blocked QB and gradient sections "
                          "(for counter runs of the FP64 step and pass)")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="run only the gradient section and print its JSON object "
+                         "(for kernel traces of rsvd_svd_grad)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
@@ -373,6 +377,15 @@ def main():
     lib = _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.grad_only:
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        r = grad_step(lib, api.handle(dev), args, stream, ctypes.c_void_p(stream.cuda_stream), P,
+                      e0, e1)
+        print(json.dumps({"grad": r}), flush=True)
+        return
     m, n = W.C2_SHAPE
     k, p, q, seed = 200, 20, 2, 0x5EED0001
     l = min(k + p, m, n)

@@ -11,10 +11,8 @@
 //    of ||A - Q Q^T A||_F^2 = ||A||_F^2 - sum_i s_i^2 (all l values).
 //  * copyltu_kernel: Mc = copyltu(-P + Q) (P = dQ^T Q, Q = R dR^T or none).
 //  * add_kernel, zero_kernel: X += Y, X = 0.
-//  * outer_kernel: dA = sum_t X_t W_t^T over the 2q + 2 rank-l terms of the
-//    passes (X_t m x l, W_t n x l), plus 2 dres A (the direct part of the
-//    derivative of ||A||_F^2), one 64 x 64 tile of dA per workgroup on the
-//    matrix cores; dA is written once, never read.
+// dA itself, the sum of the 2q + 2 rank-l terms, is formed by the low-rank
+// tile kernel.
 #include "common.h"
 #include "internal.h"
 
@@ -76,49 +74,6 @@ __global__ __launch_bounds__(GNT) void zero_kernel(double* __restrict__ X, int64
   X[r * ldx + c] = 0.0;
 }
 
-__global__ __launch_bounds__(GNT) void outer_kernel(OuterTerms t, int64_t m, int64_t n,
-                                                    const double* __restrict__ A, int64_t lda,
-                                                    const double* __restrict__ dres,
-                                                    double* __restrict__ dA, int64_t ldda) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.y * 64 + wave * 16;
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  const int64_t xr = r0 + li;
-  const bool rok = xr < m;
-  d4 acc[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int q = 0; q < t.count; ++q) {
-    const double* X = t.X[q];
-    const double* Wt = t.W[q];
-    for (int k0 = 0; k0 < t.l; k0 += 4) {
-      const int k = k0 + lk;
-      const double av = (rok && k < t.l) ? X[xr * t.ldx + k] : 0.0;     // X_t[row][k]
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int64_t col = c0 + ct * 16 + li;
-        const double bv = (col < n && k < t.l) ? Wt[col * t.ldw + k] : 0.0;   // W_t[col][k]
-        acc[ct] = Mfma<double>::mma(av, bv, acc[ct]);
-      }
-    }
-  }
-  const double alpha = dres ? 2.0 * dres[0] : 0.0;
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t col = c0 + ct * 16 + li;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = r0 + drow(lk, v);
-      if (row < m && col < n) {
-        double x = acc[ct][v];
-        if (dres) x = fma(alpha, A[row * lda + col], x);
-        dA[row * ldda + col] = x;
-      }
-    }
-  }
-}
-
 }  // namespace
 
 hipError_t launch_svd_inner(const double* Pu, const double* Pv, int64_t ldp, const double* s,
@@ -148,15 +103,6 @@ hipError_t launch_zero(double* X, int64_t ldx, int64_t rows, int cols, hipStream
   if (rows <= 0 || cols <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_kernel, dim3((unsigned)cdiv(rows * cols, GNT)), dim3(GNT), 0, st, X, ldx,
                      rows, cols);
-  return hipGetLastError();
-}
-
-hipError_t launch_outer(const OuterTerms& t, int64_t m, int64_t n, const double* A, int64_t lda,
-                        const double* dres, double* dA, int64_t ldda, hipStream_t st) {
-  if (t.count < 1 || t.count > OUTER_MAX || t.l < 1) return hipErrorInvalidValue;
-  if (m <= 0 || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
-  hipLaunchKernelGGL(outer_kernel, grid, dim3(GNT), 0, st, t, m, n, A, lda, dres, dA, ldda);
   return hipGetLastError();
 }
 

@@ -121,6 +121,26 @@ hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const doubl
                           int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,
                           int64_t x_c, hipStream_t s);
 
+// --------------------------------------------------------------- lowrank --
+// P = sum_t X_t W_t^T over count terms (X_t m x l, W_t n x l, row-major with
+// leading dimensions ldx / ldw; columns >= l are not read), FP64.
+constexpr int LR_MAX = 18;       // 2q + 2 terms of the derivative for q <= 8
+struct LowRank {
+  const double* X[LR_MAX];
+  const double* W[LR_MAX];
+  int64_t ldx, ldw;
+  int count, l;
+};
+// number of partial sums written by the norm modes (the size of `part`)
+int64_t lowrank_tiles(int64_t m, int64_t n);
+// out = P + 2 dres[0] A (the A term only when dres is not null); out m x n
+hipError_t launch_lowrank_out(const LowRank& t, int64_t m, int64_t n, const double* A,
+                              int64_t lda, const double* dres, double* out, int64_t ldo,
+                              hipStream_t st);
+// *norm2 = ||A - P||_F^2, with A = A - P written when store is true
+hipError_t launch_lowrank_sub(const LowRank& t, int64_t m, int64_t n, double* A, int64_t lda,
+                              bool store, double* part, double* norm2, hipStream_t st);
+
 // -------------------------------------------------------------------- qb --
 // A -= Q Bt^T (A m x n in place, Q m x b, Bt n x b; b <= 256) and
 // *norm2 = ||A||_F^2 of the result; part holds qb_update_tiles(m, n) doubles.
@@ -141,13 +161,6 @@ hipError_t launch_sub(double* X, int64_t ldx, const double* Y, int64_t ldy, int6
 
 // ------------------------------------------------------------------ grad --
 // Reverse-mode pieces of the randomized SVD (FP64).
-constexpr int OUTER_MAX = 18;   // 2q + 2 terms for q <= 8
-struct OuterTerms {
-  const double* X[OUTER_MAX];   // m x l each (ld ldx)
-  const double* W[OUTER_MAX];   // n x l each (ld ldw)
-  int64_t ldx, ldw;
-  int count, l;
-};
 // out = (F o (Pu - Pu^T)) S + diag(ds) + S (F o (Pv - Pv^T)), F_ij = 1/(s_j^2 - s_i^2),
 // ds_i = dS_i (i < k; dS may be null) - 2 dres[0] s_i (dres, a device scalar, may be null)
 hipError_t launch_svd_inner(const double* Pu, const double* Pv, int64_t ldp, const double* s,
@@ -161,9 +174,6 @@ hipError_t launch_zero(double* X, int64_t ldx, int64_t rows, int cols, hipStream
 // X += Y (rows x cols)
 hipError_t launch_add(double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t rows,
                       int cols, hipStream_t st);
-// dA = sum_t X_t W_t^T (+ 2 dres[0] A when dres is not null), m x n
-hipError_t launch_outer(const OuterTerms& t, int64_t m, int64_t n, const double* A, int64_t lda,
-                        const double* dres, double* dA, int64_t ldda, hipStream_t st);
 
 // ------------------------------------------------------------------- cur --
 // atype: element type of A, 0 FP64, 1 FP32, 2 BF16

@@ -501,7 +501,7 @@ hipError_t run_qb(Ctx& c, const QbBufs& w, int64_t m, int64_t n, int b, int M, i
 // Z_j = A^T Qy_j, Qz_j Rz_j = Z_j, Y_{j+1} = A Qz_j; Q Rq = Y_q; B^T = A^T Q;
 // Qh Rh = B^T; Rh = Uh diag(s) Vh^T (all l values).  The adjoint then walks
 // these steps backwards; dA collects one rank-l term per product with A.
-constexpr int GRAD_MAX_Q = (OUTER_MAX - 2) / 2;
+constexpr int GRAD_MAX_Q = (LR_MAX - 2) / 2;
 
 struct GradBufs {
   double *Om, *Yt, *Zt, *Q, *Rq, *Qh, *Rh, *Wj, *sv, *Uh, *Vh;
@@ -658,7 +658,7 @@ hipError_t run_grad(Ctx& c, const Shape& s, const GradBufs& g, const double* A, 
   // B^T = Qh Rh
   RSVD_TRY(qr_adjoint(c, g, lp, g.Qh, g.Rh, g.dQh, g.dRh, n, l, g.dBt));
   // B^T = A^T Q: dA += Q dBt^T, dQ += A dBt
-  OuterTerms t;
+  LowRank t;
   std::memset(&t, 0, sizeof(t));
   t.ldx = lp; t.ldw = lp; t.l = l;
   auto term = [&](const double* X, const double* W) {
@@ -686,7 +686,7 @@ hipError_t run_grad(Ctx& c, const Shape& s, const GradBufs& g, const double* A, 
   }
   // Y_0 = A Omega
   term(g.dY[0], g.Om);
-  return launch_outer(t, m, n, A, lda, io.dres, io.dA, io.ldda, c.st);
+  return launch_lowrank_out(t, m, n, A, lda, io.dres, io.dA, io.ldda, c.st);
 }
 
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {

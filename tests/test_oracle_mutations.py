@@ -142,7 +142,23 @@ def pin_grad():
     assert abs(fd - np.sum(dA * E)) < 1e-6 * max(1.0, abs(fd))
 
 
+def pin_grad_residual():
+    # central difference of ||A - Q Q^T A||_F^2 formed directly from Q and A
+    m, n, k, p = 40, 30, 5, 3
+    A, _ = W.logspace_type(m, n, 1, seed=6)
+    g = np.random.default_rng(8)
+    dA, _ = G.rsvd_grad(A, k, p, 1, 11, dres=1.0)
+    E = g.standard_normal((m, n))
+    h = 1e-6
+    fp = G.rsvd_forward_tape(A + h * E, k, p, 1, 11)["resid2"]
+    fm = G.rsvd_forward_tape(A - h * E, k, p, 1, 11)["resid2"]
+    fd = (fp - fm) / (2 * h)
+    assert abs(fd - np.sum(dA * E)) < 1e-6 * max(1.0, abs(fd))
+
+
 MUTANTS = [
+    (G.rsvd_grad, "ds -= 2.0 * dres * s", "ds += 2.0 * dres * s", pin_grad_residual),
+    (G.rsvd_grad, "dA += 2.0 * dres * A", "pass", pin_grad_residual),
     (G.qr_adjoint, "C = dQ + Q @ copyltu(M)", "C = dQ + Q @ np.tril(M)", pin_grad),
     (G.qr_adjoint, "M = -(dQ.T @ Q)", "M = dQ.T @ Q", pin_grad),
     (G.svd_adjoint, "F[off] = 1.0 / D[off]", "F[off] = -1.0 / D[off]", pin_grad),
