@@ -13,7 +13,7 @@ GFLOP/s counts the algorithmic work of the RSVD only:
 is timed but not credited.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
-                       [--grad-only]
+                       [--grad-only] [--batch-only]
 """
 
 import argparse
@@ -270,6 +270,69 @@ def grad_step(lib, h, args, stream, sp, P, e0, e1):
     return out
 
 
+BATCH_P, BATCH_Q, BATCH_SEED = 8, 1, 0x5EED0004
+
+
+def batch_step(lib, args, stream, e0, e1):
+    """Time the batched randomized SVD of the 4096 uneven FP32 matrices
+    (m ~ U{64..2048}, n ~ U{64..1024}, k ~ U{4..64}, p = 8, q = 1,
+    sigma_j = exp(-j/8)): one rsvd_batch_svd call (queue reset + one
+    persistent kernel) per step, eagerly and as replays of a captured graph."""
+    import numpy as np
+    import torch
+    import paper_1502_05366_amd as R
+    from paper_1502_05366_amd import workloads as W
+
+    ms, ns, ks = W.c4_dims()
+    p, q = BATCH_P, BATCH_Q
+    As = W.c4_batch_torch(ms, ns, 0xC0FFEE04, "cuda")
+    plan = R.BatchPlan(ms, ns, ks, p, q)
+    buf = plan.pack(As)
+    del As
+    torch.cuda.empty_cache()
+    out = plan.outputs()
+    reps = max(1, min(args.steps, 5))
+    for _ in range(max(1, args.warmup)):
+        plan.run(buf, BATCH_SEED, out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        plan.run(buf, BATCH_SEED, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / reps
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(buf, BATCH_SEED, out)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+    ls = np.minimum(ks + p, np.minimum(ms, ns)).astype(np.float64)
+    mf, nf, kf = ms.astype(np.float64), ns.astype(np.float64), ks.astype(np.float64)
+    flops = float(np.sum(2 * (2 * q + 2) * mf * nf * ls
+                         + (q + 1) * (2 * mf * ls ** 2 - 2.0 / 3 * ls ** 3)
+                         + (q + 1) * (2 * nf * ls ** 2 - 2.0 / 3 * ls ** 3)
+                         + 2 * (mf + nf) * ls * kf))
+    abytes = float(np.sum(4.0 * mf * nf)) * (2 * q + 2)
+    st = out[3].cpu().numpy()
+    log("batch: %.3f ms per batch (graph replay %.3f ms)" % (ms_eager, ms_graph))
+    return {"ms_per_batch": round(ms_eager, 4), "ms_per_batch_graph": round(ms_graph, 4),
+            "matrices": int(len(ms)), "matrices_per_s": round(len(ms) / (ms_graph * 1e-3), 1),
+            "value_gflops": round(flops / (ms_graph * 1e-3) / 1e9, 2),
+            "a_traffic_GBs": round(abytes / (ms_graph * 1e-3) / 1e9, 1),
+            "a_bytes_per_batch": abytes, "info": [int(st[0]), int(st[1])],
+            "workload": "4096 FP32 matrices, m~U{64..2048}, n~U{64..1024}, k~U{4..64}, "
+                        "p=8, q=1, sigma_j=exp(-j/8); one persistent launch per batch",
+            "note": "GFLOP/s = sum over matrices of 2(2q+2)mnl + (q+1)(2ml^2-2l^3/3) + "
+                    "(q+1)(2nl^2-2l^3/3) + 2(m+n)lk per graph replay; a_traffic = (2q+2) "
+                    "reads of every A_i per replay"}
+
+
 def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf16):
     """Time rsvd_decompose with A stored in BF16 (bf16=True) or FP32, and one
     pass over A of that storage type."""
@@ -358,11 +421,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32, BF16, left-sketch ID, blocked QB and gradient sections "
+                    help="skip the FP32, BF16, left-sketch ID, blocked QB, gradient and batch "
+                         "sections "
                          "(for counter runs of the FP64 step and pass)")
     ap.add_argument("--grad-only", action="store_true",
                     help="run only the gradient section and print its JSON object "
                          "(for kernel traces of rsvd_svd_grad)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched section and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
@@ -377,6 +443,12 @@ def main():
     lib = _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batch_only:
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        print(json.dumps({"batch": batch_step(lib, args, stream, e0, e1)}), flush=True)
+        return
     if args.grad_only:
         stream = torch.cuda.current_stream(dev)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -490,11 +562,12 @@ def main():
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
-    idl = qbr = grd = None
+    idl = qbr = grd = bat = None
     if not args.no_extras:
         idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
         qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
         grd = grad_step(lib, h, args, stream, sp, P, e0, e1)
+        bat = batch_step(lib, args, stream, e0, e1)
 
     out = {
         "metric": METRIC,
@@ -529,6 +602,7 @@ def main():
         out["id_left"] = idl
         out["qb"] = qbr
         out["grad"] = grd
+        out["batch"] = bat
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

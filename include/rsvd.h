@@ -67,6 +67,7 @@ enum {
 };
 
 typedef struct rsvd_handle_s* rsvd_handle_t;
+typedef struct rsvd_batch_s* rsvd_batch_t;
 
 /* Operation selector of rsvd_workspace_bytes. */
 enum { RSVD_OP_SVD = 1, RSVD_OP_ID = 2, RSVD_OP_CUR = 4 };
@@ -171,6 +172,45 @@ int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p
                   double* dA, int64_t ldda, double* U, int64_t ldu, double* S, double* V,
                   int64_t ldv, double* resid2, void* work, size_t work_bytes, int32_t* info,
                   void* stream);
+
+/* Batched randomized SVD: `count` independent FP32 matrices A_i (m_i x n_i,
+ * rank k_i, the same p and q), each decomposed as by rsvd_svd (Alg. 5 with
+ * re-orthonormalization after every product, Sec. 3.2; the small SVD from the
+ * QR of B_i^T) in one persistent launch: the workgroups take matrices from a
+ * work queue in decreasing order of work, one matrix per workgroup at a time
+ * (the matrices are independent, as the blocks of Alg. 8 are).  Omega_i is
+ * Philox stream 0 with batch index i under the call's seed.  Limits:
+ * l_i = min(k_i + p, m_i, n_i) <= 80.  Products on the FP32 matrix cores
+ * (FP32 accumulation); orth (CholeskyQR2), the Jacobi SVD and U, V in FP64.
+ * The orth does not replace dependent columns: a Cholesky pivot below
+ * 1e-13 G_jj gives a unit row of R and sets info bit 1.
+ *
+ * rsvd_batch_create: host arrays m, n (int64) and k (int32) of `count`
+ *   entries; the plan keeps its own copy.  Codes: -i for an invalid i-th
+ *   argument, RSVD_ERR_UNSUPPORTED when some l_i exceeds 80.
+ * rsvd_batch_layout: the packed layouts (host outputs, each may be NULL):
+ *   A_i at element a_off[i] of one FP32 buffer, row-major with leading
+ *   dimension lda[i] = n_i rounded up to a multiple of 4 (the buffer must be
+ *   16-byte aligned); U_i (m_i x k_i FP32, ld k_i) at u_off[i]; S_i (k_i FP64,
+ *   descending) at s_off[i]; V_i (n_i x k_i FP32, ld k_i) at v_off[i]; the
+ *   totals in a_elems, u_elems, s_elems, v_elems.
+ * rsvd_batch_prepare: copies the plan's descriptor table into the workspace
+ *   (rsvd_batch_workspace_bytes bytes, 256-byte aligned) and synchronizes the
+ *   stream; once per workspace, outside any stream capture.
+ * rsvd_batch_svd: launches only kernels (a queue reset and the persistent
+ *   kernel), so it may be captured into a graph and replayed; calls that
+ *   share a workspace must not overlap.  info (2 int32, device) as for the
+ *   other calls. */
+int rsvd_batch_create(rsvd_handle_t h, int64_t count, const int64_t* m, const int64_t* n,
+                      const int32_t* k, int p, int q, rsvd_batch_t* plan);
+int rsvd_batch_destroy(rsvd_batch_t plan);
+int rsvd_batch_layout(rsvd_batch_t plan, int64_t* a_elems, int64_t* u_elems, int64_t* s_elems,
+                      int64_t* v_elems, int64_t* a_off, int64_t* lda, int64_t* u_off,
+                      int64_t* s_off, int64_t* v_off);
+size_t rsvd_batch_workspace_bytes(rsvd_batch_t plan);
+int rsvd_batch_prepare(rsvd_batch_t plan, void* work, size_t work_bytes, void* stream);
+int rsvd_batch_svd(rsvd_batch_t plan, uint64_t seed, const float* A, float* U, double* S, float* V,
+                   void* work, size_t work_bytes, int32_t* info, void* stream);
 
 /* Rank-k CUR from the two-sided ID (Sec. 2.5, Alg. 3; Sec. 3.6): Jc = skeleton
  * columns of the ID above, Jr = the k rows chosen by k steps of column-pivoted

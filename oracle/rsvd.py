@@ -9,6 +9,9 @@ bench's cpu_baseline leg may use it.
                   Y = A Z }; Q = orth(Y).
 ``rsvd``          Alg. 5 lines 11-15: B^T = A^T Q, [Qh, Rh] = qr(B^T, 0),
                   [Uh, S, Vh] = svd(Rh), U_k = Q Vh(:, 1:k), V_k = Qh Uh(:, 1:k).
+``batch_rsvd``    ``rsvd`` of every matrix of a batch, matrix i with the sketch of
+                  batch index i (the matrices are independent, as the blocks
+                  of Alg. 8 are).
 ``rsvd_fig1``     Fig. 1: SVD of B = Q^T A directly (cross-check).
 ``rsvd_alg4``     Alg. 4 (Version I): eigen-decomposition of B B^T (cross-check).
 ``qb_id``         ID from B = Q^T A (Sec. 3.5, last part): k-step CPQR of B gives
@@ -39,16 +42,17 @@ def sample_size(m, n, k, p):
     return min(k + p, m, n)
 
 
-def range_finder(A, k, p, q, seed):
+def range_finder(A, k, p, q, seed, batch=0):
     """Q (m x l) with orthonormal columns such that Q Q^T A ~ A.
 
     Alg. 5 lines 1-10 with s = 1: orthonormalize before every product with
     A or A^T (the second scheme of Sec. 3.2), then a final Q = orth(Y).
+    Omega comes from Philox stream 0 with batch index ``batch``.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = sample_size(m, n, k, p)
-    Omega = philox.sketch(seed, n, l)
+    Omega = philox.sketch(seed, n, l, batch=batch)
     Y = A @ Omega
     for _ in range(q):
         Qy = orth(Y)
@@ -58,13 +62,13 @@ def range_finder(A, k, p, q, seed):
     return orth(Y)
 
 
-def rsvd(A, k, p, q, seed, return_details=False):
+def rsvd(A, k, p, q, seed, return_details=False, batch=0):
     """Rank-k randomized SVD, Alg. 5 (QR of B^T, SVD of the l x l R_hat).
 
     Returns U_k (m x k), sigma (k,), V_k (n x k) with A ~ U_k diag(sigma) V_k^T.
     """
     A = np.asarray(A, dtype=np.float64)
-    Q = range_finder(A, k, p, q, seed)
+    Q = range_finder(A, k, p, q, seed, batch=batch)
     Bt = A.T @ Q                              # n x l, = B^T
     Qh, Rh = householder_qr(Bt)               # B^T = Qh Rh
     Uh, s, Vh, sweeps, conv = jacobi_svd(Rh)  # Rh = Uh diag(s) Vh^T
@@ -74,6 +78,13 @@ def rsvd(A, k, p, q, seed, return_details=False):
         return U, s[:k], V, dict(Q=Q, Bt=Bt, Qh=Qh, Rh=Rh, s_all=s,
                                  sweeps=sweeps, converged=conv)
     return U, s[:k], V
+
+
+def batch_rsvd(As, ks, p, q, seed):
+    """The randomized SVD of each matrix of a batch on its own: matrix i uses
+    the sketch of Philox stream 0 with batch index i.  Returns a list of
+    (U_k, sigma, V_k)."""
+    return [rsvd(A, k, p, q, seed, batch=i) for i, (A, k) in enumerate(zip(As, ks))]
 
 
 def rsvd_fig1(A, k, p, q, seed):

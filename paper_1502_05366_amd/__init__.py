@@ -11,13 +11,14 @@ used for device memory and streams.  Names follow the C entry points:
     cur(A, k, p, q, seed)        -> Jc, Jr, U, info    (CUR from the two-sided ID)
     svd_grad(A, k, p, q, seed, dU, dS, dV, dres) -> dA (adjoint, sketch fixed)
     svd_diff(A, k, p, q, seed)   -> U, S, V, resid2    (torch.autograd.Function)
+    BatchPlan(ms, ns, ks, p, q)  -> batched RSVD of FP32 matrices in one persistent launch
     decompose(A, k, p, q, seed)  -> dict with all three from one range finder
 
 and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
 """
 
 from .api import (  # noqa: F401
-    RsvdError, handle, svd, id, id_left, qb, cur, svd_grad, svd_diff, decompose, workspace_bytes,
-    sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK, INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER,
-    F64, F32,
+    RsvdError, handle, svd, id, id_left, qb, cur, svd_grad, svd_diff, BatchPlan, decompose,
+    workspace_bytes, sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK,
+    INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32,
 )

@@ -37,6 +37,15 @@ SIGNATURES = {
                               c_i64, c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_ptr, c_i64,
                               c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_ptr, c_size, c_ptr,
                               c_ptr]),
+    "rsvd_batch_create": (c_int, [c_ptr, c_i64, c_ptr, c_ptr, c_ptr, c_int, c_int,
+                                  ctypes.POINTER(c_ptr)]),
+    "rsvd_batch_destroy": (c_int, [c_ptr]),
+    "rsvd_batch_layout": (c_int, [c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr,
+                                  c_ptr]),
+    "rsvd_batch_workspace_bytes": (c_size, [c_ptr]),
+    "rsvd_batch_prepare": (c_int, [c_ptr, c_ptr, c_size, c_ptr]),
+    "rsvd_batch_svd": (c_int, [c_ptr, c_u64, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_size, c_ptr,
+                               c_ptr]),
     "rsvd_id_left_workspace_bytes": (c_size, [c_int, c_i64, c_i64, c_int, c_int, c_int]),
     "rsvd_id_left": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr,
                              c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_size, c_ptr, c_ptr]),

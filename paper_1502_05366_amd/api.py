@@ -311,6 +311,90 @@ def svd_diff(A, k, p, q, seed):
     return _SvdFunction.apply(A, k, p, q, seed)
 
 
+class BatchPlan:
+    """Batched randomized SVD of FP32 matrices (rsvd_batch_*): the plan fixes
+    the sizes; pack() lays the matrices out in one buffer, run() launches the
+    persistent kernel (capturable in a CUDA/HIP graph once prepared), unpack()
+    splits U, S, V per matrix."""
+
+    def __init__(self, ms, ns, ks, p, q, device="cuda"):
+        import numpy as np
+        lib = _lib.load()
+        self.device = torch.device(device)
+        self.count = len(ms)
+        self.ms = np.asarray(ms, dtype=np.int64)
+        self.ns = np.asarray(ns, dtype=np.int64)
+        self.ks = np.asarray(ks, dtype=np.int32)
+        if not (len(self.ns) == self.count == len(self.ks)):
+            raise RsvdError("ms, ns, ks must have the same length")
+        self.p, self.q = p, q
+        plan = ctypes.c_void_p()
+        rc = lib.rsvd_batch_create(handle(self.device), self.count,
+                                   self.ms.ctypes.data_as(ctypes.c_void_p),
+                                   self.ns.ctypes.data_as(ctypes.c_void_p),
+                                   self.ks.ctypes.data_as(ctypes.c_void_p), p, q,
+                                   ctypes.byref(plan))
+        _check(rc, "rsvd_batch_create")
+        self._plan = plan
+        tot = [ctypes.c_int64(0) for _ in range(4)]
+        offs = [np.zeros(self.count, dtype=np.int64) for _ in range(5)]
+        rc = lib.rsvd_batch_layout(plan, *[ctypes.byref(t) for t in tot],
+                                   *[o.ctypes.data_as(ctypes.c_void_p) for o in offs])
+        _check(rc, "rsvd_batch_layout")
+        self.a_elems, self.u_elems, self.s_elems, self.v_elems = [t.value for t in tot]
+        self.a_off, self.lda, self.u_off, self.s_off, self.v_off = offs
+        self.work_bytes = int(lib.rsvd_batch_workspace_bytes(plan))
+        self.work = _workspace(self.work_bytes, self.device)
+        rc = lib.rsvd_batch_prepare(plan, _ptr(self.work), self.work.numel(),
+                                    _stream(self.device))
+        _check(rc, "rsvd_batch_prepare")
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and _lib._lib is not None:
+            _lib._lib.rsvd_batch_destroy(plan)
+            self._plan = None
+
+    def pack(self, As):
+        """One FP32 buffer holding every A_i at its offset (rows padded to lda)."""
+        buf = torch.zeros(self.a_elems + 4, dtype=torch.float32, device=self.device)
+        for i, A in enumerate(As):
+            m, n = int(self.ms[i]), int(self.ns[i])
+            ld, off = int(self.lda[i]), int(self.a_off[i])
+            view = buf[off:off + m * ld].view(m, ld)
+            view[:, :n] = torch.as_tensor(A, device=self.device).to(torch.float32)
+        return buf
+
+    def outputs(self):
+        dev = self.device
+        return (torch.empty(max(self.u_elems, 1), dtype=torch.float32, device=dev),
+                torch.empty(max(self.s_elems, 1), dtype=torch.float64, device=dev),
+                torch.empty(max(self.v_elems, 1), dtype=torch.float32, device=dev),
+                torch.zeros(2, dtype=torch.int32, device=dev))
+
+    def run(self, A_packed, seed, out=None):
+        """Launch the batch; out = (U, S, V, info) buffers from outputs() (new ones
+        when None).  Returns the four buffers."""
+        lib = _lib.load()
+        if A_packed.dtype != torch.float32 or A_packed.numel() < self.a_elems:
+            raise RsvdError("A_packed must be the FP32 buffer from pack()")
+        U, S, V, info = self.outputs() if out is None else out
+        rc = lib.rsvd_batch_svd(self._plan, seed, _ptr(A_packed), _ptr(U), _ptr(S), _ptr(V),
+                                _ptr(self.work), self.work.numel(), _ptr(info),
+                                _stream(self.device))
+        _check(rc, "rsvd_batch_svd")
+        return U, S, V, info
+
+    def unpack(self, U, S, V):
+        """Per-matrix views (U_i m_i x k_i, S_i k_i, V_i n_i x k_i)."""
+        res = []
+        for i in range(self.count):
+            m, n, k = int(self.ms[i]), int(self.ns[i]), int(self.ks[i])
+            uo, so, vo = int(self.u_off[i]), int(self.s_off[i]), int(self.v_off[i])
+            res.append((U[uo:uo + m * k].view(m, k), S[so:so + k], V[vo:vo + n * k].view(n, k)))
+        return res
+
+
 def cur(A, k, p, q, seed):
     """Rank-k CUR: Jc (k), Jr (k), U (k x k FP64), info; A ~ A[:, Jc] U A[Jr, :]."""
     lib = _lib.load()

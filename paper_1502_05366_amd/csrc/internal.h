@@ -175,6 +175,32 @@ hipError_t launch_zero(double* X, int64_t ldx, int64_t rows, int cols, hipStream
 hipError_t launch_add(double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t rows,
                       int cols, hipStream_t st);
 
+// ----------------------------------------------------------------- batch --
+// Batched randomized SVD of small FP32 matrices, one workgroup per matrix in
+// one persistent launch.
+constexpr int BATCH_MAX_LP = 80;     // l = min(k + p, m, n) <= 80
+struct BatchDesc {
+  int64_t m, n, lda;                 // A_i: m x n row-major, lda % 4 == 0
+  int64_t a_off, u_off, v_off, s_off;   // element offsets in the packed A, U, V, S
+  int32_t k, l, lp, index;           // index: position in the caller's list
+};
+struct BatchArgs {
+  const BatchDesc* desc;             // in work-queue order
+  int64_t count;
+  int32_t* counter;                  // work-queue head (reset by the launcher)
+  const float* A;
+  float* U;
+  double* S;
+  float* V;
+  char* scratch;                     // one slot of slot_bytes per workgroup
+  int64_t slot_bytes;
+  int64_t off_om, off_y, off_q, off_z, off_zq, off_t, off_qh, off_uh, off_vh;
+  uint32_t k0, k1;                   // seed words
+  int q;
+  int32_t* info;
+};
+hipError_t launch_batch_rsvd(const BatchArgs& g, int grid, hipStream_t st);
+
 // ------------------------------------------------------------------- cur --
 // atype: element type of A, 0 FP64, 1 FP32, 2 BF16
 hipError_t launch_gather_cols(int atype, const void* A, int64_t lda, int64_t m, int64_t n,

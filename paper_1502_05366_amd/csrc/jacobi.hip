@@ -18,111 +18,13 @@
 // matching columns of Uh and Vh.
 #include "common.h"
 #include "internal.h"
+#include "jacobi_dev.h"
 
 namespace rsvd {
 namespace {
 
 constexpr int JNT = 1024;
 constexpr int LDS_MAX_L = 64;     // 2 * 64 * 64 * 8 B = 64 KB
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Rotation (c, s) that orthogonalizes a column pair with squared norms al, be
-// and inner product ga (the formulas in the header); false when the pair is
-// already orthogonal to within tol.
-// 1/x with one Newton step: enough for quantities that only set the rotation
-// angle (c and s are made consistent afterwards)
-__device__ __forceinline__ double rcp_nr1(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-
-__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol,
-                                                double& cs, double& sn) {
-  // |ga| > tol sqrt(al be), compared in squares
-  if (!(ga * ga > (tol * tol) * (al * be))) return false;
-  const double zeta = (be - al) * (0.5 * rcp_nr1(ga));
-  const double az = fabs(zeta);
-  double t;
-  if (az < 1e150) {
-    const double z2 = fma(zeta, zeta, 1.0);
-    t = rcp_nr1(az + z2 * rsq_nr(z2));
-  } else {
-    t = 0.5 * rcp_nr1(az);
-  }
-  t = zeta >= 0.0 ? t : -t;
-  // c = 1 / sqrt(1 + t^2) to full precision, so that c^2 + s^2 = 1 to rounding
-  cs = rsq_nr(fma(t, t, 1.0));
-  sn = cs * t;
-  return true;
-}
-
-__device__ __forceinline__ int rr_player(int pos, int r, int N) {
-  return pos == 0 ? 0 : ((pos - 1 + r) % (N - 1)) + 1;
-}
-
-// Singular values = column norms of W; the k largest (stable descending
-// order) go to S with Uh(:, rank) = w_j / sigma_j and Vh(:, rank) = v_j.
-// Called by every thread of a workgroup of JNT threads; sig has l entries.
-__device__ void jacobi_finish(const double* W, const double* V, int64_t ld, int l, int k,
-                              double* sig, double* __restrict__ S, double* __restrict__ Uh,
-                              int64_t lduh, double* __restrict__ Vh, int64_t ldvh) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = wave; j < l; j += JNT / 64) {
-    double s2 = 0.0;
-    for (int i = lane; i < l; i += 64) { const double x = W[j * ld + i]; s2 += x * x; }
-    s2 = wave_sum(s2);
-    if (lane == 0) sig[j] = sqrt(s2);
-  }
-  __syncthreads();
-  for (int j = wave; j < l; j += JNT / 64) {
-    const double sj = sig[j];
-    int rank = 0;
-    for (int i = lane; i < l; i += 64) {
-      const double si = sig[i];
-      rank += (si > sj || (si == sj && i < j)) ? 1 : 0;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rank += __shfl_xor(rank, off, 64);
-    if (rank < k) {
-      if (lane == 0) S[rank] = sj;
-      const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-      for (int i = lane; i < l; i += 64) {
-        Uh[(int64_t)i * lduh + rank] = W[j * ld + i] * inv;
-        Vh[(int64_t)i * ldvh + rank] = V[j * ld + i];
-      }
-    }
-  }
-}
-
-// Rotate the column pair (a, b) of W (and V) if it is not yet orthogonal;
-// executed by one wave.  Returns true when a rotation was applied.
-__device__ __forceinline__ bool rotate_pair(double* wa, double* wb, double* va, double* vb, int l,
-                                            int lane, double tol) {
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int i = lane; i < l; i += 64) {
-    const double x = wa[i], y = wb[i];
-    al += x * x; be += y * y; ga += x * y;
-  }
-  al = wave_allsum(al); be = wave_allsum(be); ga = wave_allsum(ga);
-  double cs, sn;
-  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
-  for (int i = lane; i < l; i += 64) {
-    const double x = wa[i], y = wb[i];
-    wa[i] = cs * x - sn * y;
-    wb[i] = sn * x + cs * y;
-  }
-  for (int i = lane; i < l; i += 64) {
-    const double x = va[i], y = vb[i];
-    va[i] = cs * x - sn * y;
-    vb[i] = sn * x + cs * y;
-  }
-  return true;
-}
 
 // l <= LDS_MAX_L: the whole iteration in one workgroup, W and V in LDS.
 __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restrict__ Rh, int64_t ldr,
@@ -164,7 +66,7 @@ __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restric
     __syncthreads();
   }
   if (!converged && tid == 0) info_or(info, INFO_JACOBI_CAP);
-  jacobi_finish(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
+  jacobi_finish<JNT>(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
 }
 
 // ---- block one-sided Jacobi over several workgroups (l > LDS_MAX_L) -------
@@ -448,7 +350,7 @@ __global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __rest
                                                             double* __restrict__ Vh,
                                                             int64_t ldvh) {
   __shared__ double sig[256];
-  jacobi_finish(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
+  jacobi_finish<JNT>(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
 }
 
 }  // namespace

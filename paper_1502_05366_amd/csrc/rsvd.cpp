@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <vector>
 
 #include "rsvd.h"
 #include "common.h"
@@ -30,6 +32,23 @@ struct rsvd_handle_s {
   // beside the ID / CUR post-processing inside rsvd_decompose
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
+};
+
+// Host side of a batch: the per-matrix descriptors in work-queue order and
+// the packed layouts of A, U, S, V in the caller's order.
+struct rsvd_batch_s {
+  rsvd_handle_s* h;
+  int64_t count;
+  int p, q;
+  std::vector<rsvd::BatchDesc> desc;     // queue order (decreasing work)
+  std::vector<int64_t> a_off, lda, u_off, s_off, v_off;   // caller order
+  int64_t a_elems, u_elems, s_elems, v_elems;
+  int64_t mmax, nmax;
+  int grid;
+  // workspace layout
+  int64_t desc_off, slot_off, slot_bytes;
+  int64_t off_om, off_y, off_q, off_z, off_zq, off_t, off_qh, off_uh, off_vh;
+  size_t work_bytes;
 };
 
 namespace rsvd {
@@ -983,6 +1002,153 @@ int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p
   io.dA = dA; io.ldda = ldda;
   io.U = U; io.S = S; io.V = V; io.resid2 = resid2; io.ldu = ldu; io.ldv = ldv;
   return finish(run_grad(c, s, g, A, lda, io));
+}
+
+int rsvd_batch_create(rsvd_handle_t h, int64_t count, const int64_t* m, const int64_t* n,
+                      const int32_t* k, int p, int q, rsvd_batch_t* plan) {
+  using namespace rsvd;
+  if (!h) return -1;
+  if (count < 1) return -2;
+  if (!m) return -3;
+  if (!n) return -4;
+  if (!k) return -5;
+  if (p < 0) return -6;
+  if (q < 0) return -7;
+  if (!plan) return -8;
+  for (int64_t i = 0; i < count; ++i) {
+    if (m[i] < 1) return -3;
+    if (n[i] < 1) return -4;
+    if (k[i] < 1 || k[i] > std::min(m[i], n[i])) return -5;
+    const int64_t l = std::min<int64_t>((int64_t)k[i] + p, std::min(m[i], n[i]));
+    if (rup(l, 16) > BATCH_MAX_LP) return RSVD_ERR_UNSUPPORTED;
+  }
+  rsvd_batch_s* b = new rsvd_batch_s;
+  b->h = h;
+  b->count = count;
+  b->p = p;
+  b->q = q;
+  b->a_off.resize(count); b->lda.resize(count); b->u_off.resize(count);
+  b->s_off.resize(count); b->v_off.resize(count);
+  int64_t ao = 0, uo = 0, so = 0, vo = 0;
+  b->mmax = b->nmax = 0;
+  std::vector<BatchDesc> d(count);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t ld = rup(n[i], 4);
+    b->a_off[i] = ao; b->lda[i] = ld; b->u_off[i] = uo; b->s_off[i] = so; b->v_off[i] = vo;
+    BatchDesc& e = d[i];
+    e.m = m[i]; e.n = n[i]; e.lda = ld;
+    e.a_off = ao; e.u_off = uo; e.v_off = vo; e.s_off = so;
+    e.k = k[i];
+    e.l = (int32_t)std::min<int64_t>((int64_t)k[i] + p, std::min(m[i], n[i]));
+    e.lp = (int32_t)rup(e.l, 16);
+    e.index = (int32_t)i;
+    ao += m[i] * ld;
+    uo += m[i] * k[i];
+    so += k[i];
+    vo += n[i] * k[i];
+    b->mmax = std::max(b->mmax, m[i]);
+    b->nmax = std::max(b->nmax, n[i]);
+  }
+  b->a_elems = ao; b->u_elems = uo; b->s_elems = so; b->v_elems = vo;
+  // queue order: decreasing work (passes 2 (2q+2) m n l), ties by index
+  std::vector<int64_t> ord(count);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+    return d[x].m * d[x].n * d[x].l > d[y].m * d[y].n * d[y].l;
+  });
+  b->desc.resize(count);
+  for (int64_t i = 0; i < count; ++i) b->desc[i] = d[ord[i]];
+  b->grid = (int)std::min<int64_t>(h->ncu, count);
+  // workspace: [queue head][descriptors][one slot per workgroup]
+  const int64_t lpm = BATCH_MAX_LP;
+  const int64_t rmax = std::max(b->mmax, b->nmax);
+  auto r256 = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+  int64_t o = 0;
+  b->off_om = o; o = r256(o + b->nmax * lpm * 4);
+  b->off_y = o;  o = r256(o + b->mmax * lpm * 4);
+  b->off_q = o;  o = r256(o + b->mmax * lpm * 4);
+  b->off_z = o;  o = r256(o + b->nmax * lpm * 4);
+  b->off_zq = o; o = r256(o + b->nmax * lpm * 4);
+  b->off_t = o;  o = r256(o + rmax * lpm * 8);
+  b->off_qh = o; o = r256(o + b->nmax * lpm * 8);
+  b->off_uh = o; o = r256(o + lpm * lpm * 8);
+  b->off_vh = o; o = r256(o + lpm * lpm * 8);
+  b->slot_bytes = o;
+  b->desc_off = 256;
+  b->slot_off = r256(b->desc_off + count * (int64_t)sizeof(BatchDesc));
+  b->work_bytes = (size_t)(b->slot_off + b->grid * b->slot_bytes);
+  *plan = b;
+  return RSVD_OK;
+}
+
+int rsvd_batch_destroy(rsvd_batch_t plan) {
+  delete plan;
+  return RSVD_OK;
+}
+
+int rsvd_batch_layout(rsvd_batch_t b, int64_t* a_elems, int64_t* u_elems, int64_t* s_elems,
+                      int64_t* v_elems, int64_t* a_off, int64_t* lda, int64_t* u_off,
+                      int64_t* s_off, int64_t* v_off) {
+  if (!b) return -1;
+  if (a_elems) *a_elems = b->a_elems;
+  if (u_elems) *u_elems = b->u_elems;
+  if (s_elems) *s_elems = b->s_elems;
+  if (v_elems) *v_elems = b->v_elems;
+  const size_t nb = sizeof(int64_t) * (size_t)b->count;
+  if (a_off) std::memcpy(a_off, b->a_off.data(), nb);
+  if (lda) std::memcpy(lda, b->lda.data(), nb);
+  if (u_off) std::memcpy(u_off, b->u_off.data(), nb);
+  if (s_off) std::memcpy(s_off, b->s_off.data(), nb);
+  if (v_off) std::memcpy(v_off, b->v_off.data(), nb);
+  return RSVD_OK;
+}
+
+size_t rsvd_batch_workspace_bytes(rsvd_batch_t b) { return b ? b->work_bytes : 0; }
+
+int rsvd_batch_prepare(rsvd_batch_t b, void* work, size_t work_bytes, void* stream) {
+  if (!b) return -1;
+  if (!work) return -2;
+  if (work_bytes < b->work_bytes) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(b->h->device) != hipSuccess) return RSVD_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(work);
+  if (hipMemcpyAsync(w + b->desc_off, b->desc.data(), sizeof(rsvd::BatchDesc) * b->count,
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return RSVD_ERR_HIP;
+  return hipStreamSynchronize(st) == hipSuccess ? RSVD_OK : RSVD_ERR_HIP;
+}
+
+int rsvd_batch_svd(rsvd_batch_t b, uint64_t seed, const float* A, float* U, double* S, float* V,
+                   void* work, size_t work_bytes, int32_t* info, void* stream) {
+  using namespace rsvd;
+  if (!b) return -1;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 15)) return -3;
+  if (!U) return -4;
+  if (!S) return -5;
+  if (!V) return -6;
+  if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -7;
+  if (work_bytes < b->work_bytes) return RSVD_ERR_WORKSPACE;
+  if (!info) return -9;
+  if (hipSetDevice(b->h->device) != hipSuccess) return RSVD_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(work);
+  BatchArgs g;
+  g.desc = reinterpret_cast<const BatchDesc*>(w + b->desc_off);
+  g.count = b->count;
+  g.counter = reinterpret_cast<int32_t*>(w);
+  g.A = A; g.U = U; g.S = S; g.V = V;
+  g.scratch = w + b->slot_off;
+  g.slot_bytes = b->slot_bytes;
+  g.off_om = b->off_om; g.off_y = b->off_y; g.off_q = b->off_q; g.off_z = b->off_z;
+  g.off_zq = b->off_zq; g.off_t = b->off_t; g.off_qh = b->off_qh; g.off_uh = b->off_uh;
+  g.off_vh = b->off_vh;
+  g.k0 = (uint32_t)seed; g.k1 = (uint32_t)(seed >> 32);
+  g.q = b->q;
+  g.info = info;
+  hipError_t e = launch_set_word(info, 0, st);
+  if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
+  if (e == hipSuccess) e = launch_batch_rsvd(g, b->grid, st);
+  return finish(e);
 }
 
 int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,

@@ -116,6 +116,54 @@ def c5_matrix(seed=0xC0FFEE05):
     return kron_haar_matrix(128, 64, 64, 64, 64, s, seed), s
 
 
+C4_COUNT = 4096
+
+
+def c4_dims(count=C4_COUNT, seed=0xC0FFEE04, mmax=2048, nmax=1024, kmax=64):
+    """Sizes of a batch of uneven problems: m ~ U{64..mmax}, n ~ U{64..nmax},
+    k ~ U{4..kmax} (clamped to min(m, n))."""
+    g = rng(seed)
+    m = g.integers(min(64, mmax), mmax + 1, size=count).astype(np.int64)
+    n = g.integers(min(64, nmax), nmax + 1, size=count).astype(np.int64)
+    k = g.integers(min(4, kmax), kmax + 1, size=count)
+    k = np.minimum(k, np.minimum(m, n)).astype(np.int32)
+    return m, n, k
+
+
+def c4_spectrum(m, n, rmax=320):
+    """sigma_j = exp(-j/8), j = 1 .. min(m, n, rmax)."""
+    r = min(m, n, rmax)
+    return np.exp(-np.arange(1, r + 1) / 8.0)
+
+
+def c4_batch_torch(ms, ns, seed, device, rmax=320):
+    """The batch's FP32 matrices A_i = U_i diag(sigma) V_i^T generated on a
+    device with torch: U_i, V_i are the first r columns of a product of two
+    Householder reflectors with Gaussian vectors (orthonormal; a Gaussian
+    sketch is rotation-invariant, so the error law of the method depends only
+    on sigma), formed in FP64 and rounded to FP32 once."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+
+    def factor(rows, r):
+        E = torch.eye(rows, r, dtype=torch.float64, device=device)
+        for _ in range(2):
+            w = torch.randn(rows, 1, dtype=torch.float64, device=device, generator=gen)
+            w = w / torch.linalg.vector_norm(w)
+            E = E - 2.0 * w @ (w.T @ E)
+        return E
+
+    out = []
+    for m, n in zip(ms, ns):
+        m, n = int(m), int(n)
+        s = torch.as_tensor(c4_spectrum(m, n, rmax), device=device)
+        r = s.numel()
+        U, V = factor(m, r), factor(n, r)
+        out.append(((U * s) @ V.T).to(torch.float32))
+    return out
+
+
 def exact_rank_matrix(m, n, r, seed, decay=0.5):
     """Rank-r A = U diag(s) V^T with s_j = decay^j (j = 0..r-1)."""
     s = decay ** np.arange(r)

@@ -138,3 +138,32 @@ def test_svd_grad_workspace_query(lib):
     assert w(0, 300, 200, 10, 6, 9) == 0        # q <= 8
     # the FP64 8192 x 4096, k = 64, p = 16, q = 2 case
     assert w(0, 8192, 4096, 64, 16, 2) < 256 << 20
+
+
+def test_batch_create_argument_codes(lib):
+    import numpy as np
+    m = np.array([100, 50], dtype=np.int64)
+    n = np.array([80, 40], dtype=np.int64)
+    k = np.array([10, 5], dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    plan = ctypes.c_void_p()
+    cr = lib.rsvd_batch_create
+    assert cr(NULLP, 2, P(m), P(n), P(k), 8, 1, ctypes.byref(plan)) == -1
+    assert cr(FAKE, 0, P(m), P(n), P(k), 8, 1, ctypes.byref(plan)) == -2
+    assert cr(FAKE, 2, NULLP, P(n), P(k), 8, 1, ctypes.byref(plan)) == -3
+    assert cr(FAKE, 2, P(m), NULLP, P(k), 8, 1, ctypes.byref(plan)) == -4
+    assert cr(FAKE, 2, P(m), P(n), NULLP, 8, 1, ctypes.byref(plan)) == -5
+    assert cr(FAKE, 2, P(m), P(n), P(k), -1, 1, ctypes.byref(plan)) == -6
+    assert cr(FAKE, 2, P(m), P(n), P(k), 8, -1, ctypes.byref(plan)) == -7
+    assert cr(FAKE, 2, P(m), P(n), P(k), 8, 1, NULLP) == -8
+    bad_k = np.array([10, 41], dtype=np.int32)            # k > min(m, n)
+    assert cr(FAKE, 2, P(m), P(n), P(bad_k), 8, 1, ctypes.byref(plan)) == -5
+    bad_m = np.array([100, 0], dtype=np.int64)
+    assert cr(FAKE, 2, P(bad_m), P(n), P(k), 8, 1, ctypes.byref(plan)) == -3
+    m2 = np.array([200, 50], dtype=np.int64)
+    n2 = np.array([100, 40], dtype=np.int64)
+    huge = np.array([74, 5], dtype=np.int32)              # l = 82 -> lp 96: unsupported
+    assert cr(FAKE, 2, P(m2), P(n2), P(huge), 8, 1, ctypes.byref(plan)) == 3
+    assert lib.rsvd_batch_workspace_bytes(NULLP) == 0
+    assert lib.rsvd_batch_svd(NULLP, 1, PTR, PTR, PTR, PTR, PTR, 1, PTR, NULLP) == -1
+    assert lib.rsvd_batch_prepare(NULLP, PTR, 1, NULLP) == -1

@@ -1,0 +1,195 @@
+"""Parity of the batched randomized SVD (one persistent launch over many
+uneven FP32 matrices) with the FP64 oracle (needs a GPU), through the C-ABI
+entry points rsvd_batch_*.
+
+The oracle is oracle.rsvd.batch_rsvd: matrix i of the batch with the sketch
+of Philox batch index i, on the FP32 values of A_i taken exactly in FP64.
+The GPU path runs the products on the FP32 matrix cores (FP32 accumulation),
+so, as for the single-matrix FP32 path: sigma within 1e-5 sigma_1 of the
+oracle's, and ||U S V^T - U_o S_o V_o^T||_F within 2e-5 sigma_1 (FP32
+rounding of the passes and of U, V: ~ sqrt(n) eps_32 sigma_1 ~ 2e-6).
+Also: U and V orthonormal to 1e-5, exact recovery at exact rank <= k, edge
+shapes (l = min(m, n), l = 80, tiny m or n, k = 1), q = 0, 1, 2, replays of
+a captured graph equal to the eager call bit for bit, determinism, and the
+4096-matrix workload (sampled matrices against the oracle, properties on
+all of them).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rsvd as O
+from paper_1502_05366_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+SEED = 0x5EED0004
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1502_05366_amd as R
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return R
+
+
+def spectrum_batch(ms, ns, seed):
+    return [W.spectrum_matrix(int(m), int(n), W.c4_spectrum(int(m), int(n)), seed + i)[0]
+            .astype(np.float32) for i, (m, n) in enumerate(zip(ms, ns))]
+
+
+def run_batch(R, As, ms, ns, ks, p, q, seed=SEED):
+    plan = R.BatchPlan(ms, ns, ks, p, q)
+    buf = plan.pack([torch.from_numpy(A) for A in As])
+    U, S, V, info = plan.run(buf, seed)
+    torch.cuda.synchronize()
+    res = [(u.cpu().numpy().astype(np.float64), s.cpu().numpy(), v.cpu().numpy().astype(np.float64))
+           for u, s, v in plan.unpack(U, S, V)]
+    return res, info.cpu().numpy(), plan
+
+
+def check_against_oracle(As, ks, res, p, q, seed=SEED, idx=None):
+    idx = range(len(As)) if idx is None else idx
+    for i in idx:
+        A = As[i].astype(np.float64)
+        Uo, So, Vo = O.rsvd(A, int(ks[i]), p, q, seed, batch=i)
+        U, S, V = res[i]
+        s1 = So[0]
+        assert np.all(np.isfinite(S)) and np.all(np.diff(S) <= 0), i
+        assert np.abs(S - So).max() <= 1e-5 * s1, (i, np.abs(S - So).max() / s1)
+        d = np.linalg.norm((U * S) @ V.T - (Uo * So) @ Vo.T)
+        assert d <= 2e-5 * s1, (i, d / s1)
+        k = U.shape[1]
+        assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-5, i
+        assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-5, i
+
+
+@pytest.mark.parametrize("q", [1, 0, 2])
+def test_batch_parity_uneven(R, q):
+    g = np.random.default_rng(40 + q)
+    count = 24 if q == 1 else 10
+    ms = g.integers(16, 601, count)
+    ns = g.integers(16, 401, count)
+    ks = np.minimum(g.integers(1, 65, count), np.minimum(ms, ns))
+    print("batch parity q=%d count=%d" % (q, count), flush=True)
+    As = spectrum_batch(ms, ns, 100 * q)
+    res, info, _ = run_batch(R, As, ms, ns, ks, 8, q)
+    assert info[0] == 0, info
+    check_against_oracle(As, ks, res, 8, q)
+
+
+def test_batch_edge_shapes(R):
+    # l = min(m, n); l = 80 exactly; tiny m / n; k = 1; k = min(m, n); 1 x 1
+    shapes = [(16, 16, 16), (40, 24, 20), (500, 300, 72), (3, 5, 1), (1, 1, 1), (7, 200, 7),
+              (300, 9, 2), (129, 130, 64), (2048, 64, 60), (64, 1024, 33)]
+    ms = np.array([s[0] for s in shapes])
+    ns = np.array([s[1] for s in shapes])
+    ks = np.array([s[2] for s in shapes])
+    print("batch edge shapes", flush=True)
+    As = spectrum_batch(ms, ns, 7)
+    res, info, plan = run_batch(R, As, ms, ns, ks, 8, 1)
+    assert info[0] == 0, info
+    check_against_oracle(As, ks, res, 8, 1)
+    assert np.all(plan.lda % 4 == 0) and np.all(plan.lda >= plan.ns)
+    assert np.all(plan.a_off % 4 == 0)
+
+
+def test_batch_exact_rank(R):
+    ms, ns, ks = np.array([300, 120, 77]), np.array([200, 260, 77]), np.array([12, 9, 20])
+    As = []
+    for i, (m, n, k) in enumerate(zip(ms, ns, ks)):
+        A, _, _, _ = W.exact_rank_matrix(int(m), int(n), int(k) - 2, seed=30 + i)
+        As.append(A.astype(np.float32))
+    print("batch exact rank", flush=True)
+    res, info, _ = run_batch(R, As, ms, ns, ks, 6, 1)
+    for A, (U, S, V) in zip(As, res):
+        A = A.astype(np.float64)
+        assert np.linalg.norm(A - (U * S) @ V.T) <= 1e-5 * np.linalg.norm(A)
+
+
+def test_batch_graph_replay_and_determinism(R):
+    g = np.random.default_rng(9)
+    count = 40
+    ms = g.integers(16, 700, count)
+    ns = g.integers(16, 500, count)
+    ks = np.minimum(g.integers(1, 65, count), np.minimum(ms, ns))
+    As = spectrum_batch(ms, ns, 55)
+    plan = R.BatchPlan(ms, ns, ks, 8, 1)
+    buf = plan.pack([torch.from_numpy(A) for A in As])
+    print("batch graph replay", flush=True)
+    out = plan.outputs()
+    plan.run(buf, SEED, out)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in out[:3]]
+    plan.run(buf, SEED, out)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(out[:3], ref))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(buf, SEED, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(buf, SEED, out)
+    for rep in range(3):
+        for t in out[:3]:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(out[:3], ref)), rep
+        assert int(out[3][0].item()) == 0
+
+
+def test_batch_unsupported(R):
+    with pytest.raises(R.RsvdError):
+        R.BatchPlan([200], [100], [80], 8, 1)          # l = 88 > 80
+    with pytest.raises(R.RsvdError):
+        R.BatchPlan([20], [10], [11], 8, 1)            # k > min(m, n)
+
+
+def test_batch_c4_full(R):
+    """The 4096-matrix workload: m ~ U{64..2048}, n ~ U{64..1024},
+    k ~ U{4..64}, p = 8, q = 1, sigma_j = exp(-j/8).  Eight sampled matrices
+    (the largest, the smallest, six others) against the oracle; on all:
+    sigma_1 within the interlacing bound, and on every 97th matrix S finite
+    and descending, U and V orthonormal."""
+    ms, ns, ks = W.c4_dims()
+    print("batch C4 generate", flush=True)
+    As = W.c4_batch_torch(ms, ns, 0xC0FFEE04, "cuda")
+    plan = R.BatchPlan(ms, ns, ks, 8, 1)
+    buf = plan.pack(As)
+    print("batch C4 run", flush=True)
+    U, S, V, info = plan.run(buf, SEED)
+    torch.cuda.synchronize()
+    assert int(info[0].item()) == 0
+    views = plan.unpack(U, S, V)
+    s1 = torch.stack([s[0] for _, s, _ in views]).cpu().numpy()
+    # interlacing: the singular values of Q^T A never exceed those of A (up
+    # to the FP32 rounding of A and of the passes, the 1e-5 sigma_1 of the
+    # parity bar); with l as small as 12 on this slowly decaying spectrum the
+    # randomized sigma_1 lies up to ~1e-3 below the exact value
+    assert np.all(s1 <= np.exp(-1 / 8) * (1 + 1e-5))
+    assert np.all(s1 >= np.exp(-1 / 8) * (1 - 5e-3))
+    for u, s, v in views[::97]:
+        sn = s.cpu().numpy()
+        assert np.all(np.isfinite(sn)) and np.all(np.diff(sn) <= 0)
+        un, vn = u.double().cpu().numpy(), v.double().cpu().numpy()
+        k = un.shape[1]
+        assert np.abs(un.T @ un - np.eye(k)).max() <= 1e-5
+        assert np.abs(vn.T @ vn - np.eye(k)).max() <= 1e-5
+    work = ms * ns
+    pick = [int(np.argmax(work)), int(np.argmin(work))] + [int(i) for i in
+                                                           np.random.default_rng(3).choice(len(ms), 6, replace=False)]
+    print("batch C4 oracle on %s" % pick, flush=True)
+    res = {i: (views[i][0].double().cpu().numpy(), views[i][1].cpu().numpy(),
+               views[i][2].double().cpu().numpy()) for i in pick}
+    Anp = {i: As[i].cpu().numpy() for i in pick}
+    for i in pick:
+        A = Anp[i].astype(np.float64)
+        Uo, So, Vo = O.rsvd(A, int(ks[i]), 8, 1, SEED, batch=i)
+        Ug, Sg, Vg = res[i]
+        assert np.abs(Sg - So).max() <= 1e-5 * So[0], i
+        assert np.linalg.norm((Ug * Sg) @ Vg.T - (Uo * So) @ Vo.T) <= 2e-5 * So[0], i
