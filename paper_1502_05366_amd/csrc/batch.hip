@@ -14,11 +14,13 @@
 // grid is one workgroup per CU whatever the batch size, and no workgroup
 // ever waits for another.  Per matrix:
 //  * passes over A (FP32 MFMA 16x16x4, FP32 accumulation): 128-row (or
-//    128-column for A^T) tiles of A and 16-deep chunks of the skinny operand
-//    staged in LDS with 16-byte loads, double-buffered;
-//  * orth = CholeskyQR2 in FP64: Gram X^T X on FP64 MFMA, Cholesky and the
-//    inverse of R in LDS, Q = Y R^{-1} on FP64 MFMA; a pivot below
-//    1e-13 G_jj marks a dependent column (unit row of R, info bit 1);
+//    128-column for A^T) tiles of A and 64-deep chunks of A and the skinny
+//    operand staged in LDS with 16-byte loads, double-buffered;
+//  * orth = CholeskyQR2 in FP64: Gram X^T X on FP64 MFMA (upper blocks,
+//    rows split over the waves), Cholesky (one barrier per step) and the
+//    inverse of R (four lanes per column) in LDS, Q = Y R^{-1} on FP64 MFMA;
+//    a pivot below 1e-13 G_jj marks a dependent column (unit row of R, info
+//    bit 1);
 //  * the Jacobi SVD of the l x l factor in LDS (the rotations of the
 //    single-matrix small SVD);
 //  * U and V on FP64 MFMA, written in FP32.
@@ -35,23 +37,35 @@ namespace {
 constexpr int BNT = 512;             // 8 waves
 constexpr int BLMAX = BATCH_MAX_LP;  // lp <= 80
 constexpr int SL = BLMAX + 1;        // LDS row stride of the small FP64 matrices
-constexpr int ALD = 17;              // pass: A tile row stride (floats), 128 x 16
-constexpr int ATLD = 132;            // pass A^T: A tile row stride (floats), 16 x 128
-constexpr int XLD = 84;              // skinny chunk row stride (floats), 16 x lp
-constexpr int STAGE_FLOATS = 2 * (128 * ALD + 16 * XLD);   // double buffer
+constexpr int KC = 64;               // depth of a pass chunk
+constexpr int ALD = KC + 1;          // pass: A tile row stride (floats), 128 x KC
+constexpr int ATLD = 132;            // pass A^T: A tile row stride (floats), KC x 128
+constexpr int XLD = 84;              // skinny chunk row stride (floats), KC x lp
+constexpr int STAGE_N = 2 * (128 * ALD + KC * XLD);
+constexpr int STAGE_T = 2 * (KC * ATLD + KC * XLD);
+constexpr int STAGE_FLOATS = STAGE_N > STAGE_T ? STAGE_N : STAGE_T;
 constexpr double ETA_DEP = 1e-13;
 constexpr int JAC_MAX_SWEEPS = 40;
 
-struct Lds {
-  double a[BLMAX * SL];
-  double b[BLMAX * SL];
-  float stage[STAGE_FLOATS];         // also the Gram partials (8 x 256 doubles)
+// LDS of a workgroup: the passes stage their tiles over the whole union; the
+// small factorizations use a, b (lp x lp FP64, stride SL) and the Gram
+// partials.  Declared at namespace scope so that every helper addresses it
+// as LDS even when it is not inlined.
+struct BatchLds {
+  union {
+    struct {
+      double a[BLMAX * SL];
+      double b[BLMAX * SL];
+      double part[8 * 256];
+    } sm;
+    float stage[STAGE_FLOATS];
+  } u;
   double sig[BLMAX];
   double dgn[BLMAX];
   int flag;
   int item;
 };
-static_assert(STAGE_FLOATS * sizeof(float) >= 8 * 256 * sizeof(double), "Gram partials");
+__shared__ BatchLds g_lds;
 
 __device__ __forceinline__ double to_d(float x) { return (double)x; }
 __device__ __forceinline__ double to_d(double x) { return x; }
@@ -93,45 +107,72 @@ __device__ __noinline__ void b_sketch(float* Om, int64_t n, int l, int lp, uint3
   __syncthreads();
 }
 
-// Y (m x lp) = A X, A m x n (FP32, lda % 4 == 0), X n x lp (FP32).
-__device__ __noinline__ void b_pass_n(Lds& s, const float* __restrict__ A, int64_t lda, int64_t m,
+// A float4 of row r of A at column c (c % 4 == 0, c < lda), entries at
+// columns >= n taken as zero
+__device__ __forceinline__ float4 ld_a4(const float* A, int64_t lda, int64_t m, int64_t n,
+                                        int64_t r, int64_t c) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (r < m && c < lda) {
+    v = ld4(A + r * lda + c);
+    if (c + 0 >= n) v.x = 0.f;
+    if (c + 1 >= n) v.y = 0.f;
+    if (c + 2 >= n) v.z = 0.f;
+    if (c + 3 >= n) v.w = 0.f;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void st4(float* p, const float4& v) {
+  p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+}
+
+// Y (m x lp) = A X, A m x n (FP32, lda % 4 == 0), X n x lp (FP32).  Row tiles
+// of 128 (16 rows per wave), KC-deep chunks of A and X in LDS.
+__device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
                                       float* __restrict__ Y, int lp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ncb = lp / 16;
-  float* As[2] = {s.stage, s.stage + 128 * ALD};
-  float* Xs[2] = {s.stage + 2 * 128 * ALD, s.stage + 2 * 128 * ALD + 16 * XLD};
-  const int ar = tid >> 2, ac = (tid & 3) * 4;          // A tile: row, 4 columns
+  float* st = g_lds.u.stage;
   const int xq = lp / 4;                                // float4 per X row
-  const int xr = tid / xq, xc = (tid - (tid / xq) * xq) * 4;
-  const bool xact = tid < 16 * xq;
-  const int64_t nkc = cdiv(n, 16);
+  const int xn = KC * xq;                               // float4 per X chunk
+  const int64_t nkc = cdiv(n, KC);
   for (int64_t row0 = 0; row0 < m; row0 += 128) {
     f4 acc[5];
 #pragma unroll
     for (int cb = 0; cb < 5; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 av, xv;
+    float4 av[4], xv[3];
     auto gload = [&](int64_t kc) {
-      const int64_t k0 = kc * 16;
-      const int64_t r = row0 + ar, c = k0 + ac;
-      av = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < m && c < lda) {
-        av = ld4(A + r * lda + c);
-        if (c + 0 >= n) av.x = 0.f;
-        if (c + 1 >= n) av.y = 0.f;
-        if (c + 2 >= n) av.z = 0.f;
-        if (c + 3 >= n) av.w = 0.f;
+      const int64_t k0 = kc * KC;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + BNT * u;
+        av[u] = ld_a4(A, lda, m, n, row0 + (idx >> 4), k0 + (idx & 15) * 4);
       }
-      xv = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (xact && k0 + xr < n) xv = ld4(X + (k0 + xr) * lp + xc);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int idx = tid + BNT * u;
+        const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
+        xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (idx < xn && k0 + xr < n) xv[u] = ld4(X + (k0 + xr) * lp + xc);
+      }
     };
     auto sstore = [&](int b) {
-      float* a = As[b] + ar * ALD + ac;
-      a[0] = av.x; a[1] = av.y; a[2] = av.z; a[3] = av.w;
-      if (xact) {
-        float* x = Xs[b] + xr * XLD + xc;
-        x[0] = xv.x; x[1] = xv.y; x[2] = xv.z; x[3] = xv.w;
+      float* as = st + b * (128 * ALD);
+      float* xs = st + 2 * 128 * ALD + b * (KC * XLD);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + BNT * u;
+        st4(as + (idx >> 4) * ALD + (idx & 15) * 4, av[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int idx = tid + BNT * u;
+        if (idx < xn) {
+          const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
+          st4(xs + xr * XLD + xc, xv[u]);
+        }
       }
     };
     gload(0);
@@ -140,10 +181,10 @@ __device__ __noinline__ void b_pass_n(Lds& s, const float* __restrict__ A, int64
     for (int64_t kc = 0; kc < nkc; ++kc) {
       const bool more = kc + 1 < nkc;
       if (more) gload(kc + 1);
-      const float* as = As[kc & 1];
-      const float* xs = Xs[kc & 1];
+      const float* as = st + (kc & 1) * (128 * ALD);
+      const float* xs = st + 2 * 128 * ALD + (kc & 1) * (KC * XLD);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
+      for (int kk = 0; kk < KC / 4; ++kk) {
         const float a = as[(wave * 16 + li) * ALD + kk * 4 + lk];
 #pragma unroll
         for (int cb = 0; cb < 5; ++cb)
@@ -167,45 +208,53 @@ __device__ __noinline__ void b_pass_n(Lds& s, const float* __restrict__ A, int64
   __syncthreads();
 }
 
-// Z (n x lp) = A^T X, A m x n (FP32, lda % 4 == 0), X m x lp (FP32).
-__device__ __noinline__ void b_pass_t(Lds& s, const float* __restrict__ A, int64_t lda, int64_t m,
+// Z (n x lp) = A^T X, A m x n (FP32, lda % 4 == 0), X m x lp (FP32).  Tiles
+// of 128 columns of A (16 per wave), KC-row chunks of A and X in LDS.
+__device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
                                       float* __restrict__ Z, int lp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ncb = lp / 16;
-  float* As[2] = {s.stage, s.stage + 16 * ATLD};
-  float* Xs[2] = {s.stage + 2 * 16 * ATLD, s.stage + 2 * 16 * ATLD + 16 * XLD};
-  const int ar = tid >> 5, ac = (tid & 31) * 4;         // A tile: row of 16, 4 columns of 128
+  float* st = g_lds.u.stage;
   const int xq = lp / 4;
-  const int xr = tid / xq, xc = (tid - (tid / xq) * xq) * 4;
-  const bool xact = tid < 16 * xq;
-  const int64_t nkc = cdiv(m, 16);
+  const int xn = KC * xq;
+  const int64_t nkc = cdiv(m, KC);
   for (int64_t col0 = 0; col0 < n; col0 += 128) {
     f4 acc[5];
 #pragma unroll
     for (int cb = 0; cb < 5; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 av, xv;
+    float4 av[4], xv[3];
     auto gload = [&](int64_t kc) {
-      const int64_t r0 = kc * 16;
-      const int64_t r = r0 + ar, c = col0 + ac;
-      av = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < m && c < lda) {
-        av = ld4(A + r * lda + c);
-        if (c + 0 >= n) av.x = 0.f;
-        if (c + 1 >= n) av.y = 0.f;
-        if (c + 2 >= n) av.z = 0.f;
-        if (c + 3 >= n) av.w = 0.f;
+      const int64_t r0 = kc * KC;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + BNT * u;
+        av[u] = ld_a4(A, lda, m, n, r0 + (idx >> 5), col0 + (idx & 31) * 4);
       }
-      xv = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (xact && r0 + xr < m) xv = ld4(X + (r0 + xr) * lp + xc);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int idx = tid + BNT * u;
+        const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
+        xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (idx < xn && r0 + xr < m) xv[u] = ld4(X + (r0 + xr) * lp + xc);
+      }
     };
     auto sstore = [&](int b) {
-      float* a = As[b] + ar * ATLD + ac;
-      a[0] = av.x; a[1] = av.y; a[2] = av.z; a[3] = av.w;
-      if (xact) {
-        float* x = Xs[b] + xr * XLD + xc;
-        x[0] = xv.x; x[1] = xv.y; x[2] = xv.z; x[3] = xv.w;
+      float* as = st + b * (KC * ATLD);
+      float* xs = st + 2 * KC * ATLD + b * (KC * XLD);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + BNT * u;
+        st4(as + (idx >> 5) * ATLD + (idx & 31) * 4, av[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int idx = tid + BNT * u;
+        if (idx < xn) {
+          const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
+          st4(xs + xr * XLD + xc, xv[u]);
+        }
       }
     };
     gload(0);
@@ -214,10 +263,10 @@ __device__ __noinline__ void b_pass_t(Lds& s, const float* __restrict__ A, int64
     for (int64_t kc = 0; kc < nkc; ++kc) {
       const bool more = kc + 1 < nkc;
       if (more) gload(kc + 1);
-      const float* as = As[kc & 1];
-      const float* xs = Xs[kc & 1];
+      const float* as = st + (kc & 1) * (KC * ATLD);
+      const float* xs = st + 2 * KC * ATLD + (kc & 1) * (KC * XLD);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
+      for (int kk = 0; kk < KC / 4; ++kk) {
         // A^T[col][row]: column wave*16 + li of the tile, row kk*4 + lk
         const float a = as[(kk * 4 + lk) * ATLD + wave * 16 + li];
 #pragma unroll
@@ -242,31 +291,37 @@ __device__ __noinline__ void b_pass_t(Lds& s, const float* __restrict__ A, int64
   __syncthreads();
 }
 
-// out (lp x lp in LDS, stride SL) = X^T Y for X, Y rows x lp (FP32 or FP64),
-// on FP64 MFMA.  Tasks (16x16 block, row slice) are spread over the 8 waves;
-// with fewer than 8 blocks the rows are cut into slices whose partial blocks
-// are added in slice order.
+// a (lp x lp, stride SL) = X^T Y for X, Y rows x lp (FP32 or FP64), on FP64
+// MFMA.  Tasks (16x16 block, row slice) are spread over the 8 waves; with
+// fewer than 8 blocks the rows are cut into slices whose partial blocks are
+// added in slice order.  Eight 4-row steps are loaded before their products.
 template <typename TX, typename TY>
-__device__ __noinline__ void b_xty(Lds& s, const TX* __restrict__ X, const TY* __restrict__ Y, int64_t rows,
-                      int lp, double* out) {
+__device__ __noinline__ void b_xty(const TX* __restrict__ X, const TY* __restrict__ Y,
+                                   int64_t rows, int lp) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nb = lp / 16, nblk = nb * nb;
   const int S = nblk >= 8 ? 1 : 8 / nblk;
   const int ntask = nblk * S;
   const int64_t nsteps = cdiv(rows, 4);
-  double* part = reinterpret_cast<double*>(s.stage);
+  double* out = g_lds.u.sm.a;
+  double* part = g_lds.u.sm.part;
   for (int task = wave; task < ntask; task += 8) {
     const int b = task / S, sl = task - (task / S) * S;
     const int bi = b / nb, bj = b - (b / nb) * nb;
     const int64_t st0 = sl * nsteps / S, st1 = (sl + 1) * nsteps / S;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t st = st0; st < st1; ++st) {
-      const int64_t r = st * 4 + lk;
-      const bool ok = r < rows;
-      const double a = ok ? to_d(X[r * lp + bi * 16 + li]) : 0.0;
-      const double bv = ok ? to_d(Y[r * lp + bj * 16 + li]) : 0.0;
-      acc = Mfma<double>::mma(a, bv, acc);
+    for (int64_t st = st0; st < st1; st += 8) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t r = (st + u) * 4 + lk;
+        const bool ok = st + u < st1 && r < rows;
+        av[u] = ok ? to_d(X[r * lp + bi * 16 + li]) : 0.0;
+        bv[u] = ok ? to_d(Y[r * lp + bj * 16 + li]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = Mfma<double>::mma(av[u], bv[u], acc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -289,80 +344,159 @@ __device__ __noinline__ void b_xty(Lds& s, const TX* __restrict__ X, const TY* _
   }
 }
 
-// Cholesky G = R^T R of the leading l x l block (G, R in LDS, stride SL;
-// G is overwritten).  R is upper triangular with zeros below the diagonal
-// and the identity in rows / columns l .. lp-1.  A pivot <= ETA_DEP * G_jj
-// (or not positive) gives a unit row and sets s.flag.
-__device__ __noinline__ void b_chol(Lds& s, double* G, double* R, int l, int lp) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < lp * lp; e += BNT) {
-    const int r = e / lp, c = e - (e / lp) * lp;
-    R[r * SL + c] = (r == c && r >= l) ? 1.0 : 0.0;
-  }
-  for (int i = tid; i < l; i += BNT) s.dgn[i] = G[i * SL + i];
-  __syncthreads();
-  for (int j = 0; j < l; ++j) {
-    const double d = G[j * SL + j];
-    const bool dep = !(d > ETA_DEP * s.dgn[j]);
-    const double sq = dep ? 1.0 : sqrt(d);
-    for (int t = tid; t < l - j; t += BNT) {
-      const int c = j + t;
-      R[j * SL + c] = dep ? (t == 0 ? 1.0 : 0.0) : G[j * SL + c] / sq;
+// a (upper 16x16 blocks, stride SL) = X^T X for X rows x lp (FP32 or FP64)
+// on FP64 MFMA.  Wave w forms every upper block over its eighth of the rows
+// (two 4-row steps loaded before their products); the eight partial Grams
+// are added into a in wave order.
+template <typename TX>
+__device__ __noinline__ void b_gram(const TX* __restrict__ X, int64_t rows, int lp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nb = lp / 16;
+  double* out = g_lds.u.sm.a;
+  const int64_t nsteps = cdiv(rows, 4);
+  const int64_t st0 = wave * nsteps / 8, st1 = (wave + 1) * nsteps / 8;
+  d4 acc[5][5];
+#pragma unroll
+  for (int bi = 0; bi < 5; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < 5; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t st = st0; st < st1; st += 2) {
+    double xv[2][5];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t r = (st + u) * 4 + lk;
+      const bool ok = st + u < st1 && r < rows;
+#pragma unroll
+      for (int bi = 0; bi < 5; ++bi)
+        xv[u][bi] = (ok && bi < nb) ? to_d(X[r * lp + bi * 16 + li]) : 0.0;
     }
-    if (dep && tid == 0) s.flag = 1;
-    __syncthreads();
-    const int nr = l - j - 1;
-    for (int e = tid; e < nr * nr; e += BNT) {
-      const int r = j + 1 + e / nr, c = j + 1 + (e - (e / nr) * nr);
-      if (r <= c) G[r * SL + c] -= R[j * SL + r] * R[j * SL + c];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int bi = 0; bi < 5; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < 5; ++bj)
+          if (bj < nb) acc[bi][bj] = Mfma<double>::mma(xv[u][bi], xv[u][bj], acc[bi][bj]);
+  }
+  for (int w = 0; w < 8; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int bi = 0; bi < 5; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < 5; ++bj)
+          if (bj < nb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              double* o = out + (bi * 16 + drow(lk, v)) * SL + bj * 16 + li;
+              *o = (w == 0 ? 0.0 : *o) + acc[bi][bj][v];
+            }
+          }
     }
     __syncthreads();
   }
 }
 
-// X = R^{-1} (upper triangular, lp x lp in LDS): thread c solves R x = e_c by
-// back substitution for column c < l; rows / columns l .. lp-1 are the identity.
-__device__ __noinline__ void b_rinv(const double* R, double* X, int l, int lp) {
+// Cholesky G = R^T R of the leading l x l block (G = a, R = b; only the upper
+// triangle of G is read, and G is overwritten).  R is upper triangular with
+// zeros below the diagonal and the identity in rows / columns l .. lp-1.  A
+// pivot <= ETA_DEP * G_jj (or not positive) gives a unit row and sets the
+// flag.  Step j reads only row j of G and updates rows > j, so one barrier
+// per step suffices.
+__device__ __noinline__ void b_chol(int l, int lp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* G = g_lds.u.sm.a;
+  double* R = g_lds.u.sm.b;
+  for (int e = tid; e < lp * lp; e += BNT) {
+    const int r = e / lp, c = e - (e / lp) * lp;
+    R[r * SL + c] = (r == c && r >= l) ? 1.0 : 0.0;
+  }
+  for (int i = tid; i < l; i += BNT) g_lds.dgn[i] = G[i * SL + i];
+  __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    const double d = G[j * SL + j];
+    const bool dep = !(d > ETA_DEP * g_lds.dgn[j]);
+    if (dep) {
+      for (int c = j + tid; c < l; c += BNT) R[j * SL + c] = (c == j) ? 1.0 : 0.0;
+      if (tid == 0) g_lds.flag = 1;
+    } else {
+      const double sq = sqrt(d);
+      const double inv = 1.0 / d;
+      for (int c = j + tid; c < l; c += BNT) R[j * SL + c] = G[j * SL + c] / sq;
+      // G[r][c] -= G[j][r] G[j][c] / G[j][j] for j < r <= c < l
+      for (int r = j + 1 + wave; r < l; r += BNT / 64) {
+        const double gr = G[j * SL + r] * inv;
+        for (int c = r + lane; c < l; c += 64) G[r * SL + c] -= gr * G[j * SL + c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// a = R^{-1} with R = b (upper triangular, lp x lp): four lanes per column c
+// solve R x = e_c by back substitution, each summing a quarter of every dot
+// product; rows / columns l .. lp-1 are the identity.
+__device__ __noinline__ void b_rinv(int l, int lp) {
   const int tid = threadIdx.x;
+  const double* R = g_lds.u.sm.b;
+  double* X = g_lds.u.sm.a;
   for (int e = tid; e < lp * lp; e += BNT) {
     const int r = e / lp, c = e - (e / lp) * lp;
     X[r * SL + c] = (r == c && r >= l) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int c = tid; c < l; c += BNT) {
+  const int grp = tid >> 2, sub = tid & 3;
+  for (int c = grp; c < l; c += BNT / 4) {
     for (int i = c; i >= 0; --i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int u = i + 1; u <= c; ++u) t -= R[i * SL + u] * X[u * SL + c];
-      X[i * SL + c] = t / R[i * SL + i];
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      int u = i + 1 + sub;
+      for (; u + 12 <= c; u += 16) {
+        t0 += R[i * SL + u] * X[u * SL + c];
+        t1 += R[i * SL + u + 4] * X[(u + 4) * SL + c];
+        t2 += R[i * SL + u + 8] * X[(u + 8) * SL + c];
+        t3 += R[i * SL + u + 12] * X[(u + 12) * SL + c];
+      }
+      for (; u <= c; u += 4) t0 += R[i * SL + u] * X[u * SL + c];
+      double t = (t0 + t1) + (t2 + t3);
+      t += __shfl_xor(t, 1, 64);
+      t += __shfl_xor(t, 2, 64);
+      if (sub == 0) X[i * SL + c] = ((i == c ? 1.0 : 0.0) - t) / R[i * SL + i];
     }
   }
   __syncthreads();
 }
 
-// Out (rows x ncols, ldo) = In (rows x K, ld lp) B (B in LDS, stride SL, K x N
-// with N = rup(ncols, 16) <= 80), on FP64 MFMA.
+// Out (rows x ncols, ldo) = In (rows x K, ld lp) a (K x N in LDS, stride SL,
+// N = rup(ncols, 16) <= 80), on FP64 MFMA; a 16-row block's K/4 operands are
+// loaded before its products.
 template <typename TI, typename TO>
-__device__ __noinline__ void b_apply(const TI* __restrict__ In, int lp, int64_t rows, int K, const double* B,
-                        int ncols, TO* __restrict__ Out, int64_t ldo) {
+__device__ __noinline__ void b_apply(const TI* __restrict__ In, int lp, int64_t rows, int K,
+                                     int ncols, TO* __restrict__ Out, int64_t ldo) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const double* B = g_lds.u.sm.a;
   const int ncb = (ncols + 15) / 16;
   const int64_t nrb = cdiv(rows, 16);
   for (int64_t rb = wave; rb < nrb; rb += 8) {
+    const int64_t r = rb * 16 + li;
+    const bool ok = r < rows;
+    double av[BLMAX / 4];
+#pragma unroll
+    for (int t = 0; t < BLMAX / 4; ++t) {
+      const int k = 4 * t + lk;
+      av[t] = (ok && k < K) ? to_d(In[r * lp + k]) : 0.0;
+    }
     d4 acc[5];
 #pragma unroll
     for (int cb = 0; cb < 5; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t r = rb * 16 + li;
-    const bool ok = r < rows;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lk;
-      const double a = (ok && k < K) ? to_d(In[r * lp + k]) : 0.0;
 #pragma unroll
-      for (int cb = 0; cb < 5; ++cb)
-        if (cb < ncb) {
-          const double bv = k < K ? B[k * SL + cb * 16 + li] : 0.0;
-          acc[cb] = Mfma<double>::mma(a, bv, acc[cb]);
-        }
+    for (int t = 0; t < BLMAX / 4; ++t) {
+      if (4 * t < K) {
+        const int k = 4 * t + lk;
+#pragma unroll
+        for (int cb = 0; cb < 5; ++cb)
+          if (cb < ncb) acc[cb] = Mfma<double>::mma(av[t], B[k * SL + cb * 16 + li], acc[cb]);
+      }
     }
 #pragma unroll
     for (int cb = 0; cb < 5; ++cb) {
@@ -382,29 +516,28 @@ __device__ __noinline__ void b_apply(const TI* __restrict__ In, int lp, int64_t 
 // Q (rows x lp) = orth(In) by CholeskyQR2 in FP64; T (rows x lp FP64) holds
 // the first pass.
 template <typename TI, typename TO>
-__device__ void b_orth(Lds& s, const TI* In, int64_t rows, int l, int lp, double* T, TO* Q) {
-  b_xty(s, In, In, rows, lp, s.a);
-  b_chol(s, s.a, s.b, l, lp);
-  b_rinv(s.b, s.a, l, lp);
-  b_apply(In, lp, rows, lp, s.a, lp, T, lp);
-  b_xty(s, T, T, rows, lp, s.a);
-  b_chol(s, s.a, s.b, l, lp);
-  b_rinv(s.b, s.a, l, lp);
-  b_apply(T, lp, rows, lp, s.a, lp, Q, lp);
+__device__ void b_orth(const TI* In, int64_t rows, int l, int lp, double* T, TO* Q) {
+  b_gram(In, rows, lp);
+  b_chol(l, lp);
+  b_rinv(l, lp);
+  b_apply(In, lp, rows, lp, lp, T, (int64_t)lp);
+  b_gram(T, rows, lp);
+  b_chol(l, lp);
+  b_rinv(l, lp);
+  b_apply(T, lp, rows, lp, lp, Q, (int64_t)lp);
 }
 
-// One-sided Jacobi on the l x l Rh held in s.a (stride SL): W = Rh (columns
-// contiguous, in s.b ... ) -- see the body for the buffer use.  Writes the k
-// largest sigma to S and Uh, Vh (l x k, ld lp) to global scratch.
-__device__ __noinline__ void b_jacobi(Lds& s, int l, int k, double* S, double* Uh, double* Vh, int lp,
-                         int32_t* info) {
+// One-sided Jacobi on the l x l Rh held in a (stride SL): W (column j
+// contiguous, ld l) goes to b and V = I to a.  Writes the k largest sigma to
+// S and Uh, Vh (l x k, ld lp) to global scratch.
+__device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, double* Vh, int lp,
+                                      int32_t* info) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // W (column j contiguous, ld l) into s.b from Rh in s.a; V = I into s.a
-  double* W = s.b;
-  double* V = s.a;
+  double* W = g_lds.u.sm.b;
+  double* V = g_lds.u.sm.a;
   for (int e = tid; e < l * l; e += BNT) {
     const int j = e / l, i = e - (e / l) * l;
-    W[j * l + i] = s.a[i * SL + j];
+    W[j * l + i] = V[i * SL + j];
   }
   __syncthreads();
   for (int e = tid; e < l * l; e += BNT) {
@@ -418,7 +551,7 @@ __device__ __noinline__ void b_jacobi(Lds& s, int l, int k, double* S, double* U
   bool converged = (l < 2);
   while (!converged && sweep < JAC_MAX_SWEEPS) {
     ++sweep;
-    if (tid == 0) s.flag = 0;
+    if (tid == 0) g_lds.flag = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       for (int pi = wave; pi < N / 2; pi += BNT / 64) {
@@ -426,21 +559,22 @@ __device__ __noinline__ void b_jacobi(Lds& s, int l, int k, double* S, double* U
         if (a >= l || b >= l) continue;
         if (a > b) { const int t = a; a = b; b = t; }
         if (rotate_pair(W + a * l, W + b * l, V + a * l, V + b * l, l, lane, tol) && lane == 0)
-          s.flag = 1;
+          g_lds.flag = 1;
       }
       __syncthreads();
     }
-    converged = (s.flag == 0);
+    converged = (g_lds.flag == 0);
     __syncthreads();
   }
   if (!converged && tid == 0) info_or(info, INFO_JACOBI_CAP);
-  jacobi_finish<BNT>(W, V, l, l, k, s.sig, S, Uh, lp, Vh, lp);
+  jacobi_finish<BNT>(W, V, l, l, k, g_lds.sig, S, Uh, lp, Vh, lp);
   __syncthreads();
 }
 
-// B (in LDS, stride SL, lp x rup(k,16)) = the l x k matrix M (ld lp, global),
-// zero elsewhere
-__device__ void b_load_small(const double* M, int l, int k, int lp, double* B) {
+// a (stride SL, lp x rup(k,16)) = the l x k matrix M (ld lp, global), zero
+// elsewhere
+__device__ void b_load_small(const double* M, int l, int k, int lp) {
+  double* B = g_lds.u.sm.a;
   const int nc = (int)rup(k, 16);
   for (int e = threadIdx.x; e < lp * nc; e += BNT) {
     const int r = e / nc, c = e - (e / nc) * nc;
@@ -450,7 +584,6 @@ __device__ void b_load_small(const double* M, int l, int k, int lp, double* B) {
 }
 
 __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
-  __shared__ Lds s;
   const int tid = threadIdx.x;
   char* slot = g.scratch + (int64_t)blockIdx.x * g.slot_bytes;
   float* Om = reinterpret_cast<float*>(slot + g.off_om);
@@ -463,35 +596,35 @@ __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
   double* Uh = reinterpret_cast<double*>(slot + g.off_uh);
   double* Vh = reinterpret_cast<double*>(slot + g.off_vh);
   for (;;) {
-    if (tid == 0) s.item = atomicAdd(g.counter, 1);
+    if (tid == 0) g_lds.item = atomicAdd(g.counter, 1);
     __syncthreads();
-    const int64_t it = s.item;
+    const int64_t it = g_lds.item;
     __syncthreads();
     if (it >= g.count) break;
     const BatchDesc d = g.desc[it];
     const int64_t m = d.m, n = d.n;
     const int l = d.l, lp = d.lp, k = d.k;
     const float* A = g.A + d.a_off;
-    if (tid == 0) s.flag = 0;
+    if (tid == 0) g_lds.flag = 0;
     __syncthreads();
     b_sketch(Om, n, l, lp, g.k0, g.k1, (uint32_t)d.index);
-    b_pass_n(s, A, d.lda, m, n, Om, Y, lp);
+    b_pass_n(A, d.lda, m, n, Om, Y, lp);
     for (int j = 0; j < g.q; ++j) {
-      b_orth(s, Y, m, l, lp, T, Q);
-      b_pass_t(s, A, d.lda, m, n, Q, Z, lp);
-      b_orth(s, Z, n, l, lp, T, Zq);
-      b_pass_n(s, A, d.lda, m, n, Zq, Y, lp);
+      b_orth(Y, m, l, lp, T, Q);
+      b_pass_t(A, d.lda, m, n, Q, Z, lp);
+      b_orth(Z, n, l, lp, T, Zq);
+      b_pass_n(A, d.lda, m, n, Zq, Y, lp);
     }
-    b_orth(s, Y, m, l, lp, T, Q);
-    b_pass_t(s, A, d.lda, m, n, Q, Z, lp);          // B^T
-    b_orth(s, Z, n, l, lp, T, Qh);
-    b_xty(s, Qh, Z, n, lp, s.a);                    // Rh = Qh^T B^T
-    if (tid == 0 && s.flag) info_or(g.info, INFO_ORTH_FALLBACK);
-    b_jacobi(s, l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
-    b_load_small(Vh, l, k, lp, s.a);
-    b_apply(Q, lp, m, lp, s.a, k, g.U + d.u_off, (int64_t)k);
-    b_load_small(Uh, l, k, lp, s.a);
-    b_apply(Qh, lp, n, lp, s.a, k, g.V + d.v_off, (int64_t)k);
+    b_orth(Y, m, l, lp, T, Q);
+    b_pass_t(A, d.lda, m, n, Q, Z, lp);          // B^T
+    b_orth(Z, n, l, lp, T, Qh);
+    b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
+    if (tid == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
+    b_jacobi(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
+    b_load_small(Vh, l, k, lp);
+    b_apply(Q, lp, m, lp, k, g.U + d.u_off, (int64_t)k);
+    b_load_small(Uh, l, k, lp);
+    b_apply(Qh, lp, n, lp, k, g.V + d.v_off, (int64_t)k);
   }
 }
 
