@@ -22,7 +22,7 @@
 //    a pivot below 1e-13 G_jj marks a dependent column (unit row of R, info
 //    bit 1);
 //  * the Jacobi SVD of the l x l factor in LDS (the rotations of the
-//    single-matrix small SVD);
+//    single-matrix small SVD, one column pair per 16 lanes);
 //  * U and V on FP64 MFMA, written in FP32.
 // Skinny matrices live in a per-workgroup slot of the workspace (L2-resident
 // for the sizes of a batch), small factors in LDS (l <= 80).
@@ -38,9 +38,13 @@ constexpr int BNT = 512;             // 8 waves
 constexpr int BLMAX = BATCH_MAX_LP;  // lp <= 80
 constexpr int SL = BLMAX + 1;        // LDS row stride of the small FP64 matrices
 constexpr int KC = 64;               // depth of a pass chunk
-constexpr int ALD = KC + 1;          // pass: A tile row stride (floats), 128 x KC
-constexpr int ATLD = 132;            // pass A^T: A tile row stride (floats), KC x 128
-constexpr int XLD = 84;              // skinny chunk row stride (floats), KC x lp
+// LDS row strides (floats), chosen so that the operand reads of a wave hit
+// distinct banks: lane (li, lk) reads row li (stride 68 = 4 mod 64) at
+// column lk of the A tile, and row lk (stride 80 = 16 mod 64, 144 = 16 mod
+// 64) at column li of the skinny chunk and of the A^T tile
+constexpr int ALD = 68;              // pass: A tile row stride, 128 x KC
+constexpr int ATLD = 144;            // pass A^T: A tile row stride, KC x 128
+constexpr int XLD = 80;              // skinny chunk row stride, KC x lp
 constexpr int STAGE_N = 2 * (128 * ALD + KC * XLD);
 constexpr int STAGE_T = 2 * (KC * ATLD + KC * XLD);
 constexpr int STAGE_FLOATS = STAGE_N > STAGE_T ? STAGE_N : STAGE_T;
@@ -527,12 +531,59 @@ __device__ void b_orth(const TI* In, int64_t rows, int l, int lp, double* T, TO*
   b_apply(T, lp, rows, lp, lp, Q, (int64_t)lp);
 }
 
+// Rotation of the column pair (a, b) of W and V (columns contiguous, length
+// l <= 80) by one group of 16 lanes: lane li holds rows li, li + 16, ...;
+// the dot products are 16-lane sums.  Returns true when a rotation was
+// applied (the same value on every lane of the group).
+__device__ __forceinline__ bool rotate_pair16(double* wa, double* wb, double* va, double* vb,
+                                              int l, int li, double tol) {
+  double xa[5], xb[5];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int i = li + 16 * t;
+    xa[t] = i < l ? wa[i] : 0.0;
+    xb[t] = i < l ? wb[i] : 0.0;
+    al = fma(xa[t], xa[t], al);
+    be = fma(xb[t], xb[t], be);
+    ga = fma(xa[t], xb[t], ga);
+  }
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    al += __shfl_xor(al, off, 16);
+    be += __shfl_xor(be, off, 16);
+    ga += __shfl_xor(ga, off, 16);
+  }
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int i = li + 16 * t;
+    if (i < l) {
+      wa[i] = cs * xa[t] - sn * xb[t];
+      wb[i] = sn * xa[t] + cs * xb[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    const int i = li + 16 * t;
+    if (i < l) {
+      const double y = va[i], z = vb[i];
+      va[i] = cs * y - sn * z;
+      vb[i] = sn * y + cs * z;
+    }
+  }
+  return true;
+}
+
 // One-sided Jacobi on the l x l Rh held in a (stride SL): W (column j
-// contiguous, ld l) goes to b and V = I to a.  Writes the k largest sigma to
-// S and Uh, Vh (l x k, ld lp) to global scratch.
+// contiguous, ld l) goes to b and V = I to a.  Round-robin rounds of
+// disjoint pairs, one pair per group of 16 lanes (32 groups).  Writes the k
+// largest sigma to S and Uh, Vh (l x k, ld lp) to global scratch.
 __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, double* Vh, int lp,
                                       int32_t* info) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
+  const int grp = tid >> 4, li = tid & 15;
   double* W = g_lds.u.sm.b;
   double* V = g_lds.u.sm.a;
   for (int e = tid; e < l * l; e += BNT) {
@@ -554,11 +605,11 @@ __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, doubl
     if (tid == 0) g_lds.flag = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int pi = wave; pi < N / 2; pi += BNT / 64) {
+      for (int pi = grp; pi < N / 2; pi += BNT / 16) {
         int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
         if (a >= l || b >= l) continue;
         if (a > b) { const int t = a; a = b; b = t; }
-        if (rotate_pair(W + a * l, W + b * l, V + a * l, V + b * l, l, lane, tol) && lane == 0)
+        if (rotate_pair16(W + a * l, W + b * l, V + a * l, V + b * l, l, li, tol) && li == 0)
           g_lds.flag = 1;
       }
       __syncthreads();
