@@ -55,7 +55,7 @@ constexpr int JAC_MAX_SWEEPS = 40;
 // small factorizations use a, b (lp x lp FP64, stride SL) and the Gram
 // partials.  Declared at namespace scope so that every helper addresses it
 // as LDS even when it is not inlined.
-struct BatchLds {
+struct alignas(16) BatchLds {
   union {
     struct {
       double a[BLMAX * SL];
@@ -126,26 +126,28 @@ __device__ __forceinline__ float4 ld_a4(const float* A, int64_t lda, int64_t m, 
   return v;
 }
 
+// 16-byte store (p is 16-byte aligned: every tile stride is a multiple of 4)
 __device__ __forceinline__ void st4(float* p, const float4& v) {
-  p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+  *reinterpret_cast<float4*>(p) = v;
 }
 
-// Y (m x lp) = A X, A m x n (FP32, lda % 4 == 0), X n x lp (FP32).  Row tiles
-// of 128 (16 rows per wave), KC-deep chunks of A and X in LDS.
+// Y (m x lp) = A X, A m x n (FP32, lda % 4 == 0), X n x lp (FP32), lp = 16 NCB.
+// Row tiles of 128 (16 rows per wave), KC-deep chunks of A and X in LDS.
+template <int NCB>
 __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
-                                      float* __restrict__ Y, int lp) {
+                                      float* __restrict__ Y) {
+  constexpr int lp = 16 * NCB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ncb = lp / 16;
   float* st = g_lds.u.stage;
   const int xq = lp / 4;                                // float4 per X row
   const int xn = KC * xq;                               // float4 per X chunk
   const int64_t nkc = cdiv(n, KC);
   for (int64_t row0 = 0; row0 < m; row0 += 128) {
-    f4 acc[5];
+    f4 acc[NCB];
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
     float4 av[4], xv[3];
     auto gload = [&](int64_t kc) {
       const int64_t k0 = kc * KC;
@@ -191,43 +193,42 @@ __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, 
       for (int kk = 0; kk < KC / 4; ++kk) {
         const float a = as[(wave * 16 + li) * ALD + kk * 4 + lk];
 #pragma unroll
-        for (int cb = 0; cb < 5; ++cb)
-          if (cb < ncb)
-            acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) {
-      if (cb < ncb) {
+    for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t r = row0 + wave * 16 + Mfma<float>::row(lk, v);
-          if (r < m) Y[r * lp + cb * 16 + li] = acc[cb][v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + wave * 16 + Mfma<float>::row(lk, v);
+        if (r < m) Y[r * lp + cb * 16 + li] = acc[cb][v];
       }
     }
   }
   __syncthreads();
 }
 
-// Z (n x lp) = A^T X, A m x n (FP32, lda % 4 == 0), X m x lp (FP32).  Tiles
-// of 128 columns of A (16 per wave), KC-row chunks of A and X in LDS.
+// Z (n x lp) = A^T X, A m x n (FP32, lda % 4 == 0), X m x lp (FP32), lp = 16 NCB.
+// Tiles of 128 columns of A (16 per wave), KC-row chunks of A and X in LDS.
+template <int NCB>
 __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
-                                      float* __restrict__ Z, int lp) {
+                                      float* __restrict__ Z) {
+  constexpr int lp = 16 * NCB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ncb = lp / 16;
   float* st = g_lds.u.stage;
   const int xq = lp / 4;
   const int xn = KC * xq;
   const int64_t nkc = cdiv(m, KC);
   for (int64_t col0 = 0; col0 < n; col0 += 128) {
-    f4 acc[5];
+    f4 acc[NCB];
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
     float4 av[4], xv[3];
     auto gload = [&](int64_t kc) {
       const int64_t r0 = kc * KC;
@@ -274,21 +275,19 @@ __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, 
         // A^T[col][row]: column wave*16 + li of the tile, row kk*4 + lk
         const float a = as[(kk * 4 + lk) * ATLD + wave * 16 + li];
 #pragma unroll
-        for (int cb = 0; cb < 5; ++cb)
-          if (cb < ncb)
-            acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) {
-      if (cb < ncb) {
+    for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t c = col0 + wave * 16 + Mfma<float>::row(lk, v);
-          if (c < n) Z[c * lp + cb * 16 + li] = acc[cb][v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t c = col0 + wave * 16 + Mfma<float>::row(lk, v);
+        if (c < n) Z[c * lp + cb * 16 + li] = acc[cb][v];
       }
     }
   }
@@ -352,49 +351,46 @@ __device__ __noinline__ void b_xty(const TX* __restrict__ X, const TY* __restric
 // on FP64 MFMA.  Wave w forms every upper block over its eighth of the rows
 // (two 4-row steps loaded before their products); the eight partial Grams
 // are added into a in wave order.
-template <typename TX>
-__device__ __noinline__ void b_gram(const TX* __restrict__ X, int64_t rows, int lp) {
+template <int NB, typename TX>
+__device__ __noinline__ void b_gram(const TX* __restrict__ X, int64_t rows) {
+  constexpr int lp = 16 * NB, nb = NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int nb = lp / 16;
   double* out = g_lds.u.sm.a;
   const int64_t nsteps = cdiv(rows, 4);
   const int64_t st0 = wave * nsteps / 8, st1 = (wave + 1) * nsteps / 8;
-  d4 acc[5][5];
+  d4 acc[NB][NB];
 #pragma unroll
-  for (int bi = 0; bi < 5; ++bi)
+  for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-    for (int bj = bi; bj < 5; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int bj = bi; bj < NB; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t st = st0; st < st1; st += 2) {
-    double xv[2][5];
+    double xv[2][NB];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int64_t r = (st + u) * 4 + lk;
       const bool ok = st + u < st1 && r < rows;
 #pragma unroll
-      for (int bi = 0; bi < 5; ++bi)
-        xv[u][bi] = (ok && bi < nb) ? to_d(X[r * lp + bi * 16 + li]) : 0.0;
+      for (int bi = 0; bi < NB; ++bi) xv[u][bi] = ok ? to_d(X[r * lp + bi * 16 + li]) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int bi = 0; bi < 5; ++bi)
+      for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = bi; bj < 5; ++bj)
-          if (bj < nb) acc[bi][bj] = Mfma<double>::mma(xv[u][bi], xv[u][bj], acc[bi][bj]);
+        for (int bj = bi; bj < NB; ++bj)
+          acc[bi][bj] = Mfma<double>::mma(xv[u][bi], xv[u][bj], acc[bi][bj]);
   }
   for (int w = 0; w < 8; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int bi = 0; bi < 5; ++bi)
+      for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = bi; bj < 5; ++bj)
-          if (bj < nb) {
+        for (int bj = bi; bj < NB; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              double* o = out + (bi * 16 + drow(lk, v)) * SL + bj * 16 + li;
-              *o = (w == 0 ? 0.0 : *o) + acc[bi][bj][v];
-            }
+          for (int v = 0; v < 4; ++v) {
+            double* o = out + (bi * 16 + drow(lk, v)) * SL + bj * 16 + li;
+            *o = (w == 0 ? 0.0 : *o) + acc[bi][bj][v];
           }
     }
     __syncthreads();
@@ -470,47 +466,42 @@ __device__ __noinline__ void b_rinv(int l, int lp) {
   __syncthreads();
 }
 
-// Out (rows x ncols, ldo) = In (rows x K, ld lp) a (K x N in LDS, stride SL,
-// N = rup(ncols, 16) <= 80), on FP64 MFMA; a 16-row block's K/4 operands are
-// loaded before its products.
-template <typename TI, typename TO>
-__device__ __noinline__ void b_apply(const TI* __restrict__ In, int lp, int64_t rows, int K,
-                                     int ncols, TO* __restrict__ Out, int64_t ldo) {
+// Out (rows x ncols, ldo) = In (rows x lp, lp = 16 NB) a (lp x lp in LDS,
+// stride SL; columns >= ncols are formed but not written), on FP64 MFMA; a
+// 16-row block's operands are loaded before its products.
+template <int NB, typename TI, typename TO>
+__device__ __noinline__ void b_apply(const TI* __restrict__ In, int64_t rows, int ncols,
+                                     TO* __restrict__ Out, int64_t ldo) {
+  constexpr int lp = 16 * NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const double* B = g_lds.u.sm.a;
-  const int ncb = (ncols + 15) / 16;
   const int64_t nrb = cdiv(rows, 16);
   for (int64_t rb = wave; rb < nrb; rb += 8) {
     const int64_t r = rb * 16 + li;
     const bool ok = r < rows;
-    double av[BLMAX / 4];
+    double av[4 * NB];
 #pragma unroll
-    for (int t = 0; t < BLMAX / 4; ++t) {
+    for (int t = 0; t < 4 * NB; ++t) av[t] = ok ? to_d(In[r * lp + 4 * t + lk]) : 0.0;
+    d4 acc[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4 * NB; ++t) {
       const int k = 4 * t + lk;
-      av[t] = (ok && k < K) ? to_d(In[r * lp + k]) : 0.0;
-    }
-    d4 acc[5];
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < BLMAX / 4; ++t) {
-      if (4 * t < K) {
-        const int k = 4 * t + lk;
-#pragma unroll
-        for (int cb = 0; cb < 5; ++cb)
-          if (cb < ncb) acc[cb] = Mfma<double>::mma(av[t], B[k * SL + cb * 16 + li], acc[cb]);
-      }
+      for (int cb = 0; cb < NB; ++cb)
+        acc[cb] = Mfma<double>::mma(av[t], B[k * SL + cb * 16 + li], acc[cb]);
+      // keep each step's LDS reads next to its products (bounded registers)
+      if (t % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int cb = 0; cb < 5; ++cb) {
-      if (cb < ncb) {
-        const int c = cb * 16 + li;
+    for (int cb = 0; cb < NB; ++cb) {
+      const int c = cb * 16 + li;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t rr = rb * 16 + drow(lk, v);
-          if (rr < rows && c < ncols) Out[rr * ldo + c] = from_d<TO>(acc[cb][v]);
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t rr = rb * 16 + drow(lk, v);
+        if (rr < rows && c < ncols) Out[rr * ldo + c] = from_d<TO>(acc[cb][v]);
       }
     }
   }
@@ -519,16 +510,17 @@ __device__ __noinline__ void b_apply(const TI* __restrict__ In, int lp, int64_t 
 
 // Q (rows x lp) = orth(In) by CholeskyQR2 in FP64; T (rows x lp FP64) holds
 // the first pass.
-template <typename TI, typename TO>
-__device__ void b_orth(const TI* In, int64_t rows, int l, int lp, double* T, TO* Q) {
-  b_gram(In, rows, lp);
+template <int NB, typename TI, typename TO>
+__device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
+  constexpr int lp = 16 * NB;
+  b_gram<NB>(In, rows);
   b_chol(l, lp);
   b_rinv(l, lp);
-  b_apply(In, lp, rows, lp, lp, T, (int64_t)lp);
-  b_gram(T, rows, lp);
+  b_apply<NB>(In, rows, lp, T, (int64_t)lp);
+  b_gram<NB>(T, rows);
   b_chol(l, lp);
   b_rinv(l, lp);
-  b_apply(T, lp, rows, lp, lp, Q, (int64_t)lp);
+  b_apply<NB>(T, rows, lp, Q, (int64_t)lp);
 }
 
 // Rotation of the column pair (a, b) of W and V (columns contiguous, length
@@ -622,16 +614,42 @@ __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, doubl
   __syncthreads();
 }
 
-// a (stride SL, lp x rup(k,16)) = the l x k matrix M (ld lp, global), zero
-// elsewhere
+// a (stride SL, lp x lp) = the l x k matrix M (ld lp, global), zero elsewhere
 __device__ void b_load_small(const double* M, int l, int k, int lp) {
   double* B = g_lds.u.sm.a;
-  const int nc = (int)rup(k, 16);
+  const int nc = lp;
   for (int e = threadIdx.x; e < lp * nc; e += BNT) {
     const int r = e / nc, c = e - (e / nc) * nc;
     B[r * SL + c] = (r < l && c < k) ? M[r * lp + c] : 0.0;
   }
   __syncthreads();
+}
+
+// The decomposition of one matrix after its sketch, for lp = 16 NB.
+template <int NB>
+__device__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A, const float* Om,
+                      float* Y, float* Q, float* Z, float* Zq, double* T, double* Qh,
+                      double* Uh, double* Vh) {
+  constexpr int lp = 16 * NB;
+  const int64_t m = d.m, n = d.n;
+  const int l = d.l, k = d.k;
+  b_pass_n<NB>(A, d.lda, m, n, Om, Y);
+  for (int j = 0; j < g.q; ++j) {
+    b_orth<NB>(Y, m, l, T, Q);
+    b_pass_t<NB>(A, d.lda, m, n, Q, Z);
+    b_orth<NB>(Z, n, l, T, Zq);
+    b_pass_n<NB>(A, d.lda, m, n, Zq, Y);
+  }
+  b_orth<NB>(Y, m, l, T, Q);
+  b_pass_t<NB>(A, d.lda, m, n, Q, Z);          // B^T
+  b_orth<NB>(Z, n, l, T, Qh);
+  b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
+  if (threadIdx.x == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
+  b_jacobi(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
+  b_load_small(Vh, l, k, lp);
+  b_apply<NB>(Q, m, k, g.U + d.u_off, (int64_t)k);
+  b_load_small(Uh, l, k, lp);
+  b_apply<NB>(Qh, n, k, g.V + d.v_off, (int64_t)k);
 }
 
 __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
@@ -653,29 +671,18 @@ __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
     __syncthreads();
     if (it >= g.count) break;
     const BatchDesc d = g.desc[it];
-    const int64_t m = d.m, n = d.n;
-    const int l = d.l, lp = d.lp, k = d.k;
+    const int lp = d.lp;
     const float* A = g.A + d.a_off;
     if (tid == 0) g_lds.flag = 0;
     __syncthreads();
-    b_sketch(Om, n, l, lp, g.k0, g.k1, (uint32_t)d.index);
-    b_pass_n(A, d.lda, m, n, Om, Y, lp);
-    for (int j = 0; j < g.q; ++j) {
-      b_orth(Y, m, l, lp, T, Q);
-      b_pass_t(A, d.lda, m, n, Q, Z, lp);
-      b_orth(Z, n, l, lp, T, Zq);
-      b_pass_n(A, d.lda, m, n, Zq, Y, lp);
+    b_sketch(Om, d.n, d.l, lp, g.k0, g.k1, (uint32_t)d.index);
+    switch (lp / 16) {
+      case 1: b_one<1>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
+      case 2: b_one<2>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
+      case 3: b_one<3>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
+      case 4: b_one<4>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
+      default: b_one<5>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
     }
-    b_orth(Y, m, l, lp, T, Q);
-    b_pass_t(A, d.lda, m, n, Q, Z, lp);          // B^T
-    b_orth(Z, n, l, lp, T, Qh);
-    b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
-    if (tid == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
-    b_jacobi(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
-    b_load_small(Vh, l, k, lp);
-    b_apply(Q, lp, m, lp, k, g.U + d.u_off, (int64_t)k);
-    b_load_small(Uh, l, k, lp);
-    b_apply(Qh, lp, n, lp, k, g.V + d.v_off, (int64_t)k);
   }
 }
 
