@@ -523,51 +523,6 @@ __device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
   b_apply<NB>(T, rows, lp, Q, (int64_t)lp);
 }
 
-// Rotation of the column pair (a, b) of W and V (columns contiguous, length
-// l <= 80) by one group of 16 lanes: lane li holds rows li, li + 16, ...;
-// the dot products are 16-lane sums.  Returns true when a rotation was
-// applied (the same value on every lane of the group).
-__device__ __forceinline__ bool rotate_pair16(double* wa, double* wb, double* va, double* vb,
-                                              int l, int li, double tol) {
-  double xa[5], xb[5];
-  double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-  for (int t = 0; t < 5; ++t) {
-    const int i = li + 16 * t;
-    xa[t] = i < l ? wa[i] : 0.0;
-    xb[t] = i < l ? wb[i] : 0.0;
-    al = fma(xa[t], xa[t], al);
-    be = fma(xb[t], xb[t], be);
-    ga = fma(xa[t], xb[t], ga);
-  }
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) {
-    al += __shfl_xor(al, off, 16);
-    be += __shfl_xor(be, off, 16);
-    ga += __shfl_xor(ga, off, 16);
-  }
-  double cs, sn;
-  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
-#pragma unroll
-  for (int t = 0; t < 5; ++t) {
-    const int i = li + 16 * t;
-    if (i < l) {
-      wa[i] = cs * xa[t] - sn * xb[t];
-      wb[i] = sn * xa[t] + cs * xb[t];
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < 5; ++t) {
-    const int i = li + 16 * t;
-    if (i < l) {
-      const double y = va[i], z = vb[i];
-      va[i] = cs * y - sn * z;
-      vb[i] = sn * y + cs * z;
-    }
-  }
-  return true;
-}
-
 // One-sided Jacobi on the l x l Rh held in a (stride SL): W (column j
 // contiguous, ld l) goes to b and V = I to a.  Round-robin rounds of
 // disjoint pairs, one pair per group of 16 lanes (32 groups).  Writes the k
@@ -601,7 +556,7 @@ __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, doubl
         int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
         if (a >= l || b >= l) continue;
         if (a > b) { const int t = a; a = b; b = t; }
-        if (rotate_pair16(W + a * l, W + b * l, V + a * l, V + b * l, l, li, tol) && li == 0)
+        if (rotate_pair16<5>(W + a * l, W + b * l, V + a * l, V + b * l, l, li, tol) && li == 0)
           g_lds.flag = 1;
       }
       __syncthreads();

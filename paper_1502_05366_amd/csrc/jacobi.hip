@@ -11,9 +11,9 @@
 // Uh_j = w_j / sigma_j, Vh_j = v_j, so R_hat = Uh diag(sigma) Vh^T.
 //
 // Pairs are scheduled in round-robin rounds of disjoint pairs (circle
-// method), one pair per wave at a time; the dot products are wave
-// reductions.  Small factors (l <= 64) run in one workgroup with W and V in
-// LDS; larger ones run as a block Jacobi over several workgroups (below).
+// method).  Small factors (l <= 96) run in one workgroup with W and V in LDS,
+// one pair per group of 16 lanes (16-lane sums); larger ones run as a block
+// Jacobi over several workgroups (below).
 // Output: the k largest sigma in descending order (stable for ties) and the
 // matching columns of Uh and Vh.
 #include "common.h"
@@ -24,7 +24,7 @@ namespace rsvd {
 namespace {
 
 constexpr int JNT = 1024;
-constexpr int LDS_MAX_L = 64;     // 2 * 64 * 64 * 8 B = 64 KB
+constexpr int LDS_MAX_L = 96;     // 2 * 96 * 96 * 8 B = 144 KB of LDS
 
 // l <= LDS_MAX_L: the whole iteration in one workgroup, W and V in LDS.
 __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restrict__ Rh, int64_t ldr,
@@ -53,11 +53,14 @@ __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restric
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
-      for (int pi = wave; pi < N / 2; pi += JNT / 64) {
+      // one pair per group of 16 lanes (64 groups: every pair of a round at once)
+      for (int pi = tid >> 4; pi < N / 2; pi += JNT / 16) {
         int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
         if (a >= l || b >= l) continue;
         if (a > b) { const int t = a; a = b; b = t; }
-        if (rotate_pair(W + a * ld, W + b * ld, V + a * ld, V + b * ld, l, lane, tol) && lane == 0)
+        if (rotate_pair16<LDS_MAX_L / 16>(W + a * ld, W + b * ld, V + a * ld, V + b * ld, l,
+                                          tid & 15, tol) &&
+            (tid & 15) == 0)
           rotated = 1;
       }
       __syncthreads();
@@ -367,6 +370,12 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
   const double tol = (double)l * 2.220446049250313e-16;
   if (l <= LDS_MAX_L) {
     const size_t shm = 2 * (size_t)l * l * sizeof(double);
+    if (shm > 65536) {
+      const hipError_t e = hipFuncSetAttribute((const void*)jacobi_lds_kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)shm);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(JNT), shm, s, Rh, ldr, l, k, S, Uh, lduh,
                        Vh, ldvh, max_sweeps, tol, info);
     return hipGetLastError();

@@ -48,6 +48,52 @@ __device__ __forceinline__ int rr_player(int pos, int r, int N) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (N - 1)) + 1;
 }
 
+// Rotation of the column pair (a, b) of W and V (columns contiguous, length
+// l <= 16 RPL) by one group of 16 lanes: lane li holds rows li, li + 16, ...;
+// the dot products are 16-lane butterfly sums (the same value on every lane
+// of the group).  Returns true when a rotation was applied.
+template <int RPL>
+__device__ __forceinline__ bool rotate_pair16(double* wa, double* wb, double* va, double* vb,
+                                              int l, int li, double tol) {
+  double xa[RPL], xb[RPL];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = li + 16 * t;
+    xa[t] = i < l ? wa[i] : 0.0;
+    xb[t] = i < l ? wb[i] : 0.0;
+    al = fma(xa[t], xa[t], al);
+    be = fma(xb[t], xb[t], be);
+    ga = fma(xa[t], xb[t], ga);
+  }
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    al += __shfl_xor(al, off, 16);
+    be += __shfl_xor(be, off, 16);
+    ga += __shfl_xor(ga, off, 16);
+  }
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = li + 16 * t;
+    if (i < l) {
+      wa[i] = cs * xa[t] - sn * xb[t];
+      wb[i] = sn * xa[t] + cs * xb[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = li + 16 * t;
+    if (i < l) {
+      const double y = va[i], z = vb[i];
+      va[i] = cs * y - sn * z;
+      vb[i] = sn * y + cs * z;
+    }
+  }
+  return true;
+}
+
 // Singular values = column norms of W; the k largest (stable descending
 // order) go to S with Uh(:, rank) = w_j / sigma_j and Vh(:, rank) = v_j.
 // Called by every thread of a workgroup of NTH threads; sig has l entries.

@@ -136,7 +136,8 @@ def test_orth_fp32(R):
 # ---------------------------------------------------------- small SVD ----
 
 @pytest.mark.parametrize("l,k,decay", [(30, 20, 3), (64, 64, 6), (220, 200, 2.5), (1, 1, 0),
-                                       (131, 7, 1)])
+                                       (131, 7, 1), (80, 64, 4), (96, 96, 5), (65, 30, 3),
+                                       (97, 50, 3), (17, 5, 2)])
 def test_small_svd_vs_oracle(R, l, k, decay):
     g = np.random.default_rng(l)
     U0 = np.linalg.qr(g.standard_normal((l, l)))[0]
