@@ -11,7 +11,7 @@
 // Uh_j = w_j / sigma_j, Vh_j = v_j, so R_hat = Uh diag(sigma) Vh^T.
 //
 // Pairs are scheduled in round-robin rounds of disjoint pairs (circle
-// method).  Small factors (l <= 96) run in one workgroup with W and V in LDS,
+// method).  Small factors (l <= 64) run in one workgroup with W and V in LDS,
 // one pair per group of 16 lanes (16-lane sums); larger ones run as a block
 // Jacobi over several workgroups (below).
 // Output: the k largest sigma in descending order (stable for ties) and the
@@ -24,7 +24,10 @@ namespace rsvd {
 namespace {
 
 constexpr int JNT = 1024;
-constexpr int LDS_MAX_L = 96;     // 2 * 96 * 96 * 8 B = 144 KB of LDS
+// One workgroup up to l = 64 (2 * 64 * 64 * 8 B = 64 KB of LDS).  At l = 80 the
+// one-workgroup iteration measured 1.09 ms against 1.00 ms for the block
+// iteration on three workgroups, so larger factors take the block iteration.
+constexpr int LDS_MAX_L = 64;
 
 // l <= LDS_MAX_L: the whole iteration in one workgroup, W and V in LDS.
 __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restrict__ Rh, int64_t ldr,
