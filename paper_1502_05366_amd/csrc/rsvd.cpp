@@ -1301,7 +1301,8 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   hipError_t e = launch_set_word(info, 0, st);
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   const bool f32 = dtype == RSVD_F32;
-  if (e == hipSuccess) e = orth(c, ob, f32, Y, ldy, rows, (int)l, Q, f32, ldq, R ? Rfull : nullptr, lp);
+  if (e == hipSuccess)
+    e = orth(c, ob, f32, Y, ldy, rows, (int)l, Q, f32, ldq, R ? Rfull : nullptr, lp);
   if (e == hipSuccess && R)
     e = hipMemcpy2DAsync(R, ldr * sizeof(double), Rfull, lp * sizeof(double), l * sizeof(double),
                          l, hipMemcpyDeviceToDevice, st);

@@ -181,8 +181,8 @@ def test_batch_c4_full(R):
         assert np.abs(un.T @ un - np.eye(k)).max() <= 1e-5
         assert np.abs(vn.T @ vn - np.eye(k)).max() <= 1e-5
     work = ms * ns
-    pick = [int(np.argmax(work)), int(np.argmin(work))] + [int(i) for i in
-                                                           np.random.default_rng(3).choice(len(ms), 6, replace=False)]
+    others = np.random.default_rng(3).choice(len(ms), 6, replace=False)
+    pick = [int(np.argmax(work)), int(np.argmin(work))] + [int(i) for i in others]
     print("batch C4 oracle on %s" % pick, flush=True)
     res = {i: (views[i][0].double().cpu().numpy(), views[i][1].cpu().numpy(),
                views[i][2].double().cpu().numpy()) for i in pick}
