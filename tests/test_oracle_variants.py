@@ -123,3 +123,39 @@ def test_qb_tolerance_is_first_crossing():
     assert d["norms"][-1] < tol
     assert np.all(d["norms"][:-1] >= tol)
     assert d["Q"].shape[1] == 12 * d["nblocks"]
+
+
+# ------------------------------------------------------------- batch --------
+
+def test_batch_oracle_is_per_matrix_rsvd_with_its_sketch():
+    """Matrix i of a batch is the randomized SVD of that matrix alone with
+    the sketch of batch index i: different indices give different sketches,
+    and the batch result does not depend on the other matrices."""
+    A1, _ = W.logspace_type(60, 40, 1, seed=1)
+    A2, _ = W.logspace_type(50, 70, 2, seed=2)
+    res = O.batch_rsvd([A1, A2], [5, 7], 4, 1, 9)
+    for i, (A, k) in enumerate([(A1, 5), (A2, 7)]):
+        U, S, V = O.rsvd(A, k, 4, 1, 9, batch=i)
+        assert np.array_equal(res[i][1], S) and np.array_equal(res[i][0], U)
+    alone = O.batch_rsvd([A2], [7], 4, 1, 9)[0]
+    assert not np.array_equal(alone[1], res[1][1])          # batch index 0 vs 1
+    assert not np.allclose(philox.sketch(9, 40, 9, batch=0), philox.sketch(9, 40, 9, batch=1))
+
+
+def test_batch_oracle_exact_rank():
+    """Every matrix of exact rank <= k is reproduced, whatever its sketch."""
+    As, ks = [], []
+    for i, (m, n, r) in enumerate([(40, 30, 3), (25, 60, 5), (33, 33, 8)]):
+        A, _, _, _ = W.exact_rank_matrix(m, n, r, seed=40 + i)
+        As.append(A)
+        ks.append(r)
+    for A, (U, S, V) in zip(As, O.batch_rsvd(As, ks, 3, 1, 11)):
+        assert np.linalg.norm(A - (U * S) @ V.T) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_c4_dims_ranges():
+    m, n, k = W.c4_dims(500, seed=3)
+    assert m.min() >= 64 and m.max() <= 2048 and n.min() >= 64 and n.max() <= 1024
+    assert k.min() >= 4 and k.max() <= 64 and np.all(k <= np.minimum(m, n))
+    s = W.c4_spectrum(100, 50)
+    assert len(s) == 50 and abs(s[0] - np.exp(-1 / 8)) < 1e-15
