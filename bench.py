@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "82fec966bfb40cab49e9d49221198db3c2ecdb25038d585385e2ecedba212a73",
-                "bytes": 4588130000}
+PASS_TRAFFIC = {"sources": "87f0dd29a8d6de49b518b41fca2f7f251b590e259a4081ee7b2dc2765059ecda",
+                "bytes": 4588230000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 
 

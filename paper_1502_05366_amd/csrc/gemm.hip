@@ -233,13 +233,25 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
     const int64_t r = row0 + e / BN;
     const int64_t c = col0 + e % BN;
     if (r >= g.M || c >= g.L) continue;
-    TC s = TC(0);
-    for (int64_t w = wf; w <= wl; ++w) {
+    // four independent chains (workgroups w, w+1, w+2, w+3), added in a fixed
+    // order: the loads of four partial tiles are in flight at once
+    TC s[4] = {TC(0), TC(0), TC(0), TC(0)};
+    int64_t w = wf;
+    for (; w + 3 <= wl; w += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t wu = w + u;
+        const bool ok = range_begin(wu, g.U, g.G) != range_begin(wu + 1, g.U, g.G);
+        const int64_t slot = 2 * wu + (wu == wf ? 1 : 0);
+        s[u] += ok ? P[slot * (int64_t)(BM * BN) + e] : TC(0);
+      }
+    }
+    for (; w <= wl; ++w) {
       if (range_begin(w, g.U, g.G) == range_begin(w + 1, g.U, g.G)) continue;
       const int64_t slot = 2 * w + (w == wf ? 1 : 0);
-      s += P[slot * (int64_t)(BM * BN) + e];
+      s[0] += P[slot * (int64_t)(BM * BN) + e];
     }
-    C[r * g.ldc + c] = (TO)s;
+    C[r * g.ldc + c] = (TO)((s[0] + s[1]) + (s[2] + s[3]));
   }
 }
 
