@@ -525,8 +525,10 @@ __device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
 
 // One-sided Jacobi on the l x l Rh held in a (stride SL): W (column j
 // contiguous, ld l) goes to b and V = I to a.  Round-robin rounds of
-// disjoint pairs, one pair per group of 16 lanes (32 groups).  Writes the k
+// disjoint pairs, one pair per group of 16 lanes (32 groups), NB = lp / 16
+// rows per lane.  Writes the k
 // largest sigma to S and Uh, Vh (l x k, ld lp) to global scratch.
+template <int NB>
 __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, double* Vh, int lp,
                                       int32_t* info) {
   const int tid = threadIdx.x;
@@ -556,7 +558,7 @@ __device__ __noinline__ void b_jacobi(int l, int k, double* S, double* Uh, doubl
         int a = rr_player(pi, r, N), b = rr_player(N - 1 - pi, r, N);
         if (a >= l || b >= l) continue;
         if (a > b) { const int t = a; a = b; b = t; }
-        if (rotate_pair16<5>(W + a * l, W + b * l, V + a * l, V + b * l, l, li, tol) && li == 0)
+        if (rotate_pair16<NB>(W + a * l, W + b * l, V + a * l, V + b * l, l, li, tol) && li == 0)
           g_lds.flag = 1;
       }
       __syncthreads();
@@ -600,7 +602,7 @@ __device__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A, co
   b_orth<NB>(Z, n, l, T, Qh);
   b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
   if (threadIdx.x == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
-  b_jacobi(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
+  b_jacobi<NB>(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
   b_load_small(Vh, l, k, lp);
   b_apply<NB>(Q, m, k, g.U + d.u_off, (int64_t)k);
   b_load_small(Uh, l, k, lp);
