@@ -193,3 +193,13 @@ def test_batch_c4_full(R):
         Ug, Sg, Vg = res[i]
         assert np.abs(Sg - So).max() <= 1e-5 * So[0], i
         assert np.linalg.norm((Ug * Sg) @ Vg.T - (Uo * So) @ Vo.T) <= 2e-5 * So[0], i
+
+
+def test_batch_single_matrix_max_l(R):
+    """A batch of one (a grid of one workgroup) at l = 80, q = 2."""
+    ms, ns, ks = np.array([700]), np.array([450]), np.array([72])
+    print("batch single matrix", flush=True)
+    As = spectrum_batch(ms, ns, 77)
+    res, info, _ = run_batch(R, As, ms, ns, ks, 8, 2)
+    assert info[0] == 0, info
+    check_against_oracle(As, ks, res, 8, 2)
