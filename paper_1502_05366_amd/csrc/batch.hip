@@ -195,7 +195,7 @@ __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, 
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
           acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
-        if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        if (kk % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
@@ -277,7 +277,7 @@ __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, 
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
           acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
-        if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        if (kk % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
