@@ -4,6 +4,12 @@
  * interpolative, and CUR decompositions of matrices on multi-core and GPU
  * architectures" (arXiv:1502.05366).
  *
+ * Entry points: the decompositions (rsvd_svd, rsvd_id, rsvd_id_left, rsvd_cur,
+ * rsvd_decompose, rsvd_qb), the reverse-mode derivative of the randomized
+ * SVD (rsvd_svd_grad), the batched randomized SVD of many small FP32
+ * matrices (rsvd_batch_*), and single steps of the path (rsvd_sketch,
+ * rsvd_philox, rsvd_pass, rsvd_orth, rsvd_small_svd, rsvd_cpqr).
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  * - All matrix pointers are DEVICE pointers; the caller allocates every
@@ -31,7 +37,7 @@
  *   info[0] is a bit set of RSVD_INFO_*, info[1] the numerical rank found by
  *   the pivoted QR when RSVD_INFO_RANK is set.  Each call resets both words.
  * - l = min(k + p, m, n) is the sample size; this build supports l <= 256 and
- *   k <= l.  p >= 0, q >= 0, 1 <= k <= min(m, n).
+ *   k <= l (l <= 80 in a batch).  p >= 0, q >= 0, 1 <= k <= min(m, n).
  * - The Gaussian test matrix is drawn from Philox4x32-10 (key = seed) with
  *   Box-Muller normals: sketch entry (i, j) is normal number j*n + i of
  *   stream 0 (see rsvd_sketch).
