@@ -205,8 +205,9 @@ int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p
  *   stream; once per workspace, outside any stream capture.
  * rsvd_batch_svd: launches only kernels (a queue reset and the persistent
  *   kernel), so it may be captured into a graph and replayed; calls that
- *   share a workspace must not overlap.  info (2 int32, device) as for the
- *   other calls. */
+ *   share a workspace must not overlap.  `work` must be the workspace last
+ *   passed to rsvd_batch_prepare for this plan (-7 otherwise).  info (2
+ *   int32, device) as for the other calls. */
 int rsvd_batch_create(rsvd_handle_t h, int64_t count, const int64_t* m, const int64_t* n,
                       const int32_t* k, int p, int q, rsvd_batch_t* plan);
 int rsvd_batch_destroy(rsvd_batch_t plan);

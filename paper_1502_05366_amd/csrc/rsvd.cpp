@@ -49,6 +49,7 @@ struct rsvd_batch_s {
   int64_t desc_off, slot_off, slot_bytes;
   int64_t off_om, off_y, off_q, off_z, off_zq, off_t, off_qh, off_uh, off_vh;
   size_t work_bytes;
+  const void* prepared;                  // the workspace that holds the descriptors
 };
 
 namespace rsvd {
@@ -1077,6 +1078,7 @@ int rsvd_batch_create(rsvd_handle_t h, int64_t count, const int64_t* m, const in
   b->desc_off = 256;
   b->slot_off = r256(b->desc_off + count * (int64_t)sizeof(BatchDesc));
   b->work_bytes = (size_t)(b->slot_off + b->grid * b->slot_bytes);
+  b->prepared = nullptr;
   *plan = b;
   return RSVD_OK;
 }
@@ -1115,7 +1117,9 @@ int rsvd_batch_prepare(rsvd_batch_t b, void* work, size_t work_bytes, void* stre
   if (hipMemcpyAsync(w + b->desc_off, b->desc.data(), sizeof(rsvd::BatchDesc) * b->count,
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return RSVD_ERR_HIP;
-  return hipStreamSynchronize(st) == hipSuccess ? RSVD_OK : RSVD_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return RSVD_ERR_HIP;
+  b->prepared = work;
+  return RSVD_OK;
 }
 
 int rsvd_batch_svd(rsvd_batch_t b, uint64_t seed, const float* A, float* U, double* S, float* V,
@@ -1128,6 +1132,7 @@ int rsvd_batch_svd(rsvd_batch_t b, uint64_t seed, const float* A, float* U, doub
   if (!V) return -6;
   if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -7;
   if (work_bytes < b->work_bytes) return RSVD_ERR_WORKSPACE;
+  if (work != b->prepared) return -7;   // the descriptors are not in this workspace
   if (!info) return -9;
   if (hipSetDevice(b->h->device) != hipSuccess) return RSVD_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(stream);

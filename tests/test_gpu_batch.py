@@ -203,3 +203,21 @@ def test_batch_single_matrix_max_l(R):
     res, info, _ = run_batch(R, As, ms, ns, ks, 8, 2)
     assert info[0] == 0, info
     check_against_oracle(As, ks, res, 8, 2)
+
+
+def test_batch_rejects_unprepared_workspace(R):
+    """A workspace that did not receive the descriptors is refused before
+    any launch."""
+    import ctypes
+    from paper_1502_05366_amd import _lib
+    plan = R.BatchPlan([100, 80], [60, 90], [5, 6], 8, 1)
+    buf = plan.pack([torch.zeros(100, 60), torch.zeros(80, 90)])
+    U, S, V, info = plan.outputs()
+    other = torch.empty_like(plan.work)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = _lib.load().rsvd_batch_svd(plan._plan, 1, P(buf), P(U), P(S), P(V), P(other),
+                                    other.numel(), P(info), stream)
+    assert rc == -7
+    plan.run(buf, 1)                                      # the prepared one works
+    torch.cuda.synchronize()
