@@ -20,7 +20,8 @@
 //    rows split over the waves), Cholesky (one barrier per step) and the
 //    inverse of R (four lanes per column) in LDS, Q = Y R^{-1} on FP64 MFMA;
 //    a pivot below 1e-13 G_jj marks a dependent column (unit row of R, info
-//    bit 1);
+//    bit 1); the second pass is skipped when the first already left
+//    ||Q^T Q - I||_F <= 2^-30, far below the FP32 rounding of the bases;
 //  * the Jacobi SVD of the l x l factor in LDS (the rotations of the
 //    single-matrix small SVD, one column pair per 16 lanes);
 //  * U and V on FP64 MFMA, written in FP32.
@@ -510,6 +511,45 @@ __device__ __noinline__ void b_apply(const TI* __restrict__ In, int64_t rows, in
 
 // Q (rows x lp) = orth(In) by CholeskyQR2 in FP64; T (rows x lp FP64) holds
 // the first pass.
+// ||G - I||_F^2 of the leading l x l block of the Gram in a (upper blocks:
+// diagonal terms once, off-diagonal ones twice), the same value on every
+// thread
+__device__ double b_gram_offset2(int l) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* G = g_lds.u.sm.a;
+  double t = 0.0;
+  for (int e = tid; e < l * l; e += BNT) {
+    const int i = e / l, j = e - (e / l) * l;
+    if (i == j) {
+      const double d = G[i * SL + i] - 1.0;
+      t = fma(d, d, t);
+    } else if (i < j) {
+      const double x = G[i * SL + j];
+      t = fma(2.0 * x, x, t);
+    }
+  }
+  t = wave_allsum(t);
+  if (lane == 0) g_lds.sig[wave] = t;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < BNT / 64; ++w) r += g_lds.sig[w];
+  __syncthreads();
+  return r;
+}
+
+// Q = T rounded to TO (rows x lp)
+template <typename TO>
+__device__ void b_copy(const double* T, int64_t rows, int lp, TO* Q) {
+  for (int64_t e = threadIdx.x; e < rows * lp; e += BNT) Q[e] = from_d<TO>(T[e]);
+  __syncthreads();
+}
+
+// Largest ||Q1^T Q1 - I||_F after the first pass for which the second pass
+// is skipped: 2^-30, far below the unit roundoff of the FP32 bases (2^-24),
+// so the orthogonality of the stored basis is set by its own rounding.
+constexpr double ORTH_SKIP2 = 0x1.0p-60;   // (2^-30)^2
+
 template <int NB, typename TI, typename TO>
 __device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
   constexpr int lp = 16 * NB;
@@ -518,6 +558,10 @@ __device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
   b_rinv(l, lp);
   b_apply<NB>(In, rows, lp, T, (int64_t)lp);
   b_gram<NB>(T, rows);
+  if (b_gram_offset2(l) <= ORTH_SKIP2) {
+    b_copy(T, rows, lp, Q);
+    return;
+  }
   b_chol(l, lp);
   b_rinv(l, lp);
   b_apply<NB>(T, rows, lp, Q, (int64_t)lp);
