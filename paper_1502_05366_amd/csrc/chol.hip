@@ -34,6 +34,9 @@ namespace {
 
 constexpr int NI_NT = 256;
 constexpr double NI_TAU2 = 2.5e-17;   // bound on ||G - I||_F^2 (about a quarter of 2^-52)
+// ||G - I||_F^2 of the second Gram below which an FP32 basis is the first
+// pass rounded to FP32: (2^-30)^2, far below the FP32 unit roundoff 2^-24
+constexpr double TRSM_SKIP2 = 0x1.0p-60;
 constexpr int CH_NT = 512;
 constexpr int CH_NW = CH_NT / 64;  // waves
 constexpr int MAXNB = 16;          // lp <= 256
@@ -324,7 +327,8 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
                                                    int64_t M, int l, int lp,
                                                    const double* __restrict__ R, int64_t ldr,
                                                    const double* __restrict__ Rdinv,
-                                                   TQ* __restrict__ Q, int64_t ldq) {
+                                                   TQ* __restrict__ Q, int64_t ldq,
+                                                   const double* __restrict__ skip_part) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
@@ -334,6 +338,22 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
   const bool rok = r < M;
   const TY* yr = Y + (rok ? r : 0) * ldy;
   TQ* qr = Q + (rok ? r : 0) * ldq;
+  if (skip_part) {
+    // ||Y^T Y - I||_F^2 from its parts (the same order on every thread): when
+    // Y is orthonormal to within TRSM_SKIP2, Q = Y rounded to TQ
+    double e2 = 0.0;
+    for (int c = 0; c < nb; ++c) e2 += skip_part[c];
+    if (e2 <= TRSM_SKIP2) {
+      for (int c = 0; c < nb; ++c) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = c * 16 + 4 * v + lk;
+          if (rok && col < l) qr[col] = (TQ)yr[col];
+        }
+      }
+      return;
+    }
+  }
   d4 qt[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
@@ -664,35 +684,43 @@ hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, 
 template <int NB>
 hipError_t launch_trsm_nb(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                           int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
-                          int64_t ldq, hipStream_t s) {
+                          int64_t ldq, const double* skip_part, hipStream_t s) {
   const dim3 grid((unsigned)cdiv(M, 64));
   if (!y_f32 && !q_f32)
     hipLaunchKernelGGL((trsm_kernel<double, double, NB>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, skip_part);
   else if (y_f32 && q_f32)
     hipLaunchKernelGGL((trsm_kernel<float, float, NB>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, skip_part);
   else if (y_f32 && !q_f32)
     hipLaunchKernelGGL((trsm_kernel<float, double, NB>), grid, dim3(256), 0, s,
-                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq);
+                       (const float*)Y, ldy, M, l, lp, R, ldr, Rdinv, (double*)Q, ldq, skip_part);
   else
     hipLaunchKernelGGL((trsm_kernel<double, float, NB>), grid, dim3(256), 0, s,
-                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq);
+                       (const double*)Y, ldy, M, l, lp, R, ldr, Rdinv, (float*)Q, ldq, skip_part);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
-                       int64_t ldq, hipStream_t s) {
+                       int64_t ldq, hipStream_t s, const double* skip_part) {
   if (M <= 0) return hipSuccess;
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
   const int nb = lp / 16;
-  if (nb <= 2) return launch_trsm_nb<2>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
-  if (nb <= 4) return launch_trsm_nb<4>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
-  if (nb <= 8) return launch_trsm_nb<8>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+  if (nb <= 2) 
+    return launch_trsm_nb<2>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq,
+                              skip_part, s);
+  if (nb <= 4) 
+    return launch_trsm_nb<4>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq,
+                              skip_part, s);
+  if (nb <= 8) 
+    return launch_trsm_nb<8>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq,
+                              skip_part, s);
   if (nb <= 12)
-    return launch_trsm_nb<12>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
-  return launch_trsm_nb<16>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, s);
+    return launch_trsm_nb<12>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq,
+                              skip_part, s);
+  return launch_trsm_nb<16>(y_f32, q_f32, Y, ldy, M, l, lp, R, ldr, Rdinv, Q, ldq, skip_part,
+                            s);
 }
 
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,

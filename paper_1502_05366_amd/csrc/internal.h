@@ -76,9 +76,11 @@ size_t gram_part_bytes(int lp, int ncu_cap);
 hipError_t launch_gram(bool y_f32, const void* Y, int64_t ldy, int64_t rows, int l, int lp,
                        double* Gm, int64_t ldg, double* part, int ncu, hipStream_t s);
 // Q = Y R^{-1} (M x l); Y and Q may be FP32 or FP64; arithmetic in FP64.
+// With skip_part (the lp/16 parts of ||Y^T Y - I||_F^2 left by the
+// near-identity Cholesky), Q = Y when their sum is at most 2^-60.
 hipError_t launch_trsm(bool y_f32, bool q_f32, const void* Y, int64_t ldy, int64_t M, int l,
                        int lp, const double* R, int64_t ldr, const double* Rdinv, void* Q,
-                       int64_t ldq, hipStream_t s);
+                       int64_t ldq, hipStream_t s, const double* skip_part = nullptr);
 // overwrite the columns j with dep[j] != 0 of Q (M rows) by N(0, 1/M) values
 hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, const int32_t* dep,
                           uint64_t seed, uint32_t call, hipStream_t s);

@@ -243,7 +243,10 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
   RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st,
                        ob.nip));
-  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st));
+  // an FP32 basis is the first pass rounded to FP32 when that pass is already
+  // orthonormal far below the FP32 rounding (the near-identity parts decide)
+  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st,
+                       q_f32 ? ob.nip : nullptr));
   if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, ob.dep, Rout, ldr, lp, c.st));
   return hipSuccess;
 }
