@@ -194,3 +194,21 @@ def test_cpqr_rank_deficient_reports_rank(R):
     assert info[1] == 5
     f = OD.cpqr(B, 10)
     assert f['frank'] == 5
+
+
+@pytest.mark.parametrize("decay", [0.0, 3.0, 5.0])
+def test_orth_fp32_conditioning(R, decay):
+    """FP32 bases across conditioning: well-conditioned Y takes the rounding
+    copy after the first pass, ill-conditioned Y (kappa ~1e5) the full second
+    pass; both give an FP32-orthonormal Q spanning range(Y)."""
+    g = np.random.default_rng(31 + int(decay))
+    rows, l = 6000, 48
+    Y = (g.standard_normal((rows, l)) @ np.diag(np.logspace(0, -decay, l))
+         @ np.linalg.qr(g.standard_normal((l, l)))[0]).astype(np.float32)
+    Q, Rm, info = R.orth(dev(Y, torch.float32))
+    Q = Q.cpu().numpy().astype(np.float64)
+    assert int(info.cpu()[0]) == 0
+    assert orth_err(Q) < 1e-5
+    Y64 = Y.astype(np.float64)
+    # range(Y) inside range(Q), relative to the size of Y
+    assert np.linalg.norm(Y64 - Q @ (Q.T @ Y64)) <= 1e-5 * np.linalg.norm(Y64)
