@@ -84,6 +84,19 @@ int rsvd_create(rsvd_handle_t* handle, int device);
 int rsvd_destroy(rsvd_handle_t handle);
 const char* rsvd_status_string(int code);
 
+/* Options of a handle, for the calls made through it afterwards:
+ *   RSVD_OPT_JACOBI_MAX_SWEEPS (1..1000, default 40): sweep cap of the Jacobi
+ *     SVD of the small factor; stopping at the cap sets RSVD_INFO_JACOBI_CAP.
+ *   RSVD_OPT_TEST_WAIT_GIVEUP (0 or 1, default 0): failure-handling test
+ *     mode.  The kernels whose workgroups wait for each other (the pivoted QR
+ *     and the block Jacobi, l > 64) then wait for a value that no workgroup
+ *     posts, with a small spin cap, so every wait gives up: the kernels run
+ *     to their end, the call reports RSVD_INFO_BARRIER and its outputs are
+ *     invalid (J then lists the columns in order).
+ * Returns -2 for an unknown option, -3 for a value out of range. */
+enum { RSVD_OPT_JACOBI_MAX_SWEEPS = 1, RSVD_OPT_TEST_WAIT_GIVEUP = 2 };
+int rsvd_set_option(rsvd_handle_t h, int option, int value);
+
 /* Bytes of device workspace needed by rsvd_decompose (and rsvd_svd, rsvd_id,
  * rsvd_cur) for the outputs selected by `ops` (a bit set of RSVD_OP_*).
  * Pure host function of its arguments; 0 for invalid arguments. */

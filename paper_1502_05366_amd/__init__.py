@@ -20,5 +20,6 @@ and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
 from .api import (  # noqa: F401
     RsvdError, handle, svd, id, id_left, qb, cur, svd_grad, svd_diff, BatchPlan, decompose,
     workspace_bytes, sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK,
-    INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32,
+    INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32, set_option,
+    OPT_JACOBI_MAX_SWEEPS, OPT_TEST_WAIT_GIVEUP,
 )

@@ -23,6 +23,7 @@ SIGNATURES = {
     "rsvd_create": (c_int, [ctypes.POINTER(c_ptr), c_int]),
     "rsvd_destroy": (c_int, [c_ptr]),
     "rsvd_status_string": (ctypes.c_char_p, [c_int]),
+    "rsvd_set_option": (c_int, [c_ptr, c_int, c_int]),
     "rsvd_workspace_bytes": (c_size, [c_int, c_int, c_i64, c_i64, c_int, c_int, c_int]),
     "rsvd_svd": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr, c_i64,
                          c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_size, c_ptr, c_ptr]),

@@ -7,6 +7,7 @@ return code.  The numerical status words are returned as a 2-element int32
 device tensor (read it with .cpu() when needed).
 """
 
+import atexit
 import ctypes
 
 import torch
@@ -24,6 +25,7 @@ INFO_NONFINITE = 8
 INFO_BARRIER = 16
 
 OP_SVD, OP_ID, OP_CUR = 1, 2, 4
+OPT_JACOBI_MAX_SWEEPS, OPT_TEST_WAIT_GIVEUP = 1, 2
 
 
 class RsvdError(RuntimeError):
@@ -52,6 +54,31 @@ def handle(device=None):
         h = p
         _handles[idx] = h
     return h
+
+
+def _release_handles():
+    """At interpreter exit: wait for each device's work, then destroy its
+    handle (its second stream and events) before the HIP runtime tears down."""
+    if not _handles:
+        return
+    lib = _lib.load()
+    for idx, h in list(_handles.items()):
+        try:
+            with torch.cuda.device(idx):
+                torch.cuda.synchronize()
+        except Exception:  # noqa: BLE001  (exit path: release what can be released)
+            pass
+        lib.rsvd_destroy(h)
+        del _handles[idx]
+
+
+atexit.register(_release_handles)
+
+
+def set_option(option, value, device=None):
+    """rsvd_set_option on the device's handle (OPT_JACOBI_MAX_SWEEPS,
+    OPT_TEST_WAIT_GIVEUP)."""
+    _check(_lib.load().rsvd_set_option(handle(device), int(option), int(value)), "rsvd_set_option")
 
 
 def _check(rc, what):

@@ -3,7 +3,8 @@
 // (Sec. 3.5, last part) and, applied to C^T, the rows of the CUR (Sec. 2.5,
 // Sec. 3.6).  Then T = S11^{-1} S12 (Sec. 2.4) by back substitution.
 //
-// One cooperative launch of G workgroups; workgroup g keeps columns
+// One launch of G <= (compute units) workgroups that wait for each other with
+// bounded spins (below); workgroup g keeps columns
 // [g*cs, (g+1)*cs) of B in LDS for the whole factorization.  Step s:
 //   1. each workgroup finds its unchosen column with the largest residual
 //      norm ||B(s:, j)|| (FP64, lowest column index on ties) and publishes
@@ -33,6 +34,8 @@ struct CpqrArgs {
   int64_t slot_len;
   uint32_t* tags;                  // [2][G] (FLAG_STRIDE apart) step + 1 of the last post
   uint32_t* abort_flag;            // set when a wait exceeds its spin cap
+  uint32_t wait_bias;              // 0; 1 only in the forced give-up test mode
+  uint32_t spin_cap;
   int64_t* J;                      // [c]
   double* S11t;                    // column t = top k rows of pivot column t (ld = lds)
   double* S12t;                    // column rho = top k rows of residual column rho
@@ -47,8 +50,11 @@ struct CpqrArgs {
 // agent-scope loads.  No counter is shared, so no atomic is contended.  A wait
 // longer than its spin cap raises the abort flag and INFO_BARRIER; all later
 // waits then return at once, so the kernel always runs to its end (its
-// results are then flagged invalid).
+// results are then flagged invalid).  In the forced give-up test mode the
+// host sets wait_bias = 1, so every wait is for a value that no workgroup
+// posts, and a small spin cap.
 constexpr uint32_t SPIN_CAP = 1u << 22;
+constexpr uint32_t SPIN_CAP_TEST = 1u << 10;
 
 // Called by every thread of the workgroup after the slot data has been stored
 // with agent-scope stores: each wave waits for its stores, then thread 0
@@ -61,12 +67,12 @@ __device__ __forceinline__ void post_tag(uint32_t* tag, uint32_t value) {
 
 // Relaxed polling; the slot data is then read with agent-scope loads.
 __device__ __forceinline__ void wait_tag(const uint32_t* tag, uint32_t value, uint32_t* abort_flag,
-                                         int32_t* info) {
+                                         uint32_t spin_cap, int32_t* info) {
   uint32_t spins = 0;
   while (ld_agent_u32(tag) != value) {
     if ((++spins & 63) == 0) {
       if (ld_agent_u32(abort_flag) != 0) break;
-      if (spins > SPIN_CAP) {
+      if (spins > spin_cap) {
         st_agent_u32(abort_flag, 1u);
         info_or(info, INFO_BARRIER);
         break;
@@ -80,6 +86,13 @@ __device__ __forceinline__ void wait_tag(const uint32_t* tag, uint32_t value, ui
 __device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t i2) {
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
+
+// Selection key of a squared residual norm: NaN (from non-finite entries of
+// B) maps to -0.5, below every finite norm and above the empty-candidate
+// value -1, so such columns are still chosen, last and lowest index first:
+// the k pivots are always k distinct columns and the index bookkeeping
+// below stays a permutation.  The step then reports INFO_NONFINITE.
+__device__ __forceinline__ double sel_key(double s2) { return s2 == s2 ? s2 : -0.5; }
 
 constexpr int CQ_NW = CQ_NT / 64;
 constexpr int CQ_RPL = 16;         // rows per lane (16 lanes per column): r <= 256
@@ -143,8 +156,11 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     }
     s2 = row16_sum(s2);
     if (act) {
-      if (rl == 0) { nrm[jj] = s2; chosen_at[jj] = -1; fpart += s2; }
-      if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+      if (rl == 0) {
+        nrm[jj] = s2; chosen_at[jj] = -1; fpart += s2;
+        if (!(s2 <= 1.7976931348623157e308)) info_or(a.info, INFO_NONFINITE);   // NaN or Inf in B
+      }
+      if (better(sel_key(s2), j0 + jj, bv, bi)) { bv = sel_key(s2); bi = j0 + jj; }
     }
   }
   fpart = wave_allsum(fpart);
@@ -188,7 +204,8 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     int gg = 0;
     double fro_part = 0.0;
     for (int w = tid; w < a.G; w += CQ_NT) {
-      wait_tag(a.tags + (par * a.G + w) * FLAG_STRIDE, (uint32_t)s + 1u, a.abort_flag, a.info);
+      wait_tag(a.tags + (par * a.G + w) * FLAG_STRIDE, (uint32_t)s + 1u + a.wait_bias,
+               a.abort_flag, a.spin_cap, a.info);
       const double* sl = a.slots + ((int64_t)par * a.G + w) * a.slot_len;
       const double vv = ld_agent(sl + 0);
       const double iv = ld_agent(sl + 1);
@@ -218,9 +235,15 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
       for (int w = 0; w < CQ_NW; ++w) fro2 += redf[w];
       tol = (double)(r > a.c ? r : a.c) * DEPS * sqrt(fro2);
     }
-    if (gi < 0 || gi >= a.c) { gi = 0; gg = 0; }     // only after an aborted barrier
-    // the pivot's posted norm^2 is ||x||^2 of its rows s..r-1
-    const double pnorm = sqrt(gv > 0.0 ? gv : 0.0);
+    // without a valid candidate (possible only after an aborted wait, whose
+    // results are flagged invalid) column 0 stands in, so that every index
+    // stays in range
+    if (gi < 0 || gi >= a.c) { gi = 0; gg = 0; }
+    // the pivot's posted norm^2 is ||x||^2 of its rows s..r-1; a non-finite
+    // pivot (NaN key -0.5, or Inf) is taken with a zero reflector
+    const bool pfin = gv >= 0.0 && gv <= 1.7976931348623157e308;
+    if (!pfin && g == 0 && tid == 0) info_or(a.info, INFO_NONFINITE);
+    const double pnorm = pfin ? sqrt(gv) : 0.0;
     if (frank == a.k && pnorm <= tol) frank = s;
     const double* psl = a.slots + ((int64_t)par * a.G + gg) * a.slot_len;
     for (int i = s + tid; i < r; i += CQ_NT) v[i] = ld_agent(psl + 3 + i);
@@ -292,7 +315,7 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
       const double s2 = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
       if (act && !is_piv) {
         if (rl == 0) nrm[jj] = s2;
-        if (better(s2, j0 + jj, bv, bi)) { bv = s2; bi = j0 + jj; }
+        if (better(sel_key(s2), j0 + jj, bv, bi)) { bv = sel_key(s2); bi = j0 + jj; }
       }
     }
   }
@@ -300,6 +323,13 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   if (g == 0 && tid == 0 && frank < a.k) {
     info_or(a.info, INFO_RANK);
     a.info[1] = frank;
+  }
+  // After an aborted wait the workgroups may disagree on the pivots, so the
+  // positions below would not be a permutation: then J lists the columns in
+  // order and the factors are not written (the call reports INFO_BARRIER).
+  if (ld_agent_u32(a.abort_flag) != 0) {
+    for (int64_t jj = tid; jj < ncols; jj += CQ_NT) a.J[j0 + jj] = j0 + jj;
+    return;
   }
   // outputs: top k rows of every owned column
   for (int64_t jj = wave; jj < ncols; jj += CQ_NW) {
@@ -451,7 +481,8 @@ size_t cpqr_work_bytes(const CpqrPlan& p) {
 
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
                        const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
-                       int64_t lds, double* pivn, int32_t* info, bool coop, hipStream_t s) {
+                       int64_t lds, double* pivn, int32_t* info, bool giveup_test,
+                       hipStream_t s) {
   if (!p.ok) return hipErrorInvalidValue;
   CpqrArgs a;
   a.Bt = Bt; a.ldb = ldb; a.r = r; a.c = c; a.k = k;
@@ -462,17 +493,15 @@ hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c
   a.tags = reinterpret_cast<uint32_t*>(w + 2 * p.G * p.slot_len);
   a.abort_flag = a.tags + 2 * p.G * FLAG_STRIDE;
   a.J = J; a.S11t = S11t; a.S12t = S12t; a.lds = lds; a.pivn = pivn; a.info = info;
+  a.wait_bias = giveup_test ? 1u : 0u;
+  a.spin_cap = giveup_test ? SPIN_CAP_TEST : SPIN_CAP;
   hipError_t e = launch_fill_u32(a.tags, 0u, (2 * p.G + 1) * FLAG_STRIDE, s);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
   const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
   if (e != hipSuccess) return e;
-  if (coop) {
-    e = hipLaunchCooperativeKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
-  } else {
-    e = hipLaunchKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
-  }
+  e = hipLaunchKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

@@ -93,13 +93,14 @@ hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s);
 // ---------------------------------------------------------------- jacobi --
 // work: jacobi_work_bytes(l) bytes; sweeps_out (device int, may be null)
 // receives the number of sweeps of the block iteration.  The block iteration
-// (l > 64) waits across at most 8 workgroups: with coop it is a cooperative
-// launch; without, the caller keeps that many CUs free of other waiting
-// kernels.
+// (l > 64) waits across at most 8 workgroups of one ordinary launch (bounded
+// spins, INFO_BARRIER on give-up): the caller keeps that many CUs free of
+// other waiting kernels.  giveup_test: every cross-workgroup wait waits for a
+// value no workgroup posts, with a small spin cap (failure-handling tests).
 size_t jacobi_work_bytes(int l);
 hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
                          double* Uh, int64_t lduh, double* Vh, int64_t ldvh, int max_sweeps,
-                         int32_t* info, int32_t* sweeps_out, bool coop, hipStream_t s);
+                         int32_t* info, int32_t* sweeps_out, bool giveup_test, hipStream_t s);
 
 // ------------------------------------------------------------------ cpqr --
 struct CpqrPlan {
@@ -112,12 +113,14 @@ struct CpqrPlan {
 };
 CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu);
 size_t cpqr_work_bytes(const CpqrPlan& p);
-// The p.G workgroups wait for each other at every step: with coop the launch
-// is cooperative; without, p.G must fit in CUs not held by other waiting
-// kernels (one workgroup per CU).
+// The p.G workgroups of one ordinary launch wait for each other at every step
+// (bounded spins, INFO_BARRIER on give-up): p.G must fit in CUs not held by
+// other waiting kernels (one workgroup per CU).  giveup_test as for
+// launch_jacobi.
 hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c, int k,
                        const CpqrPlan& p, void* work, int64_t* J, double* S11t, double* S12t,
-                       int64_t lds, double* pivn, int32_t* info, bool coop, hipStream_t s);
+                       int64_t lds, double* pivn, int32_t* info, bool giveup_test,
+                       hipStream_t s);
 // X = S^{-1} B by back substitution (k <= 256); a zero pivot S_ii gives x_i = 0
 hipError_t launch_backsub(const double* S, int64_t s_r, int64_t s_c, const double* Bm,
                           int64_t b_r, int64_t b_c, int k, int64_t nrhs, double* X, int64_t x_r,

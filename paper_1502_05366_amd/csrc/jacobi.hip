@@ -16,6 +16,8 @@
 // Jacobi over several workgroups (below).
 // Output: the k largest sigma in descending order (stable for ties) and the
 // matching columns of Uh and Vh.
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 #include "jacobi_dev.h"
@@ -78,8 +80,8 @@ __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restric
 // ---- block one-sided Jacobi over several workgroups (l > LDS_MAX_L) -------
 //
 // The l columns are cut into blocks of BS; blocks are paired by the same
-// round-robin schedule as columns, and each of the NB/2 workgroups of a
-// cooperative launch takes one block pair per round: it loads the 2*BS
+// round-robin schedule as columns, and each of the NB/2 workgroups of one
+// launch takes one block pair per round: it loads the 2*BS
 // columns of W and V into LDS, rotates every cross pair (x from the first
 // block, y from the second; in round 0 also the pairs inside each block),
 // and writes the columns back.  Between rounds the workgroups exchange
@@ -95,6 +97,8 @@ struct JacArgs {
   uint32_t* tags;       // [G] rounds completed by each workgroup (FLAG_STRIDE apart)
   uint32_t* rot;        // [2][G] rotation flag of the current / previous sweep
   uint32_t* abort_flag;
+  uint32_t wait_bias;   // 0; 1 in the forced give-up test mode (waits for a value never posted)
+  uint32_t spin_cap;
   int32_t* info;
   int32_t* sweeps_out;
 };
@@ -103,10 +107,10 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   const int tid = threadIdx.x;
   if (tid < a.G) {
     uint32_t spins = 0;
-    while (ld_agent_u32(a.tags + tid * FLAG_STRIDE) < target) {
+    while (ld_agent_u32(a.tags + tid * FLAG_STRIDE) < target + a.wait_bias) {
       if ((++spins & 63) == 0) {
         if (ld_agent_u32(a.abort_flag)) break;
-        if (spins > (1u << 22)) {
+        if (spins > a.spin_cap) {
           st_agent_u32(a.abort_flag, 1u);
           info_or(a.info, INFO_BARRIER);
           break;
@@ -127,12 +131,19 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
 // 2BS x 2BS orthogonal J (two rows per lane), and the round ends with
 // V(:, pair blocks) <- V(:, pair blocks) J on the matrix cores.
 constexpr int JB_NT = 256;   // 4 waves x 4 pairs = BS pairs per step
-constexpr int JLD = 272;     // LDS column stride of W: 256 rows (rows >= l hold zeros) + 16
-                             // doubles, so columns q and q+1 start on opposite halves
-                             // of the LDS banks
-constexpr int JRPL = 256 / 16;
 constexpr int JJ = 2 * BS;   // order of J
-constexpr int JJS = 48;      // LDS column stride of J (alternating bank halves)
+// Rows per lane JRPL: 16 for l <= 256, 36 for l <= 576 (a column of W is
+// 16 JRPL rows, rows >= l zero).  LDS column stride of W: the rows + 16
+// doubles, so columns q and q+1 start on opposite halves of the LDS banks;
+// J's column stride alternates bank halves too.  At JRPL = 36 the two W blocks
+// and J fill 158 KB of the 160 KB of LDS.
+constexpr int JACOBI_MAX_L = 576;
+template <int JRPL> struct JacDims {
+  static constexpr int ROWS = 16 * JRPL;
+  static constexpr int JLD = ROWS + 16;
+  static constexpr int JJS = JRPL > 16 ? 40 : 48;
+  static constexpr size_t LDS = (2 * (size_t)BS * JLD + (size_t)JJ * JJS) * sizeof(double);
+};
 
 __device__ __forceinline__ double row16_sum(double x) {
   x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
@@ -142,6 +153,7 @@ __device__ __forceinline__ double row16_sum(double x) {
   return x;
 }
 
+template <int JRPL>
 __device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xj)[2],
                                              double (&yw)[JRPL], double (&yj)[2], double tol) {
   double al[2] = {0.0, 0.0}, be[2] = {0.0, 0.0}, ga[2] = {0.0, 0.0};   // two chains each
@@ -172,24 +184,32 @@ __device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xj)[2]
   return rot;
 }
 
+template <int JRPL>
 __device__ __forceinline__ void lds_col_load(const double* base, int rl, double (&v)[JRPL]) {
 #pragma unroll
   for (int e = 0; e < JRPL; ++e) v[e] = base[rl + 16 * e];
 }
+template <int JRPL>
 __device__ __forceinline__ void lds_col_store(double* base, int rl, const double (&v)[JRPL]) {
 #pragma unroll
   for (int e = 0; e < JRPL; ++e) base[rl + 16 * e] = v[e];
 }
+template <int JJS>
 __device__ __forceinline__ void lds_j_load(const double* Jl, int col, int rl, double (&v)[2]) {
   v[0] = Jl[col * JJS + rl];
   v[1] = Jl[col * JJS + rl + 16];
 }
+template <int JJS>
 __device__ __forceinline__ void lds_j_store(double* Jl, int col, int rl, const double (&v)[2]) {
   Jl[col * JJS + rl] = v[0];
   Jl[col * JJS + rl + 16] = v[1];
 }
 
+template <int JRPL>
 __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
+  constexpr int ROWS = JacDims<JRPL>::ROWS;
+  constexpr int JLD = JacDims<JRPL>::JLD;
+  constexpr int JJS = JacDims<JRPL>::JJS;
   extern __shared__ double smem[];
   __shared__ int rotated;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -210,19 +230,19 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
       // load the two W blocks (columns >= l and rows >= l read as zero), each
       // thread issuing all its loads before its LDS writes; J = I
       {
-        constexpr int PER = 2 * BS * 256 / JB_NT;
-        double vv[PER];
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JB_NT;
-          const int c = idx / 256, i = idx % 256;
+        // wave w takes columns w, w+4, .. of the 2 BS; lanes run down the
+        // rows (one column's loads per batch)
+        for (int cc = 0; cc < 2 * BS / 4; ++cc) {
+          const int c = wave + 4 * cc;
           const int gcol = gcol_of(c);
-          vv[e] = (i < l && gcol < l) ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
-        }
+          double vv[ROWS / 64];
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JB_NT;
-          Wl[(idx / 256) * JLD + idx % 256] = vv[e];
+          for (int t = 0; t < ROWS / 64; ++t) {
+            const int i = lane + 64 * t;
+            vv[t] = (i < l && gcol < l) ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < ROWS / 64; ++t) Wl[c * JLD + lane + 64 * t] = vv[t];
         }
 #pragma unroll
         for (int e = 0; e < JJ * JJ / JB_NT; ++e) {
@@ -240,11 +260,11 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
           int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
           if (p > q) { const int x = p; p = q; q = x; }
           p += half * BS; q += half * BS;
-          lds_col_load(Wl + p * JLD, rl, xw); lds_j_load(Jl, p, rl, xj);
-          lds_col_load(Wl + q * JLD, rl, yw); lds_j_load(Jl, q, rl, yj);
-          rot |= rotate_row16(xw, xj, yw, yj, a.tol);
-          lds_col_store(Wl + p * JLD, rl, xw); lds_j_store(Jl, p, rl, xj);
-          lds_col_store(Wl + q * JLD, rl, yw); lds_j_store(Jl, q, rl, yj);
+          lds_col_load<JRPL>(Wl + p * JLD, rl, xw); lds_j_load<JJS>(Jl, p, rl, xj);
+          lds_col_load<JRPL>(Wl + q * JLD, rl, yw); lds_j_load<JJS>(Jl, q, rl, yj);
+          rot |= rotate_row16<JRPL>(xw, xj, yw, yj, a.tol);
+          lds_col_store<JRPL>(Wl + p * JLD, rl, xw); lds_j_store<JJS>(Jl, p, rl, xj);
+          lds_col_store<JRPL>(Wl + q * JLD, rl, yw); lds_j_store<JJS>(Jl, q, rl, yj);
           __syncthreads();
         }
       }
@@ -252,60 +272,68 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
       // x_p in registers, the y columns move between slots through LDS
       {
         const int p = ps;
-        lds_col_load(Wl + p * JLD, rl, xw); lds_j_load(Jl, p, rl, xj);
+        lds_col_load<JRPL>(Wl + p * JLD, rl, xw); lds_j_load<JJS>(Jl, p, rl, xj);
         for (int t = 0; t < BS; ++t) {
           const int q = BS + (p + t) % BS;
-          lds_col_load(Wl + q * JLD, rl, yw); lds_j_load(Jl, q, rl, yj);
-          rot |= rotate_row16(xw, xj, yw, yj, a.tol);
-          lds_col_store(Wl + q * JLD, rl, yw); lds_j_store(Jl, q, rl, yj);
+          lds_col_load<JRPL>(Wl + q * JLD, rl, yw); lds_j_load<JJS>(Jl, q, rl, yj);
+          rot |= rotate_row16<JRPL>(xw, xj, yw, yj, a.tol);
+          lds_col_store<JRPL>(Wl + q * JLD, rl, yw); lds_j_store<JJS>(Jl, q, rl, yj);
           __syncthreads();
         }
-        lds_col_store(Wl + p * JLD, rl, xw); lds_j_store(Jl, p, rl, xj);
+        lds_col_store<JRPL>(Wl + p * JLD, rl, xw); lds_j_store<JJS>(Jl, p, rl, xj);
       }
       if (rot) rotated = 1;
       __syncthreads();
       // W back to memory
       {
-        constexpr int PER = 2 * BS * 256 / JB_NT;
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-          const int idx = tid + e * JB_NT;
-          const int c = idx / 256, i = idx % 256;
+        for (int cc = 0; cc < 2 * BS / 4; ++cc) {
+          const int c = wave + 4 * cc;
           const int gcol = gcol_of(c);
-          if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * JLD + i]);
-        }
-      }
-      // V(:, pair) <- V(:, pair) J: wave v takes row tiles v, v+4, v+8, v+12
-      // (16 rows each) and both 16-column halves; it reads all of its rows
-      // before it writes any, and no other wave touches them
-      {
-        const int li = lane & 15, lk = lane >> 4;
-        double av[4][JJ / 4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = (wave + 4 * q) * 16 + li;
-#pragma unroll
-          for (int kk = 0; kk < JJ / 4; ++kk) {
-            const int gcol = gcol_of(kk * 4 + lk);
-            av[q][kk] = (row < l && gcol < l) ? ld_agent(a.V + (int64_t)gcol * a.ld + row) : 0.0;
+          for (int t = 0; t < ROWS / 64; ++t) {
+            const int i = lane + 64 * t;
+            if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * JLD + i]);
           }
         }
+      }
+      // V(:, pair) <- V(:, pair) J: wave v takes row tiles v, v+4, v+8, ..
+      // (16 rows each, in groups of RG tiles) and both 16-column halves; it
+      // reads all rows of a group before it writes any, and no other wave
+      // touches them
+      {
+        constexpr int RT = JRPL / 4;           // row tiles per wave
+        constexpr int RG = RT % 3 == 0 ? 3 : RT;
+        const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-        for (int ct = 0; ct < JJ / 16; ++ct) {
-          double bv[JJ / 4];
+        for (int q0 = 0; q0 < RT; q0 += RG) {
+          double av[RG][JJ / 4];
 #pragma unroll
-          for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJS + kk * 4 + lk];
+          for (int q = 0; q < RG; ++q) {
+            const int row = (wave + 4 * (q0 + q)) * 16 + li;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < JJ / 4; ++kk) {
+              const int gcol = gcol_of(kk * 4 + lk);
+              av[q][kk] =
+                  (row < l && gcol < l) ? ld_agent(a.V + (int64_t)gcol * a.ld + row) : 0.0;
+            }
+          }
 #pragma unroll
-            for (int kk = 0; kk < JJ / 4; ++kk)
-              acc = Mfma<double>::mma(av[q][kk], bv[kk], acc);
-            const int gcol = gcol_of(ct * 16 + li);
+          for (int ct = 0; ct < JJ / 16; ++ct) {
+            double bv[JJ / 4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = (wave + 4 * q) * 16 + drow(lk, v);
-              if (row < l && gcol < l) st_agent(a.V + (int64_t)gcol * a.ld + row, acc[v]);
+            for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJS + kk * 4 + lk];
+#pragma unroll
+            for (int q = 0; q < RG; ++q) {
+              d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int kk = 0; kk < JJ / 4; ++kk)
+                acc = Mfma<double>::mma(av[q][kk], bv[kk], acc);
+              const int gcol = gcol_of(ct * 16 + li);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = (wave + 4 * (q0 + q)) * 16 + drow(lk, v);
+                if (row < l && gcol < l) st_agent(a.V + (int64_t)gcol * a.ld + row, acc[v]);
+              }
             }
           }
         }
@@ -355,21 +383,36 @@ __global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __rest
                                                             double* __restrict__ Uh, int64_t lduh,
                                                             double* __restrict__ Vh,
                                                             int64_t ldvh) {
-  __shared__ double sig[256];
+  __shared__ double sig[JACOBI_MAX_L];
   jacobi_finish<JNT>(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
 }
 
 }  // namespace
 
+// control words of the block iteration: tags [64], rotation flags [2][64],
+// the abort flag (FLAG_STRIDE apart; at most 64 workgroups)
+constexpr int JCTL = 200;
+
 size_t jacobi_work_bytes(int l) {
   // W, V (l x l each) and the control words of the block iteration
-  return 2 * (size_t)l * l * sizeof(double) + 64 * FLAG_STRIDE * sizeof(uint32_t) + 256;
+  return 2 * (size_t)l * l * sizeof(double) + JCTL * FLAG_STRIDE * sizeof(uint32_t) + 256;
+}
+
+template <int JRPL>
+hipError_t launch_block(JacArgs& a, hipStream_t s) {
+  const size_t shm = JacDims<JRPL>::LDS;
+  hipError_t e = hipFuncSetAttribute((const void*)jacobi_block_kernel<JRPL>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchKernel((const void*)jacobi_block_kernel<JRPL>, dim3(a.G), dim3(JB_NT), args,
+                         shm, s);
 }
 
 hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
                          double* Uh, int64_t lduh, double* Vh, int64_t ldvh, int max_sweeps,
-                         int32_t* info, int32_t* sweeps_out, bool coop, hipStream_t s) {
-  if (l > 256) return hipErrorInvalidValue;
+                         int32_t* info, int32_t* sweeps_out, bool giveup_test, hipStream_t s) {
+  if (l > JACOBI_MAX_L) return hipErrorInvalidValue;
   const double tol = (double)l * 2.220446049250313e-16;
   if (l <= LDS_MAX_L) {
     const size_t shm = 2 * (size_t)l * l * sizeof(double);
@@ -391,26 +434,20 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
   JacArgs a;
   a.W = W; a.V = V; a.ld = l; a.l = l; a.nbp = nbp; a.G = nbp / 2; a.max_sweeps = max_sweeps;
   a.tol = tol;
-  a.tags = ctl;                                   // 16 flags
-  a.rot = ctl + 16 * FLAG_STRIDE;                 // 2 x 16 flags
-  a.abort_flag = ctl + 48 * FLAG_STRIDE;
+  a.tags = ctl;                                   // 64 flags
+  a.rot = ctl + 64 * FLAG_STRIDE;                 // 2 x 64 flags
+  a.abort_flag = ctl + 192 * FLAG_STRIDE;
+  a.wait_bias = giveup_test ? 1u : 0u;
+  a.spin_cap = giveup_test ? (1u << 10) : (1u << 22);
   a.info = info;
   a.sweeps_out = sweeps_out;
-  hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)cdiv((int64_t)l * l, 256)), dim3(256), 0,
-                     s, Rh, ldr, l, W, V, (int64_t)l, ctl, 64 * FLAG_STRIDE);
+  // one thread per element of W and per control word
+  const int64_t ninit = std::max<int64_t>((int64_t)l * l, (int64_t)JCTL * FLAG_STRIDE);
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, Rh,
+                     ldr, l, W, V, (int64_t)l, ctl, JCTL * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t shm = (2 * (size_t)BS * JLD + (size_t)JJ * JJS) * sizeof(double);
-  e = hipFuncSetAttribute((const void*)jacobi_block_kernel,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
-  void* args[] = {&a};
-  if (coop) {
-    e = hipLaunchCooperativeKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args,
-                                   shm, s);
-  } else {
-    e = hipLaunchKernel((const void*)jacobi_block_kernel, dim3(a.G), dim3(JB_NT), args, shm, s);
-  }
+  e = (l <= 256) ? launch_block<16>(a, s) : launch_block<36>(a, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, (int64_t)l, l, k, S, Uh,
                      lduh, Vh, ldvh);

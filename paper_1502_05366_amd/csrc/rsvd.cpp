@@ -32,6 +32,9 @@ struct rsvd_handle_s {
   // beside the ID / CUR post-processing inside rsvd_decompose
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
+  // options (rsvd_set_option)
+  int jacobi_max_sweeps;
+  bool giveup_test;
 };
 
 // Host side of a batch: the per-matrix descriptors in work-queue order and
@@ -322,8 +325,8 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
       RSVD_TRY(hipStreamWaitEvent(c.h->aux, c.h->ev_fork, 0));
       s1 = c.h->aux;
     }
-    RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, o.S, b.Uh, s.kp, b.Vh, s.kp, JACOBI_MAX_SWEEPS,
-                           c.info, nullptr, !fork, s1));
+    RSVD_TRY(launch_jacobi(b.Rh, lp, l, k, b.Wj, o.S, b.Uh, s.kp, b.Vh, s.kp,
+                           c.h->jacobi_max_sweeps, c.info, nullptr, c.h->giveup_test, s1));
     const GemmPlan pu = plan_gemm(m, l, k, ncu, 0);
     RSVD_TRY(launch_gemm(f32 ? GEMM_FDDF : GEMM_DDDD, false, b.Q, lp, b.Vh, s.kp, o.U, o.ldu, m, l,
                          k, pu, b.ob.part, b.ob.part_bytes, s1));
@@ -339,14 +342,14 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
     const int64_t ldt = o.T ? o.ldt : (n - k);
     const CpqrPlan cp = plan_cpqr(l, n, k, ncq);
     RSVD_TRY(launch_cpqr(f32, b.Z, lp, l, n, k, cp, b.cq_work, J, b.S11t, b.S12t, s.kp, b.pivn,
-                         c.info, !fork, c.st));
+                         c.info, c.h->giveup_test, c.st));
     RSVD_TRY(launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st));
     if (o.Jr) {
       // row selection on C^T = A(:, J_k)^T
       RSVD_TRY(launch_gather_cols(s.atype, A, lda, m, n, J, k, b.Crow, s.kp, c.st));
       const CpqrPlan cp2 = plan_cpqr(k, m, k, ncq);
       RSVD_TRY(launch_cpqr(false, b.Crow, s.kp, k, m, k, cp2, b.cq2_work, b.J2, b.S11t2, b.S12t2,
-                           s.kp, b.pivn2, c.info, !fork, c.st));
+                           s.kp, b.pivn2, c.info, c.h->giveup_test, c.st));
       // R^T = A(Jr, :)^T = Qt Rt
       RSVD_TRY(launch_gather_rows_t(s.atype, A, lda, m, n, b.J2, k, b.Rt, s.kp, c.st));
       RSVD_TRY(orth(c, b.ob2, false, b.Rt, s.kp, n, k, b.Qt, false, s.kp, b.Rtt, s.kp));
@@ -425,7 +428,7 @@ hipError_t run_id_left(Ctx& c, const Shape& s, const LeftBufs& b, const void* A,
   }
   const CpqrPlan cp = plan_cpqr(l, n, k, std::min(c.ncu, NCU_CAP));
   RSVD_TRY(launch_cpqr(f32, b.Yt, lp, l, n, k, cp, b.cq_work, J, b.S11t, b.S12t, s.kp, b.pivn,
-                       c.info, true, c.st));
+                       c.info, c.h->giveup_test, c.st));
   return launch_backsub(b.S11t, 1, s.kp, b.S12t, 1, s.kp, k, n - k, T, ldt, 1, c.st);
 }
 
@@ -644,8 +647,8 @@ hipError_t run_grad(Ctx& c, const Shape& s, const GradBufs& g, const double* A, 
   RSVD_TRY(orth(c, ob, false, g.Yt, lp, m, l, g.Q, false, lp, g.Rq, lp));
   RSVD_TRY(pass(c, 0, true, m, n, l, A, lda, g.Q, lp, g.Zt, lp, ob.part, ob.part_bytes));
   RSVD_TRY(orth(c, ob, false, g.Zt, lp, n, l, g.Qh, false, lp, g.Rh, lp));
-  RSVD_TRY(launch_jacobi(g.Rh, lp, l, l, g.Wj, g.sv, g.Uh, lp, g.Vh, lp, JACOBI_MAX_SWEEPS,
-                         c.info, nullptr, true, c.st));
+  RSVD_TRY(launch_jacobi(g.Rh, lp, l, l, g.Wj, g.sv, g.Uh, lp, g.Vh, lp, c.h->jacobi_max_sweeps,
+                         c.info, nullptr, c.h->giveup_test, c.st));
   if (io.U) RSVD_TRY(small_gemm(c, ob, false, g.Q, lp, g.Vh, lp, io.U, io.ldu, m, l, k));
   if (io.V) RSVD_TRY(small_gemm(c, ob, false, g.Qh, lp, g.Uh, lp, io.V, io.ldv, n, l, k));
   if (io.S)
@@ -747,6 +750,8 @@ int rsvd_create(rsvd_handle_t* handle, int device) {
   h->ncu = prop.multiProcessorCount;
   h->aux = nullptr;
   h->ev_fork = h->ev_join = nullptr;
+  h->jacobi_max_sweeps = JACOBI_MAX_SWEEPS;
+  h->giveup_test = false;
   const bool ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
@@ -766,6 +771,22 @@ int rsvd_destroy(rsvd_handle_t handle) {
   if (handle->aux) (void)hipStreamDestroy(handle->aux);
   delete handle;
   return RSVD_OK;
+}
+
+int rsvd_set_option(rsvd_handle_t h, int option, int value) {
+  if (!h) return -1;
+  switch (option) {
+    case RSVD_OPT_JACOBI_MAX_SWEEPS:
+      if (value < 1 || value > 1000) return -3;
+      h->jacobi_max_sweeps = value;
+      return RSVD_OK;
+    case RSVD_OPT_TEST_WAIT_GIVEUP:
+      if (value != 0 && value != 1) return -3;
+      h->giveup_test = value != 0;
+      return RSVD_OK;
+    default:
+      return -2;
+  }
 }
 
 const char* rsvd_status_string(int code) {
@@ -1346,8 +1367,8 @@ int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t 
   hipError_t e = launch_set_word(info, 0, st);
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   if (e == hipSuccess)
-    e = launch_jacobi(Rh, ldr, (int)l, k, jw, S, Uh, lduh, Vh, ldvh, JACOBI_MAX_SWEEPS, info,
-                      nullptr, true, st);
+    e = launch_jacobi(Rh, ldr, (int)l, k, jw, S, Uh, lduh, Vh, ldvh, h->jacobi_max_sweeps, info,
+                      nullptr, h->giveup_test, st);
   return finish(e);
 }
 
@@ -1396,7 +1417,7 @@ int rsvd_cpqr(rsvd_handle_t h, int dtype, int64_t r, int64_t c, int k, const voi
   if (e == hipSuccess) e = launch_set_word(info + 1, 0, st);
   if (e == hipSuccess)
     e = launch_cpqr(dtype == RSVD_F32, Bcols, ldb, (int)r, c, k, pr, cw, J, S11t, S12t, kp, pv,
-                    info, true, st);
+                    info, h->giveup_test, st);
   if (e == hipSuccess && c > k)
     e = launch_backsub(S11t, 1, kp, S12t, 1, kp, k, c - k, T, ldt, 1, st);
   if (e == hipSuccess && pivn)

@@ -63,6 +63,17 @@ def c1_matrix(seed=0xC0FFEE00):
     return A, s
 
 
+def kron_haar_factors(m1, r1, m2, n1, n2, seed):
+    """The Haar factors of kron_haar_matrix: U1[:, :r1] (U1 m1 x m1), U2
+    (m2 x m2), V1 (n1 x n1), V2 (n2 x n2), drawn in that order."""
+    g = rng(seed)
+    U1 = haar(g, m1, m1)[:, :r1]
+    U2 = haar(g, m2, m2)
+    V1 = haar(g, n1, n1)
+    V2 = haar(g, n2, n2)
+    return U1, U2, V1, V2
+
+
 def kron_haar_matrix(m1, r1, m2, n1, n2, s, seed):
     """A = (U1[:, :r1] kron U2) diag(s) (V1 kron V2)^T.
 
@@ -73,11 +84,7 @@ def kron_haar_matrix(m1, r1, m2, n1, n2, s, seed):
     Kronecker factors: rows (a, b) of W = diag(s) V^T are mapped by
     U1[:, :r1] on a and by U2 on b.
     """
-    g = rng(seed)
-    U1 = haar(g, m1, m1)[:, :r1]
-    U2 = haar(g, m2, m2)
-    V1 = haar(g, n1, n1)
-    V2 = haar(g, n2, n2)
+    U1, U2, V1, V2 = kron_haar_factors(m1, r1, m2, n1, n2, seed)
     r = r1 * m2
     n = n1 * n2
     assert r == len(s) and r == n
@@ -85,7 +92,24 @@ def kron_haar_matrix(m1, r1, m2, n1, n2, s, seed):
     W *= np.asarray(s, dtype=np.float64)[:, None]
     W = W.reshape(r1, m2, n)
     T1 = np.matmul(U2[None, :, :], W)            # (r1, m2, n): U2 on index b
+    del W
     A = np.tensordot(U1, T1, axes=([1], [0]))    # (m1, m2, n): U1 on index a
+    return A.reshape(m1 * m2, n)
+
+
+def kron_haar_matrix_torch(m1, r1, m2, n1, n2, s, seed, device):
+    """kron_haar_matrix assembled on a device with torch (FP64), from the same
+    factors; it differs from the host assembly only by the order of the
+    rounding of the sums (a few units of FP64 rounding per entry)."""
+    import torch
+    U1, U2, V1, V2 = (torch.as_tensor(x, device=device)
+                      for x in kron_haar_factors(m1, r1, m2, n1, n2, seed))
+    n = n1 * n2
+    W = torch.kron(V1.T.contiguous(), V2.T.contiguous())
+    W *= torch.as_tensor(np.asarray(s, dtype=np.float64), device=device)[:, None]
+    T1 = torch.matmul(U2, W.view(r1, m2, n))     # (r1, m2, n)
+    del W
+    A = torch.tensordot(U1, T1, dims=([1], [0]))  # (m1, m2, n)
     return A.reshape(m1 * m2, n)
 
 
@@ -102,6 +126,28 @@ def c2_matrix(seed=0xC0FFEE01, noise_std=1e-6):
         g = rng(seed ^ 0x5A5A5A5A)
         A += noise_std * g.standard_normal(A.shape)
     return A, s
+
+
+C3_SHAPE = (65536, 32768)
+C3_KRON = (256, 128, 256, 128, 256)       # m1, r1, m2, n1, n2
+
+
+def c3_spectrum():
+    """sigma_j = j^(-1.5), j = 1..32768."""
+    return np.arange(1, C3_SHAPE[1] + 1, dtype=np.float64) ** -1.5
+
+
+def c3_matrix(seed=0xC0FFEE02):
+    """65536 x 32768, sigma_j = j^(-1.5), Kronecker-Haar factors
+    U = U1[:, :128] kron U2 (U1, U2 256^2) and V = V1 kron V2 (128^2, 256^2):
+    the mixed-precision workload (stored BF16 or FP8 E4M3 with per-column
+    scales).  17.2 GB in FP64."""
+    return kron_haar_matrix(*C3_KRON, c3_spectrum(), seed), c3_spectrum()
+
+
+def c3_matrix_torch(device, seed=0xC0FFEE02):
+    """c3_matrix assembled on the device (FP64)."""
+    return kron_haar_matrix_torch(*C3_KRON, c3_spectrum(), seed, device)
 
 
 C5_SHAPE = (8192, 4096)
