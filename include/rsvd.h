@@ -59,7 +59,8 @@ enum {
   RSVD_ERR_HIP = 1,         /* a HIP call failed (launch or device query)       */
   RSVD_ERR_WORKSPACE = 2,   /* work_bytes smaller than the workspace query      */
   RSVD_ERR_UNSUPPORTED = 3, /* valid arguments outside what this build supports */
-  RSVD_ERR_NO_DEVICE = 4    /* no HIP device with the requested index           */
+  RSVD_ERR_NO_DEVICE = 4,   /* no HIP device with the requested index           */
+  RSVD_ERR_SCRATCH = 5      /* the call needs more than RSVD_NOALLOC_MAX_BYTES  */
 };
 
 enum {
@@ -114,6 +115,22 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
              uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
              void* V, int64_t ldv, void* work, size_t work_bytes, int32_t* info,
              void* stream);
+
+/* rsvd_svd without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops): the call
+ * allocates nothing and uses a static scratch array of RSVD_NOALLOC_MAX_BYTES
+ * (64 MiB) in device memory instead, one copy per device that loads the
+ * library, held until the process ends.  Same arguments (without work,
+ * work_bytes), outputs and errors as rsvd_svd, plus RSVD_ERR_SCRATCH when the
+ * problem needs more scratch than that: rsvd_svd_noalloc_bytes(...) returns
+ * the need (0 for invalid sizes).  Every call on a device shares that device's
+ * scratch and leaves its contents behind, so calls that overlap on one device
+ * (two streams, two host threads) race and must not be issued. */
+#define RSVD_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+size_t rsvd_svd_noalloc_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q);
+int rsvd_svd_noalloc(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                     uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
+                     void* V, int64_t ldv, int32_t* info, void* stream);
 
 /* Rank-k column ID computed from B = Q^T A (Sec. 3.5, last part; Alg. 1 on B):
  * k steps of column-pivoted QR of B give the skeleton J[0..k) (pivot order)

@@ -5,6 +5,7 @@ Every step of the computation runs in the library's HIP kernels; PyTorch is
 used for device memory and streams.  Names follow the C entry points:
 
     svd(A, k, p, q, seed)        -> U, S, V, info      (Alg. 5, s = 1)
+    svd_noalloc(A, k, p, q, seed) -> the same without a workspace (static scratch)
     id(A, k, p, q, seed)         -> J, T, info         (ID from B = Q^T A)
     id_left(A, k, p, q, seed)    -> J, T, info         (ID from Y = Omega~ A, Alg. 6)
     qb(A, b, M, q, tol, seed)    -> Q, B, resid, R, info (blocked adaptive QB, Alg. 7)
@@ -18,7 +19,7 @@ and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
 """
 
 from .api import (  # noqa: F401
-    RsvdError, handle, svd, id, id_left, qb, cur, svd_grad, svd_diff, BatchPlan, decompose,
+    RsvdError, handle, svd, svd_noalloc, id, id_left, qb, cur, svd_grad, svd_diff, BatchPlan, decompose,
     workspace_bytes, sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK,
     INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32, set_option,
     OPT_JACOBI_MAX_SWEEPS, OPT_TEST_WAIT_GIVEUP,

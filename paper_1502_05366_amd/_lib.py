@@ -27,6 +27,9 @@ SIGNATURES = {
     "rsvd_workspace_bytes": (c_size, [c_int, c_int, c_i64, c_i64, c_int, c_int, c_int]),
     "rsvd_svd": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr, c_i64,
                          c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_size, c_ptr, c_ptr]),
+    "rsvd_svd_noalloc_bytes": (c_size, [c_int, c_i64, c_i64, c_int, c_int, c_int]),
+    "rsvd_svd_noalloc": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr,
+                                 c_i64, c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_ptr]),
     "rsvd_id": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr, c_i64,
                         c_ptr, c_ptr, c_i64, c_ptr, c_size, c_ptr, c_ptr]),
     "rsvd_qb_workspace_bytes": (c_size, [c_int, c_i64, c_i64, c_int, c_int, c_int]),

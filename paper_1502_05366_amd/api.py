@@ -193,6 +193,27 @@ def svd(A, k, p, q, seed):
     return U, S, V, info
 
 
+def svd_noalloc(A, k, p, q, seed, out=None):
+    """rsvd_svd_noalloc: the randomized SVD of `svd` with the library's static
+    device scratch instead of a workspace.  `out` = (U, S, V, info) tensors to
+    write into (allocated here when None)."""
+    lib = _lib.load()
+    A = _row_major(A)
+    dev = A.device
+    m, n = A.shape
+    dt = _dtype_code(A)
+    if out is None:
+        out = (torch.empty((m, k), dtype=_out_dtype(A), device=dev),
+               torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty((n, k), dtype=_out_dtype(A), device=dev),
+               torch.zeros(2, dtype=torch.int32, device=dev))
+    U, S, V, info = out
+    rc = lib.rsvd_svd_noalloc(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0), _ptr(U),
+                              U.stride(0), _ptr(S), _ptr(V), V.stride(0), _ptr(info), _stream(dev))
+    _check(rc, "rsvd_svd_noalloc")
+    return U, S, V, info
+
+
 def id(A, k, p, q, seed):  # noqa: A001  (named after the C entry point)
     """Rank-k column ID: J (n; skeleton J[:k]), T (k x (n-k)), info."""
     lib = _lib.load()

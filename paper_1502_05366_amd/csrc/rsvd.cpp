@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -35,6 +36,8 @@ struct rsvd_handle_s {
   // options (rsvd_set_option)
   int jacobi_max_sweeps;
   bool giveup_test;
+  // this device's copy of the static scratch of rsvd_svd_noalloc
+  void* scratch;
 };
 
 // Host side of a batch: the per-matrix descriptors in work-queue order and
@@ -55,8 +58,31 @@ struct rsvd_batch_s {
   const void* prepared;                  // the workspace that holds the descriptors
 };
 
+// Scratch of rsvd_svd_noalloc: a fixed array in device memory, one copy per
+// device that loads the library, held until the process ends.  In host code
+// its name is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns on each device (scratch_addr).
+static __device__ __align__(256) char scratch[RSVD_NOALLOC_MAX_BYTES];
+
 namespace rsvd {
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES];
+
+// The address of `scratch` on the current device `device`, looked up once per
+// device (nullptr when the lookup fails).
+void* scratch_addr(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    scratch_dev[device] = p;
+  }
+  return scratch_dev[device];
+}
 
 constexpr int MAX_L = 256;
 constexpr int NCU_CAP = 256;          // workspace is sized for at most this many CUs
@@ -752,7 +778,9 @@ int rsvd_create(rsvd_handle_t* handle, int device) {
   h->ev_fork = h->ev_join = nullptr;
   h->jacobi_max_sweeps = JACOBI_MAX_SWEEPS;
   h->giveup_test = false;
-  const bool ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
+  h->scratch = scratch_addr(device);   // with `device` current
+  const bool ok = h->scratch != nullptr &&
+                  hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
   (void)hipSetDevice(prev);
@@ -797,6 +825,7 @@ const char* rsvd_status_string(int code) {
     case RSVD_ERR_WORKSPACE: return "workspace too small";
     case RSVD_ERR_UNSUPPORTED: return "unsupported by this build";
     case RSVD_ERR_NO_DEVICE: return "no such device";
+    case RSVD_ERR_SCRATCH: return "needs more than the static scratch of the no-allocation call";
     default: return "unknown status";
   }
 }
@@ -883,6 +912,37 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   Bufs b;
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+size_t rsvd_svd_noalloc_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q) {
+  return rsvd_workspace_bytes(RSVD_OP_SVD, dtype, m, n, k, p, q);
+}
+
+int rsvd_svd_noalloc(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                     uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
+                     void* V, int64_t ldv, int32_t* info, void* stream) {
+  int rc = check_common(h, dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
+  if (!U) return -11;
+  if (ldu < k) return -12;
+  if (!S) return -13;
+  if (!V) return -14;
+  if (ldv < k) return -15;
+  if (!info) return -16;
+  const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
+  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (layout(s, nullptr, nullptr) > RSVD_NOALLOC_MAX_BYTES) return RSVD_ERR_SCRATCH;
+  Bufs b;
+  layout(s, h->scratch, &b);
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
   Outs o;
