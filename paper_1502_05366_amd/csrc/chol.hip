@@ -468,6 +468,28 @@ __global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ Am
 
 __global__ void set_word_kernel(int32_t* w, int32_t v) { *w = v; }
 
+// T = Y - T: the residual of a projection of Y (block orthonormalization)
+template <typename TY>
+__global__ __launch_bounds__(256) void rsub_kernel(const TY* __restrict__ Y, int64_t ldy,
+                                                   double* __restrict__ T, int64_t ldt,
+                                                   int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e - r * cols;
+    T[r * ldt + c] = (double)Y[r * ldy + c] - T[r * ldt + c];
+  }
+}
+
+// rows of R that belong to dependent columns, zeroed (their unit rows are
+// placeholders, not part of Y = Q R)
+__global__ __launch_bounds__(64) void zero_dep_rows_kernel(double* __restrict__ R, int64_t ldr,
+                                                           int lp, const int32_t* __restrict__ dep) {
+  const int j = blockIdx.x;
+  if (!dep[j]) return;
+  for (int c = threadIdx.x; c < lp; c += blockDim.x) R[(int64_t)j * ldr + c] = 0.0;
+}
+
 // Gram matrix G = Y^T Y (FP64) of a tall Y (rows x l), upper 16x16 tiles only.
 // The column blocks are cut into segments of 4; a tile group is a pair of
 // segments (sa <= sb) and holds the at most 16 upper tiles between them, so a
@@ -747,6 +769,27 @@ hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int6
 
 hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(set_word_kernel, dim3(1), dim3(1), 0, s, w, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_rsub(bool y_f32, const void* Y, int64_t ldy, double* T, int64_t ldt,
+                       int64_t rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  int64_t grid = cdiv(rows * cols, 256);
+  if (grid > 16384) grid = 16384;
+  if (y_f32)
+    hipLaunchKernelGGL(rsub_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s,
+                       (const float*)Y, ldy, T, ldt, rows, cols);
+  else
+    hipLaunchKernelGGL(rsub_kernel<double>, dim3((unsigned)grid), dim3(256), 0, s,
+                       (const double*)Y, ldy, T, ldt, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_dep_rows(double* R, int64_t ldr, int l, int lp, const int32_t* dep,
+                                hipStream_t s) {
+  if (l <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_dep_rows_kernel, dim3(l), dim3(64), 0, s, R, ldr, lp, dep);
   return hipGetLastError();
 }
 

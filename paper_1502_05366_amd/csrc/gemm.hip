@@ -346,6 +346,8 @@ hipError_t launch_gemm(GemmTypes ty, bool trans, const void* A, int64_t lda, con
     case GEMM_FFDD: return dispatch_trans<float, float, double, double>(g, trans, p.cbw, s);
     case GEMM_FDDF: return dispatch_trans<float, double, double, float>(g, trans, p.cbw, s);
     case GEMM_DDDF: return dispatch_trans<double, double, double, float>(g, trans, p.cbw, s);
+    case GEMM_FDDD: return dispatch_trans<float, double, double, double>(g, trans, p.cbw, s);
+    case GEMM_DFDD: return dispatch_trans<double, float, double, double>(g, trans, p.cbw, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -23,6 +23,8 @@ enum GemmTypes {      // element types A, X, compute, C
   GEMM_FFDD = 2,
   GEMM_FDDF = 3,
   GEMM_DDDF = 4,
+  GEMM_FDDD = 5,
+  GEMM_DFDD = 6,
 };
 struct GemmPlan {
   int64_t nrt, nct, KI, U, G;
@@ -89,6 +91,12 @@ hipError_t launch_replace(bool q_f32, void* Q, int64_t ldq, int64_t M, int l, co
 hipError_t launch_trmm_upper(const double* A, int64_t lda, const double* B, int64_t ldb,
                              const int32_t* bdep, double* C, int64_t ldc, int lp, hipStream_t s);
 hipError_t launch_set_word(int32_t* w, int32_t v, hipStream_t s);
+// T = Y - T (rows x cols; Y FP32 or FP64, T FP64)
+hipError_t launch_rsub(bool y_f32, const void* Y, int64_t ldy, double* T, int64_t ldt,
+                       int64_t rows, int cols, hipStream_t s);
+// rows j < l of R with dep[j] != 0 set to zero (R lp x lp)
+hipError_t launch_zero_dep_rows(double* R, int64_t ldr, int l, int lp, const int32_t* dep,
+                                hipStream_t s);
 
 // ---------------------------------------------------------------- jacobi --
 // work: jacobi_work_bytes(l) bytes; sweeps_out (device int, may be null)

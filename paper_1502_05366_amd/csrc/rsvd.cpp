@@ -84,7 +84,9 @@ void* scratch_addr(int device) {
   return scratch_dev[device];
 }
 
-constexpr int MAX_L = 256;
+constexpr int MAX_L = 256;          // ID / CUR, derivative, blocked QB
+constexpr int MAX_L_SVD = 576;      // randomized SVD and its steps (block Jacobi limit)
+constexpr int ORTH_BLOCK = 256;     // orth works on column blocks of at most this many
 constexpr int NCU_CAP = 256;          // workspace is sized for at most this many CUs
 constexpr double ETA_ORTH = 1e-13;    // Cholesky pivot / G_jj below which a column is dependent
 constexpr int JACOBI_MAX_SWEEPS = 40;
@@ -135,6 +137,9 @@ struct OrthBufs {
   void* part = nullptr;
   size_t part_bytes = 0;
   double* gpart = nullptr;  // partial Gram tiles, gram_part_bytes(lp, NCU_CAP)
+  // l > ORTH_BLOCK (column blocks): the projected block T (rows x ORTH_BLOCK) and
+  // the coefficients W, W2 and W2 R1 (lp x ORTH_BLOCK)
+  double *T = nullptr, *W = nullptr, *W2 = nullptr, *P2 = nullptr;
 };
 
 struct Bufs {
@@ -157,6 +162,8 @@ struct Bufs {
 size_t max_part(const Shape& s) {
   const int ncu = NCU_CAP;
   size_t b = 0;
+  // the projections of the block orth: at most every CU with a full partial tile
+  if (s.l > ORTH_BLOCK) b = (size_t)2 * ncu * 128 * 256 * sizeof(double);
   auto upd = [&](int64_t M, int64_t K, int64_t L) {
     if (M <= 0 || K <= 0 || L <= 0) return;
     b = std::max(b, gemm_part_bytes(plan_gemm(M, K, L, ncu, 0), 8));
@@ -187,6 +194,12 @@ OrthBufs take_orth(Arena& a, int64_t rows, int lp, size_t part_bytes) {
   ob.part_bytes = part_bytes;
   ob.part = a.take<char>(part_bytes);
   ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
+  if (lp > ORTH_BLOCK) {
+    ob.T = a.take<double>((size_t)rows * ORTH_BLOCK);
+    ob.W = a.take<double>((size_t)lp * ORTH_BLOCK);
+    ob.W2 = a.take<double>((size_t)lp * ORTH_BLOCK);
+    ob.P2 = a.take<double>((size_t)lp * ORTH_BLOCK);
+  }
   return ob;
 }
 
@@ -257,27 +270,112 @@ constexpr int JACOBI_CU_RESERVE = 8;
     if (e_ != hipSuccess) return e_;        \
   } while (0)
 
-// Q = orth(Y) by CholeskyQR2 (rows x l); optionally R = R2 R1 (lp x lp, ldr).
-hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
-                int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
-                int64_t ldr) {
+// First CholeskyQR pass of orth (l <= ORTH_BLOCK): G = Y^T Y = R1^T R1,
+// Qa = Y R1^{-1} (FP64, ld rup(l, 16)), dependent columns of Qa replaced.
+hipError_t orth_p1(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
+                   int64_t rows, int l) {
   const int lp = (int)rup(l, 16);
   const int gG = std::min(c.ncu, NCU_CAP);
-  // pass 1: G = Y^T Y, G = R1^T R1, Qa = Y R1^{-1}, dependent columns replaced
   RSVD_TRY(launch_gram(y_f32, Y, ldy, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R1, lp, ob.Rd1, ob.dep, c.info, c.st));
   RSVD_TRY(launch_trsm(y_f32, false, Y, ldy, rows, l, lp, ob.R1, lp, ob.Rd1, ob.Qa, lp, c.st));
-  RSVD_TRY(launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st));
-  // pass 2 on Qa
+  return launch_replace(false, ob.Qa, lp, rows, l, ob.dep, c.seed, c.orth_calls++, c.st);
+}
+
+// Second pass: Qa = Q R2.  An FP32 basis is the first pass rounded to FP32
+// when that pass is already orthonormal far below the FP32 rounding (the
+// near-identity parts decide).
+hipError_t orth_p2(Ctx& c, const OrthBufs& ob, int64_t rows, int l, void* Q, bool q_f32,
+                   int64_t ldq) {
+  const int lp = (int)rup(l, 16);
+  const int gG = std::min(c.ncu, NCU_CAP);
   RSVD_TRY(launch_gram(false, ob.Qa, lp, rows, l, lp, ob.G, lp, ob.gpart, gG, c.st));
   RSVD_TRY(launch_chol(ob.G, lp, l, lp, ETA_ORTH, ob.R2, lp, ob.Rd2, ob.dep2, c.info, c.st,
                        ob.nip));
-  // an FP32 basis is the first pass rounded to FP32 when that pass is already
-  // orthonormal far below the FP32 rounding (the near-identity parts decide)
-  RSVD_TRY(launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st,
-                       q_f32 ? ob.nip : nullptr));
+  return launch_trsm(false, q_f32, ob.Qa, lp, rows, l, lp, ob.R2, lp, ob.Rd2, Q, ldq, c.st,
+                     q_f32 ? ob.nip : nullptr);
+}
+
+// Q = orth(Y) by CholeskyQR2 (rows x l, l <= ORTH_BLOCK); optionally
+// R = R2 R1 (rup(l, 16) square, ldr).
+hipError_t orth_small(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
+                      int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
+                      int64_t ldr) {
+  const int lp = (int)rup(l, 16);
+  RSVD_TRY(orth_p1(c, ob, y_f32, Y, ldy, rows, l));
+  RSVD_TRY(orth_p2(c, ob, rows, l, Q, q_f32, ldq));
   if (Rout) RSVD_TRY(launch_trmm_upper(ob.R2, lp, ob.R1, lp, ob.dep, Rout, ldr, lp, c.st));
   return hipSuccess;
+}
+
+// Q = orth(Y) for l > ORTH_BLOCK: block Gram-Schmidt over column blocks Y_j of
+// at most ORTH_BLOCK columns, each block projected against the columns
+// before it (Qb) and factored by one CholeskyQR pass, twice:
+//   T = Y_j - Qb (Qb^T Y_j) = Qa R1;  Qa - Qb (Qb^T Qa) = Q_j R2
+// so Y_j = Qb (W1 + W2 R1) + Q_j (R2 R1), with W1 = Qb^T Y_j, W2 = Qb^T Qa
+// (a replaced dependent column of Qa is projected in the second pass too).
+// The result is the QR factorization of Y with a positive diagonal (the
+// same Q and R as one CholeskyQR2 of all l columns, to rounding).
+hipError_t orth_blocks(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
+                       int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
+                       int64_t ldr) {
+  const int nblk = (int)cdiv(l, ORTH_BLOCK);
+  const int bs = (int)rup(cdiv(l, nblk), 16);
+  const int lp = (int)rup(l, 16);
+  const size_t ysz = y_f32 ? 4 : 8, qsz = q_f32 ? 4 : 8;
+  const int ncu = std::min(c.ncu, NCU_CAP);
+  const int64_t ldw = ORTH_BLOCK;
+  const GemmTypes ty = q_f32 ? (y_f32 ? GEMM_FFDD : GEMM_FDDD) : (y_f32 ? GEMM_DFDD : GEMM_DDDD);
+  const GemmTypes tq = q_f32 ? GEMM_FDDD : GEMM_DDDD;
+  if (Rout) RSVD_TRY(launch_zero(Rout, ldr, lp, lp, c.st));
+  for (int j = 0; j < nblk; ++j) {
+    const int c0 = j * bs;
+    const int bj = std::min(bs, l - c0);
+    const int lpj = (int)rup(bj, 16);
+    const void* Yj = static_cast<const char*>(Y) + c0 * ysz;
+    void* Qj = static_cast<char*>(Q) + c0 * qsz;
+    double* Rjj = Rout ? Rout + (int64_t)c0 * ldr + c0 : nullptr;
+    if (j == 0) {
+      RSVD_TRY(orth_small(c, ob, y_f32, Yj, ldy, rows, bj, Qj, q_f32, ldq, Rjj, ldr));
+      continue;
+    }
+    const GemmPlan pw = plan_gemm(c0, rows, bj, ncu, 0);     // Qb^T X  (c0 x bj)
+    const GemmPlan pp = plan_gemm(rows, c0, bj, ncu, 0);     // Qb W    (rows x bj)
+    double* W1 = Rout ? Rout + c0 : ob.W;                    // R(0:c0, block) holds W1
+    const int64_t ldw1 = Rout ? ldr : ldw;
+    // pass 1
+    RSVD_TRY(launch_gemm(ty, true, Q, ldq, Yj, ldy, W1, ldw1, c0, rows, bj, pw, ob.part,
+                         ob.part_bytes, c.st));
+    RSVD_TRY(launch_gemm(tq, false, Q, ldq, W1, ldw1, ob.T, ldw, rows, c0, bj, pp, ob.part,
+                         ob.part_bytes, c.st));
+    RSVD_TRY(launch_rsub(y_f32, Yj, ldy, ob.T, ldw, rows, bj, c.st));
+    RSVD_TRY(orth_p1(c, ob, false, ob.T, ldw, rows, bj));
+    // pass 2
+    RSVD_TRY(launch_gemm(tq, true, Q, ldq, ob.Qa, lpj, ob.W2, ldw, c0, rows, bj, pw, ob.part,
+                         ob.part_bytes, c.st));
+    RSVD_TRY(launch_gemm(tq, false, Q, ldq, ob.W2, ldw, ob.T, ldw, rows, c0, bj, pp, ob.part,
+                         ob.part_bytes, c.st));
+    RSVD_TRY(launch_sub(ob.Qa, lpj, ob.T, ldw, rows, bj, c.st));
+    RSVD_TRY(orth_p2(c, ob, rows, bj, Qj, q_f32, ldq));
+    if (Rout) {
+      // the unit rows of dependent columns are not part of Y_j = Qb W1 + Qa R1
+      RSVD_TRY(launch_zero_dep_rows(ob.R1, lpj, bj, lpj, ob.dep, c.st));
+      const GemmPlan pr = plan_gemm(c0, bj, bj, ncu, 0);
+      RSVD_TRY(launch_gemm(GEMM_DDDD, false, ob.W2, ldw, ob.R1, lpj, ob.P2, ldw, c0, bj, bj, pr,
+                           ob.part, ob.part_bytes, c.st));
+      RSVD_TRY(launch_add(W1, ldw1, ob.P2, ldw, c0, bj, c.st));
+      RSVD_TRY(launch_trmm_upper(ob.R2, lpj, ob.R1, lpj, ob.dep, Rjj, ldr, lpj, c.st));
+    }
+  }
+  return hipSuccess;
+}
+
+// Q = orth(Y) (rows x l); optionally R (rup(l, 16) square, ldr) with Y = Q R.
+hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t ldy,
+                int64_t rows, int l, void* Q, bool q_f32, int64_t ldq, double* Rout,
+                int64_t ldr) {
+  if (l <= ORTH_BLOCK) return orth_small(c, ob, y_f32, Y, ldy, rows, l, Q, q_f32, ldq, Rout, ldr);
+  return orth_blocks(c, ob, y_f32, Y, ldy, rows, l, Q, q_f32, ldq, Rout, ldr);
 }
 
 // One pass over A: Y = A X (trans false) or Y = A^T X (trans true).  atype 0 / 1:
@@ -754,6 +852,19 @@ int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p,
 
 int finish(hipError_t e) { return e == hipSuccess ? RSVD_OK : RSVD_ERR_HIP; }
 
+// workspace of the orth step: R (lp x lp) and the buffers of one orth
+size_t orth_step_layout(int64_t rows, int l, void* base, OrthBufs* ob, double** Rfull) {
+  const int lp = (int)rup(l, 16);
+  const size_t part = lp > ORTH_BLOCK ? (size_t)2 * NCU_CAP * 128 * 256 * sizeof(double) : 0;
+  Arena a(base);
+  double* R = a.take<double>((size_t)lp * lp);
+  const OrthBufs o = take_orth(a, rows, lp, part);
+  if (ob) *ob = o;
+  if (Rfull) *Rfull = R;
+  return a.off;
+}
+
+
 }  // namespace
 }  // namespace rsvd
 
@@ -875,7 +986,7 @@ int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int 
   int ops = (svd ? RSVD_OP_SVD : 0) | (id ? RSVD_OP_ID : 0) | (cur ? RSVD_OP_CUR : 0);
   if (cur) ops |= RSVD_OP_ID;
   const Shape s = make_shape(ops, dtype, m, n, k, p, q);
-  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (s.l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
   if ((id || cur) && !plan_cpqr(s.l, n, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
   if (cur && !plan_cpqr(k, m, k, NCU_CAP).ok) return RSVD_ERR_UNSUPPORTED;
   Bufs b;
@@ -908,7 +1019,7 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   if (!work) return -16;
   if (!info) return -18;
   const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
-  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (s.l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
   Bufs b;
   const size_t need = layout(s, work, &b);
   if (work_bytes < need) return RSVD_ERR_WORKSPACE;
@@ -939,7 +1050,7 @@ int rsvd_svd_noalloc(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, in
   if (ldv < k) return -15;
   if (!info) return -16;
   const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
-  if (s.l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (s.l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
   if (layout(s, nullptr, nullptr) > RSVD_NOALLOC_MAX_BYTES) return RSVD_ERR_SCRATCH;
   Bufs b;
   layout(s, h->scratch, &b);
@@ -1299,7 +1410,7 @@ size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int
     return 0;
   const int64_t M = trans ? n : m, K = trans ? m : n;
   if (dtype == RSVD_BF16) {
-    if (l > MAX_L) return 0;
+    if (l > MAX_L_SVD) return 0;
     return gemm_bf16_part_bytes(plan_gemm_bf16(M, K, l, NCU_CAP)) + 256 +
            (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
   }
@@ -1327,7 +1438,7 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0, h};
   if (dtype == RSVD_BF16) {
-    if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+    if (l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
     const int64_t K = trans ? m : n;
     const size_t xt_bytes = (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
     char* wb = static_cast<char*>(work);
@@ -1340,15 +1451,8 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
 }
 
 size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l) {
-  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || l < 1 || rows < l || l > MAX_L) return 0;
-  const int lp = (int)rup(l, 16);
-  Arena a(nullptr);
-  a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
-  a.take<double>((size_t)rows * lp);
-  a.take<int32_t>(2 * (size_t)lp);
-  a.take<double>(16);
-  a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
-  return a.off;
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32) || l < 1 || rows < l || l > MAX_L_SVD) return 0;
+  return orth_step_layout(rows, (int)l, nullptr, nullptr, nullptr);
 }
 
 int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
@@ -1358,7 +1462,7 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   if (dtype != RSVD_F64 && dtype != RSVD_F32) return -2;
   if (rows < 1) return -3;
   if (l < 1 || l > rows) return -4;
-  if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
   if (!Y) return -5;
   if (ldy < l) return -6;
   if (!Q) return -7;
@@ -1369,22 +1473,9 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
   if (!info) return -14;
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
   const int lp = (int)rup(l, 16);
-  Arena a(work);
-  double* blk = a.take<double>((size_t)lp * lp * 4 + (size_t)lp * 32);
   OrthBufs ob;
-  ob.G = blk;
-  ob.R1 = blk + (size_t)lp * lp;
-  ob.R2 = blk + 2 * (size_t)lp * lp;
-  double* Rfull = blk + 3 * (size_t)lp * lp;
-  ob.Rd1 = blk + 4 * (size_t)lp * lp;
-  ob.Rd2 = ob.Rd1 + (size_t)lp * 16;
-  ob.Qa = a.take<double>((size_t)rows * lp);
-  ob.dep = a.take<int32_t>(2 * (size_t)lp);
-  ob.dep2 = ob.dep + lp;
-  ob.nip = a.take<double>(16);
-  ob.part = nullptr;
-  ob.part_bytes = 0;
-  ob.gpart = a.take<double>(gram_part_bytes(lp, NCU_CAP) / sizeof(double));
+  double* Rfull = nullptr;
+  orth_step_layout(rows, (int)l, work, &ob, &Rfull);
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ctx c{st, h->ncu, info, seed, 0, h};
   hipError_t e = launch_set_word(info, 0, st);
@@ -1399,7 +1490,7 @@ int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y
 }
 
 size_t rsvd_small_svd_workspace_bytes(int64_t l) {
-  if (l < 1 || l > MAX_L) return 0;
+  if (l < 1 || l > MAX_L_SVD) return 0;
   return jacobi_work_bytes((int)l) + sizeof(int32_t) + 256;
 }
 
@@ -1408,7 +1499,7 @@ int rsvd_small_svd(rsvd_handle_t h, int64_t l, int k, const double* Rh, int64_t 
                    size_t work_bytes, int32_t* info, void* stream) {
   if (!h) return -1;
   if (l < 1) return -2;
-  if (l > MAX_L) return RSVD_ERR_UNSUPPORTED;
+  if (l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
   if (k < 1 || k > l) return -3;
   if (!Rh) return -4;
   if (ldr < l) return -5;
