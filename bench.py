@@ -30,6 +30,8 @@ METRIC = "RSVD GFLOP/s + % HBM roofline; BF16 vs FP64 speedup at stated σ error
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 
 
 # HBM bytes of one pass over A (Y = A X and Z = A^T X averaged), from the
@@ -413,6 +415,146 @@ def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf
     return out
 
 
+def c3_step(lib, h, args, stream, sp, P, e0, e1):
+    """The mixed-precision workload: A 65536 x 32768, sigma_j = j^-1.5
+    (Kronecker-Haar factors), k = 512, p = 64, q = 2, one rsvd_svd_ex call
+    per step with A stored in BF16, in FP8 E4M3 with FP32 column scales, and
+    in FP64 (the reference for the speedups).  Errors against the FP64 oracle
+    on the same A (tests/golden/c3_oracle.json, written by the committed
+    script beside it): sigma relative errors and the range-finder residual
+    ||A - Q Q^T A||_F (Q the returned basis, the product formed in FP64)."""
+    import numpy as np
+    import torch
+    from paper_1502_05366_amd import api, workloads as W
+
+    dev = torch.device("cuda:0")
+    m, n = W.C3_SHAPE
+    k, p, q, seed = 512, 64, 2, 0x5EED0002
+    l = min(k + p, m, n)
+    gpath = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    log("c3: generating A %dx%d (FP64, on the device)" % (m, n))
+    A = W.c3_matrix_torch(dev)
+    Ab = api.quantize(A, api.BF16)
+    A8, sc = api.quantize(A, api.F8E4M3)
+    torch.cuda.synchronize()
+    res = {"workload": "A 65536x32768 = (U1[:, :128] kron U2) diag(j^-1.5) (V1 kron V2)^T, "
+                       "k=512 p=64 q=2; one rsvd_svd_ex call per step; A resident in HBM in the "
+                       "storage format",
+           "m": m, "n": n, "k": k, "p": p, "q": q, "l": l}
+    sig_o = np.array(golden["fp64"]["sigma"]) if golden else None
+    A_fro = float(torch.linalg.vector_norm(A).item())
+
+    def resid_fro(Qb):
+        Q64 = Qb.to(torch.float64)
+        B = Q64.T @ A
+        s2 = 0.0
+        for i in range(0, m, 8192):
+            D = A[i:i + 8192] - Q64[i:i + 8192] @ B
+            s2 += float((D * D).sum().item())
+        return s2 ** 0.5
+
+    specs = (("bf16", api.BF16, Ab, None, torch.float32, args.c3_steps),
+             ("fp8", api.F8E4M3, A8, sc, torch.float32, args.c3_steps),
+             ("fp64", api.F64, A, None, torch.float64, max(2, args.c3_steps // 3)))
+    for name, dt, Ax, scales, ot, steps in specs:
+        wb = lib.rsvd_workspace_bytes(api.OP_SVD, dt, m, n, k, p, q)
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+        info = torch.zeros(2, dtype=torch.int32, device=dev)
+        U = torch.empty((m, k), dtype=ot, device=dev)
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        V = torch.empty((n, k), dtype=ot, device=dev)
+        Qb = torch.empty((m, l), dtype=ot, device=dev)
+        sptr = P(scales) if scales is not None else None
+
+        def step():
+            rc = lib.rsvd_svd_ex(h, dt, m, n, k, p, q, seed, P(Ax), Ax.stride(0), sptr, P(U), k,
+                                 P(S), P(V), k, P(Qb), l, P(work), wb, P(info), sp)
+            if rc != 0:
+                raise RuntimeError("rsvd_svd_ex (%s) returned %d" % (name, rc))
+
+        step()
+        torch.cuda.synchronize()
+        log("c3 %s: warmup done" % name)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        log("c3 %s: %.3f ms/step" % (name, ms))
+        S_np = S.cpu().numpy()
+        st = info.cpu().numpy()
+        r = {"ms_per_step": round(ms, 3), "steps": steps,
+             "value_gflops": round(alg_flops(m, n, k, p, q) / (ms * 1e-3) / 1e9, 1),
+             "info": [int(st[0]), int(st[1])],
+             "qb_resid_fro": resid_fro(Qb)}
+        if golden:
+            rel = np.abs(S_np - sig_o) / sig_o
+            r["sigma_rel_err_vs_fp64_oracle"] = {"max": float(rel.max()),
+                                                 "max_first_64": float(rel[:64].max()),
+                                                 "max_first_256": float(rel[:256].max()),
+                                                 "median": float(np.median(rel))}
+            r["qb_resid_rel_diff_vs_fp64_oracle"] = (r["qb_resid_fro"] / golden["fp64"]["qb_resid_fro"]
+                                                    - 1.0)
+            same = golden[name]["sigma"]
+            r["sigma_rel_err_vs_oracle_same_storage"] = float(np.max(np.abs(S_np - same) /
+                                                                     np.array(same)))
+        # one pass over A in each direction in this storage (X FP32 or FP64)
+        xt = torch.float64 if dt == api.F64 else torch.float32
+        X = torch.randn((n, l), dtype=xt, device=dev)
+        Xm = torch.randn((m, l), dtype=xt, device=dev)
+        Y = torch.empty((m, l), dtype=xt, device=dev)
+        Z = torch.empty((n, l), dtype=xt, device=dev)
+        if dt == api.F8E4M3:
+            pw = max(lib.rsvd_pass_f8_workspace_bytes(0, m, n, l),
+                     lib.rsvd_pass_f8_workspace_bytes(1, m, n, l))
+        else:
+            pw = max(lib.rsvd_pass_workspace_bytes(dt, 0, m, n, l),
+                     lib.rsvd_pass_workspace_bytes(dt, 1, m, n, l))
+        pwork = torch.empty(max(pw, 1), dtype=torch.uint8, device=dev)
+
+        def one_pass(trans, Xt, Yt):
+            if dt == api.F8E4M3:
+                rc = lib.rsvd_pass_f8(h, trans, m, n, l, P(Ax), Ax.stride(0), sptr, P(Xt), l,
+                                      P(Yt), l, 0, P(pwork), pw, sp)
+            else:
+                rc = lib.rsvd_pass(h, dt, trans, m, n, l, P(Ax), Ax.stride(0), P(Xt), l, P(Yt), l,
+                                   P(pwork), pw, sp)
+            if rc != 0:
+                raise RuntimeError("pass (%s) returned %d" % (name, rc))
+
+        reps = 3 if dt == api.F64 else 10
+        pass_ms = {}
+        for trans, Xt, Yt, key in ((0, X, Y, "A_X"), (1, Xm, Z, "At_X")):
+            one_pass(trans, Xt, Yt)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                one_pass(trans, Xt, Yt)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pass_ms[key] = e0.elapsed_time(e1) / reps
+        t_pass = 0.5 * (pass_ms["A_X"] + pass_ms["At_X"])
+        tf = 2.0 * m * n * l / (t_pass * 1e-3) / 1e12
+        peak = {"bf16": PEAK_BF16_TFLOPS, "fp8": PEAK_FP8_TFLOPS, "fp64": PEAK_FP64_TFLOPS}[name]
+        ebytes = {"bf16": 2, "fp8": 1, "fp64": 8}[name]
+        r["pass_ms"] = {kk: round(v, 4) for kk, v in pass_ms.items()}
+        r["pass_roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": peak,
+                              "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                              "a_hbm_GBs": round(ebytes * m * n / (t_pass * 1e-3) / 1e9, 1)}
+        res[name] = r
+        del work, U, V, Qb, X, Xm, Y, Z, pwork
+    res["speedup_bf16_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["bf16"]["ms_per_step"], 3)
+    res["speedup_fp8_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp8"]["ms_per_step"], 3)
+    res["a_fro"] = A_fro
+    if golden:
+        res["oracle_qb_resid_fro"] = golden["fp64"]["qb_resid_fro"]
+    del A, Ab, A8, sc
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +571,12 @@ def main():
                          "(for kernel traces of rsvd_svd_grad)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched section and print its JSON object")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="run only the mixed-precision section (65536 x 32768, l = 576) and "
+                         "print its JSON object")
+    ap.add_argument("--c3-steps", type=int, default=6,
+                    help="timed steps of the BF16 and FP8 runs of the mixed-precision section "
+                         "(the FP64 run takes a third of them, at least 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
@@ -448,6 +596,15 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         print(json.dumps({"batch": batch_step(lib, args, stream, e0, e1)}), flush=True)
+        return
+    if args.c3_only:
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        r = c3_step(lib, api.handle(dev), args, stream, ctypes.c_void_p(stream.cuda_stream), P,
+                    e0, e1)
+        print(json.dumps({"c3": r}), flush=True)
         return
     if args.grad_only:
         stream = torch.cuda.current_stream(dev)
@@ -562,12 +719,13 @@ def main():
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
-    idl = qbr = grd = bat = None
+    idl = qbr = grd = bat = c3r = None
     if not args.no_extras:
         idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
         qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
         grd = grad_step(lib, h, args, stream, sp, P, e0, e1)
         bat = batch_step(lib, args, stream, e0, e1)
+        c3r = c3_step(lib, h, args, stream, sp, P, e0, e1)
 
     out = {
         "metric": METRIC,
@@ -603,6 +761,7 @@ def main():
         out["qb"] = qbr
         out["grad"] = grd
         out["batch"] = bat
+        out["c3"] = c3r
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A_np, k, p, q, seed)

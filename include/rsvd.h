@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-typedef enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2 } rsvd_dtype_t;
+typedef enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2, RSVD_F8E4M3 = 3 } rsvd_dtype_t;
 
 enum {
   RSVD_OK = 0,
@@ -115,6 +115,38 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
              uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu, double* S,
              void* V, int64_t ldv, void* work, size_t work_bytes, int32_t* info,
              void* stream);
+
+/* rsvd_svd with the two additions of the mixed-precision path (Alg. 5; the
+ * re-orthonormalization of Sec. 3.2 between the narrow passes):
+ *  - dtype RSVD_F8E4M3: A holds FP8 E4M3 codes (uint8, lda % 16 == 0, A
+ *    16-byte aligned) and a_col_scale the n FP32 column scales s_j, so that A
+ *    stands for A8 diag(s) (rsvd_quantize makes both from an FP64 A).  For the
+ *    products Y = A X the scales are folded into X before X is quantized to
+ *    E4M3 per column; for Z = A^T X they scale the rows of the result.  The
+ *    passes run on the FP8 matrix cores (FP32 accumulation) and the last
+ *    projection B^T = A^T Q applies Q as the sum of two E4M3 terms.
+ *    a_col_scale must be NULL for the other dtypes (else -11).
+ *  - Qb (optional, m x l with ldqb >= l, type FP64 for RSVD_F64 and FP32
+ *    otherwise): the orthonormal basis Q of the range finder (Alg. 5 up to
+ *    Q = orth(Y)), from which B = Q^T A.
+ * RSVD_F8E4M3 is accepted only here (rsvd_svd_ex) and by rsvd_pass_f8; the
+ * workspace is rsvd_workspace_bytes(RSVD_OP_SVD, dtype, ...). */
+int rsvd_svd_ex(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                uint64_t seed, const void* A, int64_t lda, const float* a_col_scale, void* U,
+                int64_t ldu, double* S, void* V, int64_t ldv, void* Qb, int64_t ldqb, void* work,
+                size_t work_bytes, int32_t* info, void* stream);
+
+/* The storage formats of the mixed-precision path, from an FP64 A (m x n,
+ * lda >= n) into Aq (ldq >= n):
+ *  - RSVD_BF16: Aq (uint16) holds each entry rounded to the nearest BF16
+ *    value, ties to even, directly from FP64 (col_scale unused, may be NULL);
+ *  - RSVD_F8E4M3: col_scale[j] = fl32(max_i |A_ij| / 448) (1 for a zero
+ *    column) and Aq (uint8) the E4M3 code of the FP64 quotient A_ij /
+ *    col_scale[j], nearest with ties to even, saturated to +-448 (the OCP
+ *    E4M3 format: no infinities, largest finite 448).
+ * Both are exact decisions on FP64 values (bit-reproducible). */
+int rsvd_quantize(rsvd_handle_t h, int dtype, int64_t m, int64_t n, const double* A, int64_t lda,
+                  void* Aq, int64_t ldq, float* col_scale, void* stream);
 
 /* rsvd_svd without a workspace argument, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops): the call
@@ -300,6 +332,16 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
  * the columns before it gets a fresh random direction in Q
  * (RSVD_INFO_ORTH_FALLBACK) and a zero diagonal in R, so Y = Q R still holds
  * to rounding.  rows >= l, l <= 256. */
+/* One pass over an FP8 A with column scales (see rsvd_svd_ex): Y = A X
+ * (trans = 0; X n x l, Y m x l) or Y = A^T X (trans = 1; X m x l, Y n x l),
+ * X and Y FP32, A ~ A8 diag(a_col_scale).  split = 1 applies X as the sum of
+ * two E4M3 terms (the second holding the rounding residual of the first).
+ * l <= 576. */
+size_t rsvd_pass_f8_workspace_bytes(int trans, int64_t m, int64_t n, int64_t l);
+int rsvd_pass_f8(rsvd_handle_t h, int trans, int64_t m, int64_t n, int64_t l, const uint8_t* A,
+                 int64_t lda, const float* a_col_scale, const float* X, int64_t ldx, float* Y,
+                 int64_t ldy, int split, void* work, size_t work_bytes, void* stream);
+
 size_t rsvd_orth_workspace_bytes(int dtype, int64_t rows, int64_t l);
 int rsvd_orth(rsvd_handle_t h, int dtype, int64_t rows, int64_t l, const void* Y, int64_t ldy,
               void* Q, int64_t ldq, double* R, int64_t ldr, uint64_t seed, void* work,

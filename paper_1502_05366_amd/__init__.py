@@ -15,12 +15,16 @@ used for device memory and streams.  Names follow the C entry points:
     BatchPlan(ms, ns, ks, p, q)  -> batched RSVD of FP32 matrices in one persistent launch
     decompose(A, k, p, q, seed)  -> dict with all three from one range finder
 
-and the single steps sketch, philox, pass_, orth, small_svd, cpqr.
+    svd_ex(A, k, p, q, seed, scales, want_Q) -> U, S, V, info, Q (also FP8 A with column scales)
+    quantize(A, BF16 | F8E4M3)   -> BF16 A, or (E4M3 codes, column scales), from FP64
+
+and the single steps sketch, philox, pass_, pass_f8, orth, small_svd, cpqr.
 """
 
 from .api import (  # noqa: F401
     RsvdError, handle, svd, svd_noalloc, id, id_left, qb, cur, svd_grad, svd_diff, BatchPlan, decompose,
     workspace_bytes, sketch, philox, pass_, orth, small_svd, cpqr, INFO_ORTH_FALLBACK,
-    INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32, set_option,
+    INFO_JACOBI_CAP, INFO_RANK, INFO_NONFINITE, INFO_BARRIER, F64, F32, BF16, F8E4M3, set_option,
+    quantize, svd_ex, pass_f8,
     OPT_JACOBI_MAX_SWEEPS, OPT_TEST_WAIT_GIVEUP,
 )

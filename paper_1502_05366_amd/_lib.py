@@ -61,6 +61,14 @@ SIGNATURES = {
     "rsvd_sketch": (c_int, [c_ptr, c_int, c_u64, c_i64, c_i64, c_ptr, c_i64, c_ptr]),
     "rsvd_philox": (c_int, [c_ptr, c_u64, c_u32, c_u32, c_u64, c_i64, c_ptr, c_ptr]),
     "rsvd_pass_workspace_bytes": (c_size, [c_int, c_int, c_i64, c_i64, c_i64]),
+    "rsvd_svd_ex": (c_int, [c_ptr, c_int, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_ptr, c_i64,
+                            c_ptr, c_ptr, c_i64, c_ptr, c_ptr, c_i64, c_ptr, c_i64, c_ptr, c_size,
+                            c_ptr, c_ptr]),
+    "rsvd_quantize": (c_int, [c_ptr, c_int, c_i64, c_i64, c_ptr, c_i64, c_ptr, c_i64, c_ptr,
+                              c_ptr]),
+    "rsvd_pass_f8_workspace_bytes": (c_size, [c_int, c_i64, c_i64, c_i64]),
+    "rsvd_pass_f8": (c_int, [c_ptr, c_int, c_i64, c_i64, c_i64, c_ptr, c_i64, c_ptr, c_ptr, c_i64,
+                             c_ptr, c_i64, c_int, c_ptr, c_size, c_ptr]),
     "rsvd_pass": (c_int, [c_ptr, c_int, c_int, c_i64, c_i64, c_i64, c_ptr, c_i64, c_ptr, c_i64,
                           c_ptr, c_i64, c_ptr, c_size, c_ptr]),
     "rsvd_orth_workspace_bytes": (c_size, [c_int, c_i64, c_i64]),

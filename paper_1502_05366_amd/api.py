@@ -17,6 +17,7 @@ from . import _lib
 F64 = 0
 F32 = 1
 BF16 = 2
+F8E4M3 = 3
 
 INFO_ORTH_FALLBACK = 1
 INFO_JACOBI_CAP = 2
@@ -481,6 +482,88 @@ def philox(seed, stream_id, batch, first, count, device="cuda"):
                          _stream(out.device))
     _check(rc, "rsvd_philox")
     return out
+
+
+def quantize(A, dtype):
+    """rsvd_quantize: the storage formats of the mixed-precision path from an
+    FP64 A.  dtype BF16 -> a torch.bfloat16 matrix (rounded to nearest even
+    from FP64); dtype F8E4M3 -> (codes, scales): uint8 E4M3 codes with a
+    leading dimension padded to 16 bytes (a view of the first n columns) and
+    the FP32 column scales, A ~ dec(codes) diag(scales)."""
+    lib = _lib.load()
+    A = _row_major(A)
+    if A.dtype != torch.float64:
+        raise RsvdError("quantize takes an FP64 matrix")
+    m, n = A.shape
+    dev = A.device
+    if dtype == BF16:
+        Aq = torch.empty((m, (n + 7) // 8 * 8), dtype=torch.bfloat16, device=dev)
+        rc = lib.rsvd_quantize(handle(dev), BF16, m, n, _ptr(A), A.stride(0), _ptr(Aq),
+                               Aq.stride(0), None, _stream(dev))
+        _check(rc, "rsvd_quantize")
+        return Aq[:, :n]
+    if dtype == F8E4M3:
+        Aq = torch.empty((m, (n + 15) // 16 * 16), dtype=torch.uint8, device=dev)
+        sc = torch.empty(n, dtype=torch.float32, device=dev)
+        rc = lib.rsvd_quantize(handle(dev), F8E4M3, m, n, _ptr(A), A.stride(0), _ptr(Aq),
+                               Aq.stride(0), _ptr(sc), _stream(dev))
+        _check(rc, "rsvd_quantize")
+        return Aq[:, :n], sc
+    raise RsvdError("quantize: dtype must be BF16 or F8E4M3")
+
+
+def svd_ex(A, k, p, q, seed, scales=None, want_Q=False):
+    """rsvd_svd_ex: the randomized SVD of `svd`, also for an FP8 A (uint8
+    E4M3 codes with FP32 column scales), optionally returning the range
+    finder's basis Q.  Returns U, S, V, info, Q (None unless want_Q)."""
+    lib = _lib.load()
+    dev = A.device
+    if A.dtype == torch.uint8:
+        if scales is None:
+            raise RsvdError("an FP8 A needs its column scales")
+        if A.stride(1) != 1 or A.stride(0) % 16 or A.data_ptr() % 16:
+            raise RsvdError("FP8 A: rows must be contiguous with a leading dimension of 16k bytes")
+        dt, ot = F8E4M3, torch.float32
+    else:
+        A = _row_major(A)
+        dt, ot = _dtype_code(A), _out_dtype(A)
+    m, n = A.shape
+    l = min(k + p, m, n)
+    wb = workspace_bytes(OP_SVD, dt, m, n, k, p, q)
+    if wb == 0:
+        raise RsvdError("invalid sizes")
+    work = _workspace(wb, dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    U = torch.empty((m, k), dtype=ot, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty((n, k), dtype=ot, device=dev)
+    Qb = torch.empty((m, l), dtype=ot, device=dev) if want_Q else None
+    rc = lib.rsvd_svd_ex(handle(dev), dt, m, n, k, p, q, seed, _ptr(A), A.stride(0),
+                         _ptr(scales) if scales is not None else None, _ptr(U), k, _ptr(S),
+                         _ptr(V), k, _ptr(Qb), l, _ptr(work), work.numel(), _ptr(info),
+                         _stream(dev))
+    _check(rc, "rsvd_svd_ex")
+    return U, S, V, info, Qb
+
+
+def pass_f8(A8, scales, X, trans=False, split=False):
+    """rsvd_pass_f8: Y = A X or A^T X for A ~ dec(A8) diag(scales), X FP32."""
+    lib = _lib.load()
+    if A8.dtype != torch.uint8 or A8.stride(1) != 1 or A8.stride(0) % 16 or A8.data_ptr() % 16:
+        raise RsvdError("A8: uint8 codes, rows contiguous, leading dimension a multiple of 16")
+    X = _row_major(X)
+    if X.dtype != torch.float32:
+        raise RsvdError("X must be FP32")
+    m, n = A8.shape
+    l = X.shape[1]
+    rows = n if trans else m
+    Y = torch.empty((rows, l), dtype=torch.float32, device=A8.device)
+    work = _workspace(lib.rsvd_pass_f8_workspace_bytes(int(trans), m, n, l), A8.device)
+    rc = lib.rsvd_pass_f8(handle(A8.device), int(trans), m, n, l, _ptr(A8), A8.stride(0),
+                          _ptr(scales), _ptr(X), X.stride(0), _ptr(Y), l, int(split), _ptr(work),
+                          work.numel(), _stream(A8.device))
+    _check(rc, "rsvd_pass_f8")
+    return Y
 
 
 def pass_(A, X, trans=False):

@@ -1,0 +1,513 @@
+// Passes over an FP8 A on the matrix cores (mixed-precision range finder with
+// A stored as FP8 E4M3 codes and one FP32 scale per column, A ~ A8 diag(s)).
+//
+//   Y = A X    = A8 (diag(s) X)          : the column scales sit on the
+//                                          reduction index, so they are folded
+//                                          into the skinny operand before it is
+//                                          quantized;
+//   Z = A^T X  = diag(s) (A8^T X)        : they are an epilogue row scale.
+// The skinny operand X' (diag(s) X, or X) is quantized per output column:
+// t_j = max_k |X'_kj| / 448, X8 = e4m3(X' / t) (nearest, ties to even), and
+// the product is (op(A8) X8) diag(t) (diag(s) in the transposed case), with
+// v_mfma_scale_f32_16x16x128_f8f6f4 on E4M3 x E4M3 (unit block scales) and
+// FP32 accumulation.  A two-term split X' ~ t X8 + t2 X8lo (X8lo the codes of
+// the residual with their own column scales t2) keeps about twice the
+// significand bits in the last projection, as the BF16 passes do.
+//
+// Work decomposition as the BF16 passes: stream-K over (tile, k-step) units,
+// deterministic partial tiles and a fix-up kernel that applies the scales;
+// BM = 128 rows, BN = 32 * CBW columns (CBW <= 9, so l = 576 takes two column
+// tiles), BK = 128 bytes (one matrix-core depth), 8 waves (4 along M x 2
+// along L), each wave 2 x CBW accumulator tiles (the 256 registers per lane of
+// two waves per SIMD hold 144 accumulators at CBW = 9).
+//
+// MFMA operand layout (16 x 16 x 128, lane l, g = l / 16, c = l % 16): lane
+// l holds 32 consecutive k of row c of the A operand and the same 32 k of
+// column c of the B operand (k = 32 g .. 32 g + 31); D: lane l element v
+// holds D[4 g + v][c].  Both operands sit in LDS with k contiguous ([row][k]
+// for A, [col][k] for Xt), rows padded to 144 bytes.  A transposed pass (A
+// stored K x M) transposes 4 x 4 byte blocks in registers on the way into
+// LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace rsvd {
+namespace {
+
+typedef int i8v __attribute__((ext_vector_type(8)));       // 32 bytes: one MFMA operand
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));  // 16 bytes
+
+constexpr int BM = 128;
+constexpr int BK = 128;            // bytes (= elements) of k per step
+constexpr int KP = BK + 16;        // padded LDS row (bytes)
+constexpr int NT = 512;
+constexpr int RB = BM / 64;        // 16-row accumulator tiles per wave (2)
+constexpr int MAX_CBW = 9;
+constexpr int SCALE_ONE = 127;     // E8M0 block scale 2^0
+
+struct F8Args {
+  const uint8_t* A; int64_t lda;
+  const uint8_t* X; int64_t ldx;      // Xt: L x K codes, row c holds column c of X'
+  float* C; int64_t ldc;
+  int64_t M, K, L;
+  int64_t nct, KI, U, G;
+  float* part;
+  const float* xs;                    // L column scales t of the skinny operand
+  const float* rs;                    // M row scales (transposed pass) or null
+  int accumulate;
+};
+
+__device__ __forceinline__ int64_t range_begin(int64_t w, int64_t U, int64_t G) {
+  return (w * U) / G;
+}
+
+__device__ __forceinline__ float out_scale(const F8Args& g, int64_t r, int64_t c) {
+  return g.rs ? g.xs[c] * g.rs[r] : g.xs[c];
+}
+
+// bytes b of the four words w[0..3], packed into one word (byte r from w[r])
+__device__ __forceinline__ uint32_t gather_byte(const uint32_t (&w)[4], int b) {
+  const int sh = 8 * b;
+  return ((w[0] >> sh) & 0xFFu) | (((w[1] >> sh) & 0xFFu) << 8) | (((w[2] >> sh) & 0xFFu) << 16) |
+         (((w[3] >> sh) & 0xFFu) << 24);
+}
+
+template <bool TRANS, int CBW>
+__global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
+  constexpr int BN = 32 * CBW;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * KP];
+  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][BN * KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave & 3;
+  const int wc = wave >> 2;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+
+  const int64_t w = blockIdx.x;
+  int64_t u = range_begin(w, g.U, g.G);
+  const int64_t uend = range_begin(w + 1, g.U, g.G);
+
+  // staging: A in 16-byte chunks (APT per thread; transposed: 4 APT words per
+  // thread, k rows KR kq .. KR kq + KR - 1 of the i quad 4 ir .. 4 ir + 3);
+  // Xt in 16-byte chunks, XPT per thread (the last one partial)
+  constexpr int APT = BM * BK / 16 / NT;
+  constexpr int XCH = BN * BK / 16;
+  constexpr int XPT = (XCH + NT - 1) / NT;
+  constexpr int IQ = BM / 4;                 // i quads of a transposed tile
+  constexpr int KR = BK / (NT / IQ);         // k rows per thread (= 4 APT)
+  static_assert(KR == 4 * APT, "transposed staging covers the tile");
+  const int ir = tid % IQ, kq = tid / IQ;
+
+  while (u < uend) {
+    const int64_t tile = u / g.KI;
+    const int64_t kb = u - tile * g.KI;
+    const int64_t ke = min(g.KI, kb + (uend - u));
+    u += ke - kb;
+    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t col0 = (tile % g.nct) * BN;
+
+    f4 acc[RB][CBW];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+      u4v ra[APT];                 // A chunks (transposed: 4 k rows of one i quad each)
+    u4v rx[XPT];
+
+    auto gload = [&](int64_t kt) {
+      const int64_t k0 = kt * BK;
+      if (!TRANS) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const int ch = tid + q * NT;
+          const int64_t gi = row0 + (ch >> 3);
+          const int64_t gk = k0 + (ch & 7) * 16;
+          const uint8_t* p = g.A + gi * g.lda + gk;
+          u4v v;
+          if (gi < g.M && gk + 16 <= g.K) {
+            v = *reinterpret_cast<const u4v*>(p);
+          } else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (gi < g.M && gk + j < g.K) wv[j >> 2] |= (uint32_t)p[j] << (8 * (j & 3));
+            v = u4v{wv[0], wv[1], wv[2], wv[3]};
+          }
+          ra[q] = v;
+        }
+      } else {
+        // word r of chunk q: k row KR kq + 4 q + r, bytes i = 4 ir .. 4 ir + 3
+        const int64_t gi = row0 + 4 * ir;
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          uint32_t wv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gk = k0 + KR * kq + 4 * q + r;
+            const uint8_t* p = g.A + gk * g.lda + gi;
+            uint32_t x = 0u;
+            if (gk < g.K && gi + 4 <= g.M) {
+              x = *reinterpret_cast<const uint32_t*>(p);
+            } else {
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (gk < g.K && gi + j < g.M) x |= (uint32_t)p[j] << (8 * j);
+            }
+            wv[r] = x;
+          }
+          ra[q] = u4v{wv[0], wv[1], wv[2], wv[3]};
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int ch = tid + q * NT;
+        u4v v = u4v{0u, 0u, 0u, 0u};
+        if (ch < XCH) {
+          const int64_t gj = col0 + (ch >> 3);
+          const int64_t gk = k0 + (ch & 7) * 16;
+          const uint8_t* p = g.X + gj * g.ldx + gk;
+          if (gj < g.L && gk + 16 <= g.K) {
+            v = *reinterpret_cast<const u4v*>(p);
+          } else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (gj < g.L && gk + j < g.K) wv[j >> 2] |= (uint32_t)p[j] << (8 * (j & 3));
+            v = u4v{wv[0], wv[1], wv[2], wv[3]};
+          }
+        }
+        rx[q] = v;
+      }
+    };
+    auto sstore = [&](int buf) {
+      if (!TRANS) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const int ch = tid + q * NT;
+          *reinterpret_cast<u4v*>(&As[buf][(ch >> 3) * KP + (ch & 7) * 16]) = ra[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const uint32_t wv[4] = {ra[q][0], ra[q][1], ra[q][2], ra[q][3]};
+          const int kc = KR * kq + 4 * q;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            *reinterpret_cast<uint32_t*>(&As[buf][(4 * ir + b) * KP + kc]) = gather_byte(wv, b);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int ch = tid + q * NT;
+        if (ch < XCH) *reinterpret_cast<u4v*>(&Xs[buf][(ch >> 3) * KP + (ch & 7) * 16]) = rx[q];
+      }
+    };
+
+    gload(kb);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t kt = kb; kt < ke; ++kt) {
+      const bool more = kt + 1 < ke;
+      if (more) gload(kt + 1);
+      i8v av[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int i = wr * 16 * RB + rb * 16 + li;
+        const u4v lo = *reinterpret_cast<const u4v*>(&As[buf][i * KP + lk * 32]);
+        const u4v hi = *reinterpret_cast<const u4v*>(&As[buf][i * KP + lk * 32 + 16]);
+        av[rb] = i8v{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                     (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      }
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) {
+        const int j = wc * 16 * CBW + cb * 16 + li;
+        const u4v lo = *reinterpret_cast<const u4v*>(&Xs[buf][j * KP + lk * 32]);
+        const u4v hi = *reinterpret_cast<const u4v*>(&Xs[buf][j * KP + lk * 32 + 16]);
+        const i8v bv = i8v{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                           (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              av[rb], bv, acc[rb][cb], 0, 0, 0, SCALE_ONE, 0, SCALE_ONE);
+      }
+      if (more) sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+
+    const bool full = (kb == 0) && (ke == g.KI);
+    if (full) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
+            if (r < g.M && c < g.L) {
+              float* cp = g.C + r * g.ldc + c;
+              const float x = acc[rb][cb][v] * out_scale(g, r, c);
+              *cp = g.accumulate ? *cp + x : x;
+            }
+          }
+    } else {
+      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      float* P = g.part + slot * (int64_t)(BM * BN);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int c = wc * 16 * CBW + cb * 16 + li;
+            P[r * BN + c] = acc[rb][cb][v];
+          }
+    }
+  }
+}
+
+// Sums the partial tiles of every split tile in workgroup order, then scales.
+constexpr int FIX_CHUNK = 1024;
+
+template <int CBW>
+__global__ __launch_bounds__(256) void f8_fixup_kernel(F8Args g) {
+  constexpr int BN = 32 * CBW;
+  const int64_t tile = blockIdx.x;
+  const int64_t ufirst = tile * g.KI;
+  const int64_t ulast = ufirst + g.KI - 1;
+  const int64_t wf = ((ufirst + 1) * g.G + g.U - 1) / g.U - 1;
+  const int64_t wl = ((ulast + 1) * g.G + g.U - 1) / g.U - 1;
+  if (wf == wl) return;
+  const int64_t row0 = (tile / g.nct) * BM;
+  const int64_t col0 = (tile % g.nct) * BN;
+  const int e0 = blockIdx.y * FIX_CHUNK;
+  const int e1 = min(e0 + FIX_CHUNK, BM * BN);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t r = row0 + e / BN;
+    const int64_t c = col0 + e % BN;
+    if (r >= g.M || c >= g.L) continue;
+    float s = 0.f;
+    for (int64_t w = wf; w <= wl; ++w) {
+      if (range_begin(w, g.U, g.G) == range_begin(w + 1, g.U, g.G)) continue;
+      const int64_t slot = 2 * w + (w == wf ? 1 : 0);
+      s += g.part[slot * (int64_t)(BM * BN) + e];
+    }
+    float* cp = g.C + r * g.ldc + c;
+    const float x = s * out_scale(g, r, c);
+    *cp = g.accumulate ? *cp + x : x;
+  }
+}
+
+template <bool TRANS, int CBW>
+hipError_t run_f8(const F8Args& g, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_f8_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t T = g.U / g.KI;
+  if (g.G != T) {
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((f8_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s, g);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <bool TRANS>
+hipError_t dispatch_f8(const F8Args& g, int cbw, hipStream_t s) {
+  switch (cbw) {
+    case 1: return run_f8<TRANS, 1>(g, s);
+    case 2: return run_f8<TRANS, 2>(g, s);
+    case 3: return run_f8<TRANS, 3>(g, s);
+    case 4: return run_f8<TRANS, 4>(g, s);
+    case 5: return run_f8<TRANS, 5>(g, s);
+    case 6: return run_f8<TRANS, 6>(g, s);
+    case 7: return run_f8<TRANS, 7>(g, s);
+    case 8: return run_f8<TRANS, 8>(g, s);
+    case 9: return run_f8<TRANS, 9>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---- the skinny operand in FP8 ---------------------------------------------
+//
+// E4M3 code of an FP32 value (nearest, ties to even, saturated to +-448; NaN
+// to 0x7F): with e the binary exponent of |y| (at least -6, the smallest
+// normal), the spacing is 2^(e-3); the rounded magnitude is re-read as
+// (exponent, significand) fields.
+__device__ __forceinline__ uint8_t e4m3_from_float(float y) {
+  if (y != y) return 0x7F;
+  const uint32_t sign = y < 0.f ? 0x80u : 0u;
+  const float a = fabsf(y);
+  uint32_t code;
+  if (a >= 448.f) {
+    code = 0x7E;
+  } else {
+    int e;
+    (void)frexpf(a, &e);                       // a = f 2^e, f in [0.5, 1)
+    const int E = max(e - 1, -6);
+    const float step = ldexpf(1.f, E - 3);
+    const float q = fminf(rintf(a / step) * step, 448.f);
+    if (q >= 0x1.0p-6f) {
+      int e2;
+      (void)frexpf(q, &e2);
+      const int E2 = e2 - 1;
+      const uint32_t mant = (uint32_t)rintf((ldexpf(q, -E2) - 1.f) * 8.f);
+      code = ((uint32_t)(E2 + 7) << 3) | mant;
+    } else {
+      code = (uint32_t)rintf(q * 512.f);
+    }
+  }
+  return (uint8_t)(code | sign);
+}
+
+__device__ __forceinline__ float e4m3_to_float(uint8_t c) {
+  const int e = (c >> 3) & 0xF, m = c & 7;
+  const float v = e == 0 ? (float)m * 0x1.0p-9f : ldexpf(1.f + (float)m * 0.125f, e - 7);
+  return (c & 0x80) ? -v : v;
+}
+
+// Element (k, c) of the operand being quantized: X'(k, c) = s_k X(k, c) (s may
+// be null), or in residual mode the part that the first term leaves,
+// X'(k, c) - t0_c dec(X8_0[c][k]).
+template <typename TX>
+__device__ __forceinline__ float xval(const TX* X, int64_t ldx, const float* s, int64_t k, int c,
+                                      const uint8_t* prev, int64_t ldp, const float* t0) {
+  float v = (float)X[k * ldx + c];
+  if (s) v *= s[k];
+  if (prev) v -= t0[c] * e4m3_to_float(prev[(int64_t)c * ldp + k]);
+  return v;
+}
+
+// tmax[c] = max_k |X'(k, c)| as FP32 bits (non-negative floats order as
+// integers); tmax zeroed beforehand.  Block: 64 columns x 4 row groups.
+template <typename TX>
+__global__ __launch_bounds__(256) void colmax_kernel(const TX* __restrict__ X, int64_t ldx,
+                                                     int64_t rows, int cols, const float* s,
+                                                     const uint8_t* prev, int64_t ldp,
+                                                     const float* t0, uint32_t* tmax) {
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;
+  if (c >= cols) return;
+  float m = 0.f;
+  for (int64_t k = blockIdx.y * 4 + rg; k < rows; k += (int64_t)gridDim.y * 4)
+    m = fmaxf(m, fabsf(xval(X, ldx, s, k, c, prev, ldp, t0)));
+  atomicMax(tmax + c, __float_as_uint(m));
+}
+
+// t[c] = tmax[c] / 448 (1 for a zero column)
+__global__ __launch_bounds__(256) void colscale_kernel(const uint32_t* tmax, int cols, float* t) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  const float m = __uint_as_float(tmax[c]);
+  t[c] = m > 0.f ? m / 448.f : 1.f;
+}
+
+// Xt[c][k] = e4m3(X'(k, c) / t[c]); padding k in [rows, ldo) zero.
+template <typename TX>
+__global__ __launch_bounds__(256) void encode_kernel(const TX* __restrict__ X, int64_t ldx,
+                                                     int64_t rows, int cols, const float* s,
+                                                     const uint8_t* prev, int64_t ldp,
+                                                     const float* t0, const float* t,
+                                                     uint8_t* __restrict__ Xt, int64_t ldo) {
+  const int64_t total = (int64_t)cols * ldo;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / ldo);
+    const int64_t k = e - (int64_t)c * ldo;
+    Xt[e] = k < rows ? e4m3_from_float(xval(X, ldx, s, k, c, prev, ldp, t0) / t[c]) : (uint8_t)0;
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <typename TX>
+hipError_t quant_x(const TX* X, int64_t ldx, int64_t rows, int cols, const float* s,
+                   const uint8_t* prev, int64_t ldp, const float* t0, uint8_t* Xt, int64_t ldo,
+                   float* t, uint32_t* tmax, hipStream_t st) {
+  const unsigned cb = (unsigned)cdiv(cols, 256);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(cb), dim3(256), 0, st, tmax, cols);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gx = (unsigned)cdiv(cols, 64);
+  int64_t gy = cdiv(rows, 256);
+  if (gy > 256) gy = 256;
+  if (gy < 1) gy = 1;
+  hipLaunchKernelGGL(colmax_kernel<TX>, dim3(gx, (unsigned)gy), dim3(256), 0, st, X, ldx, rows,
+                     cols, s, prev, ldp, t0, tmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(colscale_kernel, dim3(cb), dim3(256), 0, st, tmax, cols, t);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int64_t grid = cdiv((int64_t)cols * ldo, 256);
+  if (grid > 16384) grid = 16384;
+  hipLaunchKernelGGL(encode_kernel<TX>, dim3((unsigned)grid), dim3(256), 0, st, X, ldx, rows,
+                     cols, s, prev, ldp, t0, t, Xt, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+GemmPlan plan_gemm_f8(int64_t M, int64_t K, int64_t L, int ncu) {
+  GemmPlan p;
+  const int64_t ncb = cdiv(L, 16);
+  p.cbw = ncb <= 2 * MAX_CBW ? (int)cdiv(ncb, 2) : MAX_CBW;
+  if (p.cbw < 1) p.cbw = 1;
+  const int64_t BN = 32 * p.cbw;
+  p.nrt = cdiv(M, BM);
+  p.nct = cdiv(L, BN);
+  p.KI = cdiv(K, BK);
+  if (p.KI < 1) p.KI = 1;
+  const int64_t T = p.nrt * p.nct;
+  p.U = T * p.KI;
+  if (p.KI <= 4 && T >= ncu / 2) p.G = T;
+  else p.G = p.U < ncu ? p.U : ncu;
+  p.bm = BM;
+  p.bn = (int)BN;
+  return p;
+}
+
+size_t gemm_f8_part_bytes(const GemmPlan& p) {
+  if (p.G == p.nrt * p.nct) return 0;
+  return (size_t)(2 * p.G) * (size_t)(p.bm * p.bn) * sizeof(float);
+}
+
+hipError_t launch_gemm_f8(bool trans, const uint8_t* A, int64_t lda, const uint8_t* Xt,
+                          int64_t ldx, const float* xscale, const float* rscale, float* C,
+                          int64_t ldc, int64_t M, int64_t K, int64_t L, const GemmPlan& plan,
+                          void* part, size_t part_cap, bool accumulate, hipStream_t s) {
+  if (M <= 0 || L <= 0) return hipSuccess;
+  GemmPlan p = plan;
+  if (gemm_f8_part_bytes(p) > part_cap) p.G = p.nrt * p.nct;
+  F8Args g;
+  g.A = A; g.lda = lda; g.X = Xt; g.ldx = ldx; g.C = C; g.ldc = ldc;
+  g.M = M; g.K = K; g.L = L;
+  g.nct = p.nct; g.KI = p.KI; g.U = p.U; g.G = p.G;
+  g.part = static_cast<float*>(part);
+  g.xs = xscale;
+  g.rs = rscale;
+  g.accumulate = accumulate ? 1 : 0;
+  return trans ? dispatch_f8<true>(g, p.cbw, s) : dispatch_f8<false>(g, p.cbw, s);
+}
+
+hipError_t launch_quant_x_f8(bool x_f32, const void* X, int64_t ldx, int64_t rows, int cols,
+                             const float* rowscale, const uint8_t* prev, int64_t ldp,
+                             const float* t0, uint8_t* Xt, int64_t ldo, float* t, uint32_t* tmax,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (x_f32)
+    return quant_x(static_cast<const float*>(X), ldx, rows, cols, rowscale, prev, ldp, t0, Xt, ldo,
+                   t, tmax, s);
+  return quant_x(static_cast<const double*>(X), ldx, rows, cols, rowscale, prev, ldp, t0, Xt, ldo,
+                 t, tmax, s);
+}
+
+}  // namespace rsvd

@@ -48,6 +48,30 @@ hipError_t launch_gemm_bf16_acc(bool trans, const uint16_t* A, int64_t lda, cons
                                 int64_t ldx, float* C, int64_t ldc, int64_t M, int64_t K,
                                 int64_t L, const GemmPlan& p, void* part, size_t part_cap,
                                 hipStream_t s);
+// FP8 passes: C (FP32) = op(A8) X' with A8 FP8 E4M3 codes (lda % 16 == 0,
+// 16-byte aligned) and Xt the E4M3 codes of X' transposed (L x ldx, ldx =
+// rup(K, 16)), scaled in the epilogue by the column scales of X' (xscale, L)
+// and, for the transposed pass, by row scales (rscale, M; may be null).
+GemmPlan plan_gemm_f8(int64_t M, int64_t K, int64_t L, int ncu);
+size_t gemm_f8_part_bytes(const GemmPlan& p);
+hipError_t launch_gemm_f8(bool trans, const uint8_t* A, int64_t lda, const uint8_t* Xt,
+                          int64_t ldx, const float* xscale, const float* rscale, float* C,
+                          int64_t ldc, int64_t M, int64_t K, int64_t L, const GemmPlan& p,
+                          void* part, size_t part_cap, bool accumulate, hipStream_t s);
+// Xt[c][k] = e4m3(X'(k, c) / t[c]), t[c] = max_k |X'(k, c)| / 448, with X'(k, c)
+// = rowscale[k] X(k, c) (rowscale may be null), or with prev (the codes of a
+// first term, ld ldp, scales t0) the residual X'(k, c) - t0[c] dec(prev[c][k]).
+// tmax: cols words of scratch.
+hipError_t launch_quant_x_f8(bool x_f32, const void* X, int64_t ldx, int64_t rows, int cols,
+                             const float* rowscale, const uint8_t* prev, int64_t ldp,
+                             const float* t0, uint8_t* Xt, int64_t ldo, float* t, uint32_t* tmax,
+                             hipStream_t s);
+// Storage formats from an FP64 A: BF16 bit patterns (nearest, ties to even)
+// and FP8 E4M3 codes with per-column FP32 scales.
+hipError_t launch_quantize_bf16(const double* A, int64_t lda, int64_t m, int64_t n, uint16_t* Q,
+                                int64_t ldq, hipStream_t s);
+hipError_t launch_quantize_e4m3(const double* A, int64_t lda, int64_t m, int64_t n, uint8_t* Q,
+                                int64_t ldq, float* scale, hipStream_t s);
 // Xt[c * ldo + k] = bf16(X[k * ldi + c]) (round to nearest even), zero for k >= rows
 hipError_t launch_convert_bf16(bool in_f32, const void* X, int64_t ldi, int64_t rows, int cols,
                                uint16_t* Xt, int64_t ldo, hipStream_t s);

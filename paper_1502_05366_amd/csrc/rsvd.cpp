@@ -107,6 +107,7 @@ struct Shape {
   int k, p, q, l, lp, kp;
   bool f32;       // skinny matrices (Omega, Y, Q, Z) in FP32 (FP32 and BF16 inputs)
   bool bf16;      // A in BF16: passes on the BF16 matrix cores
+  bool f8;        // A in FP8 E4M3 with column scales: passes on the FP8 matrix cores
   int atype;      // element type of A: 0 FP64, 1 FP32, 2 BF16
   size_t dsz;
   int ops;
@@ -121,12 +122,21 @@ Shape make_shape(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) 
   s.lp = (int)rup(l, 16);
   s.kp = (int)rup(k, 16);
   s.bf16 = dtype == RSVD_BF16;
-  s.f32 = dtype == RSVD_F32 || s.bf16;
-  s.atype = dtype == RSVD_F64 ? 0 : (dtype == RSVD_F32 ? 1 : 2);
+  s.f8 = dtype == RSVD_F8E4M3;
+  s.f32 = dtype == RSVD_F32 || s.bf16 || s.f8;
+  s.atype = dtype == RSVD_F64 ? 0 : (dtype == RSVD_F32 ? 1 : (dtype == RSVD_BF16 ? 2 : 3));
   s.dsz = s.f32 ? 4 : 8;
   s.ops = ops;
   return s;
 }
+
+// FP8 A: its column scales and the buffers of the quantized skinny operand
+struct F8Bufs {
+  const float* ascale = nullptr;   // n column scales of A
+  uint8_t* xt = nullptr;           // 2 x lp x rup(max(m, n), 16) codes (two terms)
+  float* t = nullptr;              // 2 x lp column scales of the two terms
+  uint32_t* tmax = nullptr;        // lp words
+};
 
 // buffers of one orth (CholeskyQR2) call
 struct OrthBufs {
@@ -145,6 +155,7 @@ struct OrthBufs {
 struct Bufs {
   void *Om, *Y, *Q, *Z, *Zq;
   uint16_t* Xt;            // BF16 passes: the skinny operand, rounded and transposed
+  F8Bufs f8;               // FP8 passes (ascale set per call)
   double *Qh, *Rh, *Wj, *Uh, *Vh;
   OrthBufs ob;
   // ID
@@ -159,11 +170,24 @@ struct Bufs {
   double *S11t2, *S12t2, *pivn2, *Rt, *Qt, *Rtt, *Qres, *Mb;
 };
 
+// partial tiles of the products of the block orth of a rows x l matrix
+size_t orth_block_part_bytes(int64_t rows, int l) {
+  if (l <= ORTH_BLOCK) return 0;
+  const int nblk = (int)cdiv(l, ORTH_BLOCK);
+  const int bs = (int)rup(cdiv(l, nblk), 16);
+  size_t b = 0;
+  for (int c0 = bs; c0 < l; c0 += bs) {
+    const int bj = std::min(bs, l - c0);
+    b = std::max(b, gemm_part_bytes(plan_gemm(c0, rows, bj, NCU_CAP, 0), 8));
+    b = std::max(b, gemm_part_bytes(plan_gemm(rows, c0, bj, NCU_CAP, 0), 8));
+    b = std::max(b, gemm_part_bytes(plan_gemm(c0, bj, bj, NCU_CAP, 0), 8));
+  }
+  return b;
+}
+
 size_t max_part(const Shape& s) {
   const int ncu = NCU_CAP;
-  size_t b = 0;
-  // the projections of the block orth: at most every CU with a full partial tile
-  if (s.l > ORTH_BLOCK) b = (size_t)2 * ncu * 128 * 256 * sizeof(double);
+  size_t b = std::max(orth_block_part_bytes(s.m, s.l), orth_block_part_bytes(s.n, s.l));
   auto upd = [&](int64_t M, int64_t K, int64_t L) {
     if (M <= 0 || K <= 0 || L <= 0) return;
     b = std::max(b, gemm_part_bytes(plan_gemm(M, K, L, ncu, 0), 8));
@@ -173,6 +197,10 @@ size_t max_part(const Shape& s) {
   if (s.bf16) {
     b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.m, s.n, s.l, ncu)));
     b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.n, s.m, s.l, ncu)));
+  }
+  if (s.f8) {
+    b = std::max(b, gemm_f8_part_bytes(plan_gemm_f8(s.m, s.n, s.l, ncu)));
+    b = std::max(b, gemm_f8_part_bytes(plan_gemm_f8(s.n, s.m, s.l, ncu)));
   }
   upd(s.m, s.l, s.k);
   upd(s.n, s.l, s.k);
@@ -214,6 +242,11 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
   b.Z = a.take<char>((size_t)s.n * s.lp * s.dsz);
   b.Zq = a.take<char>((size_t)s.n * s.lp * s.dsz);
   if (s.bf16) b.Xt = a.take<uint16_t>((size_t)s.lp * rup(std::max(s.m, s.n), 8));
+  if (s.f8) {
+    b.f8.xt = a.take<uint8_t>((size_t)2 * s.lp * rup(std::max(s.m, s.n), 16));
+    b.f8.t = a.take<float>((size_t)2 * s.lp);
+    b.f8.tmax = a.take<uint32_t>((size_t)s.lp);
+  }
   b.ob = take_orth(a, rmax, s.lp, max_part(s));
   if (s.ops & RSVD_OP_SVD) {
     b.Qh = a.take<double>((size_t)s.n * s.lp);
@@ -258,6 +291,7 @@ struct Ctx {
   uint64_t seed;
   uint32_t orth_calls;
   rsvd_handle_s* h;
+  F8Bufs f8 = F8Bufs();
 };
 
 // CUs kept free for the block Jacobi (at most 8 workgroups) while the
@@ -386,6 +420,27 @@ hipError_t pass(Ctx& c, int atype, bool trans, int64_t m, int64_t n, int l, cons
                 int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* part,
                 size_t part_bytes, uint16_t* xt = nullptr, bool split = false) {
   const int64_t M = trans ? n : m, K = trans ? m : n;
+  if (atype == 3) {
+    // FP8 A ~ A8 diag(s): Y = A8 (diag(s) X) or Z = diag(s) (A8^T X); X' is
+    // quantized per column; with split a second term holds its residual
+    const int64_t ldt = rup(K, 16);
+    const int lp = (int)rup(l, 16);
+    const GemmPlan pg = plan_gemm_f8(M, K, l, std::min(c.ncu, NCU_CAP));
+    const float* xs = trans ? nullptr : c.f8.ascale;     // folded into X' for Y = A X
+    const float* rs = trans ? c.f8.ascale : nullptr;     // epilogue row scale for A^T X
+    uint8_t* x0 = c.f8.xt;
+    uint8_t* x1 = c.f8.xt + (size_t)lp * ldt;
+    RSVD_TRY(launch_quant_x_f8(true, X, ldx, K, l, xs, nullptr, 0, nullptr, x0, ldt, c.f8.t,
+                               c.f8.tmax, c.st));
+    RSVD_TRY(launch_gemm_f8(trans, static_cast<const uint8_t*>(A), lda, x0, ldt, c.f8.t, rs,
+                            static_cast<float*>(Y), ldy, M, K, l, pg, part, part_bytes, false,
+                            c.st));
+    if (!split) return hipSuccess;
+    RSVD_TRY(launch_quant_x_f8(true, X, ldx, K, l, xs, x0, ldt, c.f8.t, x1, ldt, c.f8.t + lp,
+                               c.f8.tmax, c.st));
+    return launch_gemm_f8(trans, static_cast<const uint8_t*>(A), lda, x1, ldt, c.f8.t + lp, rs,
+                          static_cast<float*>(Y), ldy, M, K, l, pg, part, part_bytes, true, c.st);
+  }
   if (atype != 2) {
     const GemmPlan pg = plan_gemm(M, K, l, std::min(c.ncu, NCU_CAP), 0);
     return launch_gemm(atype == 1 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l,
@@ -407,6 +462,7 @@ struct Outs {
   void* U; int64_t ldu; double* S; void* V; int64_t ldv;
   int64_t* J; double* T; int64_t ldt;
   int64_t* Jc; int64_t* Jr; double* Ucur; int64_t lduc;
+  void* Qb; int64_t ldqb;          // optional copy of the range finder's basis Q
 };
 
 hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, int64_t lda,
@@ -430,6 +486,9 @@ hipError_t run_decompose(Ctx& c, const Shape& s, const Bufs& b, const void* A, i
                   b.Xt));
   }
   RSVD_TRY(orth(c, b.ob, f32, b.Y, lp, m, l, b.Q, f32, lp, nullptr, 0));
+  if (o.Qb)
+    RSVD_TRY(hipMemcpy2DAsync(o.Qb, o.ldqb * s.dsz, b.Q, lp * s.dsz, l * s.dsz, m,
+                              hipMemcpyDeviceToDevice, c.st));
   // B^T = A^T Q; with a BF16 A the basis enters this last product in two
   // BF16 parts, so B keeps ~16 bits of Q
   RSVD_TRY(pass(c, at, true, m, n, l, A, lda, b.Q, lp, b.Z, lp, b.ob.part, b.ob.part_bytes, b.Xt,
@@ -841,6 +900,7 @@ hipError_t run_grad(Ctx& c, const Shape& s, const GradBufs& g, const double* A, 
 
 int check_common(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q) {
   if (!h) return -1;
+  if (dtype == RSVD_F8E4M3) return RSVD_ERR_UNSUPPORTED;   // needs column scales: rsvd_svd_ex
   if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return -2;
   if (m < 1) return -3;
   if (n < 1) return -4;
@@ -855,7 +915,7 @@ int finish(hipError_t e) { return e == hipSuccess ? RSVD_OK : RSVD_ERR_HIP; }
 // workspace of the orth step: R (lp x lp) and the buffers of one orth
 size_t orth_step_layout(int64_t rows, int l, void* base, OrthBufs* ob, double** Rfull) {
   const int lp = (int)rup(l, 16);
-  const size_t part = lp > ORTH_BLOCK ? (size_t)2 * NCU_CAP * 128 * 256 * sizeof(double) : 0;
+  const size_t part = orth_block_part_bytes(rows, l);
   Arena a(base);
   double* R = a.take<double>((size_t)lp * lp);
   const OrthBufs o = take_orth(a, rows, lp, part);
@@ -942,9 +1002,10 @@ const char* rsvd_status_string(int code) {
 }
 
 size_t rsvd_workspace_bytes(int ops, int dtype, int64_t m, int64_t n, int k, int p, int q) {
-  if ((dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) || m < 1 || n < 1 || k < 1 ||
-      k > std::min(m, n) || p < 0 || q < 0 || (ops & 7) == 0)
+  if ((dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16 && dtype != RSVD_F8E4M3) ||
+      m < 1 || n < 1 || k < 1 || k > std::min(m, n) || p < 0 || q < 0 || (ops & 7) == 0)
     return 0;
+  if (dtype == RSVD_F8E4M3 && ops != RSVD_OP_SVD) return 0;
   if (ops & RSVD_OP_CUR) ops |= RSVD_OP_ID;
   const Shape s = make_shape(ops, dtype, m, n, k, p, q);
   return layout(s, nullptr, nullptr);
@@ -1029,6 +1090,60 @@ int rsvd_svd(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
   std::memset(&o, 0, sizeof(o));
   o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
   return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+int rsvd_svd_ex(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
+                uint64_t seed, const void* A, int64_t lda, const float* a_col_scale, void* U,
+                int64_t ldu, double* S, void* V, int64_t ldv, void* Qb, int64_t ldqb, void* work,
+                size_t work_bytes, int32_t* info, void* stream) {
+  const bool f8 = dtype == RSVD_F8E4M3;
+  int rc = check_common(h, f8 ? RSVD_BF16 : dtype, m, n, k, p, q);
+  if (rc) return rc;
+  if (!A) return -9;
+  if (lda < n) return -10;
+  if (dtype == RSVD_BF16 && (lda % 8 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
+  if (f8 && (lda % 16 || (reinterpret_cast<uintptr_t>(A) & 15))) return -10;
+  if (f8 != (a_col_scale != nullptr)) return -11;
+  if (!U) return -12;
+  if (ldu < k) return -13;
+  if (!S) return -14;
+  if (!V) return -15;
+  if (ldv < k) return -16;
+  const Shape s = make_shape(RSVD_OP_SVD, dtype, m, n, k, p, q);
+  if (Qb && ldqb < s.l) return -18;
+  if (!work) return -19;
+  if (!info) return -21;
+  if (s.l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
+  Bufs b;
+  const size_t need = layout(s, work, &b);
+  if (work_bytes < need) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, info, seed, 0, h};
+  c.f8 = b.f8;
+  c.f8.ascale = a_col_scale;
+  Outs o;
+  std::memset(&o, 0, sizeof(o));
+  o.U = U; o.ldu = ldu; o.S = S; o.V = V; o.ldv = ldv;
+  o.Qb = Qb; o.ldqb = ldqb;
+  return finish(run_decompose(c, s, b, A, lda, o));
+}
+
+int rsvd_quantize(rsvd_handle_t h, int dtype, int64_t m, int64_t n, const double* A, int64_t lda,
+                  void* Aq, int64_t ldq, float* col_scale, void* stream) {
+  if (!h) return -1;
+  if (dtype != RSVD_BF16 && dtype != RSVD_F8E4M3) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!Aq) return -7;
+  if (ldq < n) return -8;
+  if (dtype == RSVD_F8E4M3 && !col_scale) return -9;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == RSVD_BF16)
+    return finish(launch_quantize_bf16(A, lda, m, n, static_cast<uint16_t*>(Aq), ldq, st));
+  return finish(launch_quantize_e4m3(A, lda, m, n, static_cast<uint8_t*>(Aq), ldq, col_scale, st));
 }
 
 size_t rsvd_svd_noalloc_bytes(int dtype, int64_t m, int64_t n, int k, int p, int q) {
@@ -1415,6 +1530,57 @@ size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int
            (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
   }
   return gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8) + 256;
+}
+
+size_t f8_pass_layout(int trans, int64_t m, int64_t n, int64_t l, void* base, F8Bufs* f,
+                      void** part, size_t* part_bytes) {
+  const int64_t M = trans ? n : m, K = trans ? m : n;
+  const int lp = (int)rup(l, 16);
+  const size_t pb = gemm_f8_part_bytes(plan_gemm_f8(M, K, l, NCU_CAP));
+  Arena a(base);
+  F8Bufs b;
+  b.xt = a.take<uint8_t>((size_t)2 * lp * rup(K, 16));
+  b.t = a.take<float>((size_t)2 * lp);
+  b.tmax = a.take<uint32_t>((size_t)lp);
+  void* pp = a.take<char>(pb);
+  if (f) *f = b;
+  if (part) *part = pp;
+  if (part_bytes) *part_bytes = pb;
+  return a.off;
+}
+
+size_t rsvd_pass_f8_workspace_bytes(int trans, int64_t m, int64_t n, int64_t l) {
+  if ((trans != 0 && trans != 1) || m < 1 || n < 1 || l < 1 || l > MAX_L_SVD) return 0;
+  return f8_pass_layout(trans, m, n, l, nullptr, nullptr, nullptr, nullptr);
+}
+
+int rsvd_pass_f8(rsvd_handle_t h, int trans, int64_t m, int64_t n, int64_t l, const uint8_t* A,
+                 int64_t lda, const float* a_col_scale, const float* X, int64_t ldx, float* Y,
+                 int64_t ldy, int split, void* work, size_t work_bytes, void* stream) {
+  if (!h) return -1;
+  if (trans != 0 && trans != 1) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (l < 1) return -5;
+  if (l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
+  if (!A) return -6;
+  if (lda < n || lda % 16 || (reinterpret_cast<uintptr_t>(A) & 15)) return -7;
+  if (!a_col_scale) return -8;
+  if (!X) return -9;
+  if (ldx < l) return -10;
+  if (!Y) return -11;
+  if (ldy < l) return -12;
+  if (split != 0 && split != 1) return -13;
+  if (!work) return -14;
+  if (work_bytes < rsvd_pass_f8_workspace_bytes(trans, m, n, l)) return RSVD_ERR_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_ERR_HIP;
+  Ctx c{static_cast<hipStream_t>(stream), h->ncu, nullptr, 0, 0, h};
+  void* part = nullptr;
+  size_t pb = 0;
+  f8_pass_layout(trans, m, n, l, work, &c.f8, &part, &pb);
+  c.f8.ascale = a_col_scale;
+  return finish(pass(c, 3, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy, part, pb, nullptr,
+                     split == 1));
 }
 
 int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64_t l,

@@ -58,8 +58,8 @@ def svd_call(lib, **kw):
     (dict(k=0), -5), (dict(k=81), -5), (dict(p=-1), -6), (dict(q=-2), -7),
     (dict(A=NULLP), -9), (dict(lda=79), -10), (dict(U=NULLP), -11), (dict(ldu=9), -12),
     (dict(S=NULLP), -13), (dict(V=NULLP), -14), (dict(ldv=3), -15), (dict(work=NULLP), -16),
-    (dict(info=NULLP), -18), (dict(wb=16), 2), (dict(k=250, p=10, m=400, n=300, lda=300, ldu=250,
-                                                     ldv=250), 3),
+    (dict(info=NULLP), -18), (dict(wb=16), 2), (dict(k=580, p=10, m=1000, n=800, lda=800, ldu=580,
+                                                     ldv=580), 3),
 ])
 def test_svd_argument_codes(lib, kw, code):
     assert svd_call(lib, **kw) == code
@@ -74,6 +74,35 @@ def test_id_cur_argument_codes(lib):
                         PTR, NULLP) == -14
     assert lib.rsvd_cur(FAKE, 1, 50, 40, 5, 5, 1, 1, PTR, 40, PTR, PTR, PTR, 5, PTR, 8,
                         PTR, NULLP) == 2
+
+
+def test_mixed_precision_argument_codes(lib):
+    # rsvd_svd_ex: FP8 needs its column scales (and only FP8 takes them), an
+    # FP8 A needs lda % 16 == 0; the basis output needs ldqb >= l
+    def ex(dtype=3, lda=96, scale=PTR, Qb=NULLP, ldqb=0, m=100, n=80, k=10, p=5):
+        return lib.rsvd_svd_ex(FAKE, dtype, m, n, k, p, 1, 1, PTR, lda, scale, PTR, k, PTR, PTR, k,
+                               Qb, ldqb, PTR, 1 << 40, PTR, NULLP)
+    assert ex(scale=NULLP) == -11
+    assert ex(dtype=0, lda=80) == -11
+    assert ex(lda=88) == -10
+    assert ex(Qb=PTR, ldqb=14) == -18
+    assert ex(k=580, p=10, m=1000, n=800, lda=800) == 3
+    # F8E4M3 is refused by the entry points that take no scales
+    assert svd_call(lib, dtype=3) == 3
+    assert lib.rsvd_workspace_bytes(1, 3, 100, 80, 10, 5, 1) > 0
+    assert lib.rsvd_workspace_bytes(2, 3, 100, 80, 10, 5, 1) == 0
+    # rsvd_quantize: BF16 or E4M3 from FP64; E4M3 needs the scale output
+    assert lib.rsvd_quantize(FAKE, 0, 10, 10, PTR, 10, PTR, 10, PTR, NULLP) == -2
+    assert lib.rsvd_quantize(FAKE, 3, 10, 10, PTR, 10, PTR, 10, NULLP, NULLP) == -9
+    assert lib.rsvd_quantize(FAKE, 2, 10, 10, PTR, 9, PTR, 10, NULLP, NULLP) == -6
+    # rsvd_pass_f8: lda a multiple of 16, scales required, l <= 576
+    assert lib.rsvd_pass_f8(FAKE, 0, 100, 80, 10, PTR, 88, PTR, PTR, 10, PTR, 10, 0, PTR, 1 << 40,
+                            NULLP) == -7
+    assert lib.rsvd_pass_f8(FAKE, 0, 100, 80, 10, PTR, 96, NULLP, PTR, 10, PTR, 10, 0, PTR,
+                            1 << 40, NULLP) == -8
+    assert lib.rsvd_pass_f8(FAKE, 0, 1000, 800, 600, PTR, 800, PTR, PTR, 600, PTR, 600, 0, PTR,
+                            1 << 40, NULLP) == 3
+    assert lib.rsvd_pass_f8_workspace_bytes(1, 100, 80, 10) > 0
 
 
 def test_status_strings(lib):
@@ -99,8 +128,11 @@ def test_workspace_query(lib):
 def test_step_workspace_queries(lib):
     assert lib.rsvd_orth_workspace_bytes(0, 1000, 30) > 0
     assert lib.rsvd_orth_workspace_bytes(0, 10, 30) == 0
-    assert lib.rsvd_orth_workspace_bytes(0, 1000, 300) == 0
+    assert lib.rsvd_orth_workspace_bytes(0, 1000, 300) > 0       # column blocks above 256
+    assert lib.rsvd_orth_workspace_bytes(0, 1000, 600) == 0      # above 576
     assert lib.rsvd_small_svd_workspace_bytes(220) >= 2 * 220 * 220 * 8
+    assert lib.rsvd_small_svd_workspace_bytes(576) >= 2 * 576 * 576 * 8
+    assert lib.rsvd_small_svd_workspace_bytes(577) == 0
     assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 200) > 0
     assert lib.rsvd_cpqr_workspace_bytes(220, 10000, 300) == 0
     assert lib.rsvd_pass_workspace_bytes(0, 0, 20000, 10000, 220) > 0
