@@ -68,30 +68,126 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, k, p, q, seed, budget_s=20.0):
-    """The FP64 oracle (RSVD + ID + CUR) on the first rows of the same A."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, k, p, q, seed, single_run_s=20.0):
+    """The FP64 oracle (RSVD + ID + CUR) on the same 20000 x 10000 A and seed
+    as the GPU step, on all host threads: median of 3 runs, or one run when a
+    run takes longer than single_run_s.  Plus the oracle's RSVD on the
+    2000 x 1000 plain-RSVD workload on one thread (median of 3)."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import rsvd as O
+    from paper_1502_05366_amd import workloads as W
 
     m, n = A.shape
-    ms = 2000
-    t = 0.0
+    times = []
     while True:
-        As = np.ascontiguousarray(A[:ms])
         t0 = time.perf_counter()
-        O.rsvd(As, k, p, q, seed)
-        O.cur(As, k, p, q, seed)
-        t = time.perf_counter() - t0
-        if t > budget_s / 3 or ms >= m:
+        O.rsvd(A, k, p, q, seed)
+        O.cur(A, k, p, q, seed)
+        times.append(time.perf_counter() - t0)
+        if len(times) == 3 or times[0] > single_run_s:
             break
-        ms = min(m, int(ms * min(4.0, max(1.5, budget_s / 3 / max(t, 1e-3)))))
+    t = float(np.median(times))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    f = alg_flops(ms, n, k, p, q)
+    f = alg_flops(m, n, k, p, q)
+    A1, _ = W.c1_matrix()
+    t1 = []
+    with threadpool_limits(1):
+        for _ in range(3):
+            t0 = time.perf_counter()
+            O.rsvd(A1, 20, 10, 1, 0x5EED0000)
+            t1.append(time.perf_counter() - t0)
+    t1m = float(np.median(t1))
     return {"value": round(f / t / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": "oracle RSVD+ID+CUR on the first %d of %d rows (%d x %d), k=%d p=%d q=%d, "
-                      "%.1f s; GFLOP/s with the same RSVD flop count" % (ms, m, ms, n, k, p, q, t)}
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "oracle RSVD+ID+CUR on the full %d x %d matrix of the GPU step (same A and "
+                      "seed), k=%d p=%d q=%d; median of %d run(s): %s s; GFLOP/s with the same "
+                      "RSVD flop count" % (m, n, k, p, q, len(times),
+                                           ", ".join("%.1f" % x for x in times)),
+            "c1_one_thread": {"ms": round(1e3 * t1m, 1),
+                              "value_gflops": round(alg_flops(2000, 1000, 20, 10, 1) / t1m / 1e9,
+                                                    3),
+                              "runs_ms": [round(1e3 * x, 1) for x in t1],
+                              "sample": "oracle RSVD on the 2000 x 1000 plain-RSVD matrix "
+                                        "(sigma_j = 10^(-j/10)), k=20 p=10 q=1, one thread, "
+                                        "median of 3"}}
+
+
+def c1_graph_step(lib, h, args, stream, sp, P, e0, e1):
+    """The plain-RSVD workload (2000 x 1000 FP64, sigma_j = 10^(-j/10), k = 20,
+    p = 10, q = 1): one rsvd_svd call captured into a graph and replayed; the
+    per-call wall time of the replays and the sigma error against the oracle."""
+    import numpy as np
+    import torch
+    from oracle import rsvd as O
+    from paper_1502_05366_amd import api, workloads as W
+
+    dev = torch.device("cuda:0")
+    A_np, _ = W.c1_matrix()
+    A = torch.from_numpy(A_np).to(dev)
+    m, n = A.shape
+    k, p, q, seed = 20, 10, 1, 0x5EED0000
+    wb = lib.rsvd_workspace_bytes(api.OP_SVD, api.F64, m, n, k, p, q)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    U = torch.empty((m, k), dtype=torch.float64, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty((n, k), dtype=torch.float64, device=dev)
+
+    def call(st):
+        rc = lib.rsvd_svd(h, api.F64, m, n, k, p, q, seed, P(A), n, P(U), k, P(S), P(V), k,
+                          P(work), wb, P(info), ctypes.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise RuntimeError("rsvd_svd returned %d" % rc)
+
+    call(stream)
+    torch.cuda.synchronize()
+    S_eager = S.cpu().numpy().copy()
+    # eager timing
+    e0.record(stream)
+    for _ in range(50):
+        call(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / 50
+    # capture on a side stream, replay on it
+    gs = torch.cuda.Stream(device=dev)
+    gs.wait_stream(stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(g, stream=gs):
+            call(gs)
+    torch.cuda.synchronize()
+    ok = True
+    for _ in range(3):
+        S.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        ok = ok and np.array_equal(S.cpu().numpy(), S_eager)
+    reps = 200
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) / reps * 1e3
+    _, So, _ = O.rsvd(A_np, k, p, q, seed)
+    rel = float(np.max(np.abs(S_eager - So) / So))
+    return {"workload": "plain RSVD, FP64 A 2000x1000, sigma_j=10^(-j/10), k=20 p=10 q=1",
+            "graph_replay_wall_ms": round(wall_ms, 4), "eager_event_ms": round(eager_ms, 4),
+            "value_gflops": round(alg_flops(m, n, k, p, q) / (wall_ms * 1e-3) / 1e9, 1),
+            "replays_match_eager": bool(ok), "sigma_rel_err_vs_oracle": rel,
+            "info": [int(x) for x in info.cpu().numpy()]}
 
 
 def id_left_flops(m, n, k, p, q):
@@ -415,6 +511,83 @@ def lowp_step(lib, h, A, m, n, k, p, q, seed, l, args, stream, sp, P, e0, e1, bf
     return out
 
 
+def mhbm_step(lib, h, A, args, stream, sp, P, e0, e1):
+    """The HBM-bound supplement: the 20000 x 10000 matrix with k = 20, p = 10,
+    q = 1 (l = 30, 7.5 flop per byte of FP64 A: below the ridge points), A in
+    FP64 and in FP32.  One rsvd_svd call per step, and one pass over A in each
+    direction; the pass rate is the bytes of A per pass over the pass time."""
+    import torch
+    from paper_1502_05366_amd import api
+
+    dev = A.device
+    m, n = A.shape
+    k, p, q, seed = 20, 10, 1, 0x5EED0001
+    l = min(k + p, m, n)
+    out = {"workload": "C2's A (20000x10000, sigma_j=1/j + noise) with k=20 p=10 q=1 (l=30)",
+           "k": k, "p": p, "q": q, "l": l}
+    for name, dt, tt in (("fp64", api.F64, torch.float64), ("fp32", api.F32, torch.float32)):
+        Ax = A if tt == torch.float64 else A.to(tt)
+        wb = lib.rsvd_workspace_bytes(api.OP_SVD, dt, m, n, k, p, q)
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+        info = torch.zeros(2, dtype=torch.int32, device=dev)
+        U = torch.empty((m, k), dtype=tt, device=dev)
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        V = torch.empty((n, k), dtype=tt, device=dev)
+
+        def step():
+            rc = lib.rsvd_svd(h, dt, m, n, k, p, q, seed, P(Ax), n, P(U), k, P(S), P(V), k,
+                              P(work), wb, P(info), sp)
+            if rc != 0:
+                raise RuntimeError("rsvd_svd returned %d" % rc)
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        X = torch.randn((n, l), dtype=tt, device=dev)
+        Xm = torch.randn((m, l), dtype=tt, device=dev)
+        Y = torch.empty((m, l), dtype=tt, device=dev)
+        Z = torch.empty((n, l), dtype=tt, device=dev)
+        pw = max(lib.rsvd_pass_workspace_bytes(dt, 0, m, n, l),
+                 lib.rsvd_pass_workspace_bytes(dt, 1, m, n, l))
+        pwork = torch.empty(max(pw, 1), dtype=torch.uint8, device=dev)
+        pass_ms = {}
+        for trans, Xt, Yt, key in ((0, X, Y, "A_X"), (1, Xm, Z, "At_X")):
+            for _ in range(3):
+                lib.rsvd_pass(h, dt, trans, m, n, l, P(Ax), n, P(Xt), l, P(Yt), l, P(pwork), pw,
+                              sp)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.pass_reps):
+                lib.rsvd_pass(h, dt, trans, m, n, l, P(Ax), n, P(Xt), l, P(Yt), l, P(pwork), pw,
+                              sp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pass_ms[key] = e0.elapsed_time(e1) / args.pass_reps
+        esz = 8 if tt == torch.float64 else 4
+        gbs = {kk: esz * m * n / (v * 1e-3) / 1e9 for kk, v in pass_ms.items()}
+        t_pass = 0.5 * (pass_ms["A_X"] + pass_ms["At_X"])
+        a = esz * m * n / (t_pass * 1e-3) / 1e9
+        st = info.cpu().numpy()
+        out[name] = {"ms_per_step": round(ms, 4),
+                     "value_gflops": round(alg_flops(m, n, k, p, q) / (ms * 1e-3) / 1e9, 1),
+                     "info": [int(st[0]), int(st[1])],
+                     "pass_ms": {kk: round(v, 4) for kk, v in pass_ms.items()},
+                     "pass_roofline": {"bound": "hbm", "achieved": round(a, 1),
+                                       "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                       "frac": round(a / PEAK_HBM_GBS, 4),
+                                       "per_direction_GBs": {kk: round(v, 1)
+                                                             for kk, v in gbs.items()}}}
+        log("mhbm %s: %.3f ms/step, passes %s" % (name, ms, out[name]["pass_ms"]))
+        del work, U, V, X, Xm, Y, Z, pwork
+    return out
+
+
 def c3_step(lib, h, args, stream, sp, P, e0, e1):
     """The mixed-precision workload: A 65536 x 32768, sigma_j = j^-1.5
     (Kronecker-Haar factors), k = 512, p = 64, q = 2, one rsvd_svd_ex call
@@ -719,12 +892,14 @@ def main():
         r["speedup_vs_fp64"] = round(ms / r["ms_per_step"], 3)
         lowp[key] = r
 
-    idl = qbr = grd = bat = c3r = None
+    idl = qbr = grd = bat = c3r = mh = c1g = None
     if not args.no_extras:
         idl = id_left_step(lib, h, A, m, n, k, p, q, seed, args, stream, sp, P, e0, e1)
         qbr = qb_step(lib, h, A, m, n, seed, args, stream, sp, P, e0, e1)
         grd = grad_step(lib, h, args, stream, sp, P, e0, e1)
         bat = batch_step(lib, args, stream, e0, e1)
+        mh = mhbm_step(lib, h, A, args, stream, sp, P, e0, e1)
+        c1g = c1_graph_step(lib, h, args, stream, sp, P, e0, e1)
         c3r = c3_step(lib, h, args, stream, sp, P, e0, e1)
 
     out = {
@@ -761,6 +936,8 @@ def main():
         out["qb"] = qbr
         out["grad"] = grd
         out["batch"] = bat
+        out["mhbm"] = mh
+        out["c1_graph"] = c1g
         out["c3"] = c3r
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -36,8 +36,18 @@
  * - Numerical status (asynchronous) goes to the device words info[0..1]:
  *   info[0] is a bit set of RSVD_INFO_*, info[1] the numerical rank found by
  *   the pivoted QR when RSVD_INFO_RANK is set.  Each call resets both words.
- * - l = min(k + p, m, n) is the sample size; this build supports l <= 256 and
- *   k <= l (l <= 80 in a batch).  p >= 0, q >= 0, 1 <= k <= min(m, n).
+ * - l = min(k + p, m, n) is the sample size: l <= 576 for the randomized SVD
+ *   and its steps (orth works on column blocks of at most 256 above 256),
+ *   l <= 256 when the ID or CUR is requested, for the derivative and the
+ *   blocked QB, l <= 80 in a batch.  p >= 0, q >= 0, 1 <= k <= min(m, n).
+ * - Co-residency: the pivoted QR (ID, CUR) and the block Jacobi (l > 64) run
+ *   as ordinary launches of up to one workgroup per compute unit whose
+ *   workgroups wait for each other with bounded spins.  They assume the
+ *   call's kernels are not starved of compute units by concurrent kernels on
+ *   other streams; if a wait gives up, the call reports RSVD_INFO_BARRIER and
+ *   its outputs are invalid.  rsvd_decompose with both the SVD and the ID or
+ *   CUR runs the Jacobi beside the pivoted QRs and keeps 8 compute units for
+ *   it, so it needs the whole device.
  * - The Gaussian test matrix is drawn from Philox4x32-10 (key = seed) with
  *   Box-Muller normals: sketch entry (i, j) is normal number j*n + i of
  *   stream 0 (see rsvd_sketch).
@@ -214,7 +224,7 @@ int rsvd_qb(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int b, int M, int 
 /* Reverse-mode derivative of the rank-k randomized SVD with the Gaussian sketch
  * held fixed (FP64 only; q <= 8).  The forward map is the one of rsvd_svd
  * (Alg. 5, re-orthonormalization after every product as in Sec. 3.2; the small
- * SVD as in Sec. 3.2 from the QR of B^T): the call recomputes it, keeping its
+ * SVD from the QR of B^T as in Sec. 3.4): the call recomputes it, keeping its
  * bases and triangular factors in the workspace, so a caller stores only A.
  *
  * Cotangents (device pointers, each may be NULL for zero): dU (m x k, lddu),
@@ -295,7 +305,10 @@ int rsvd_cur(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int
  * Output groups may be NULL to skip them: (U, S, V) for the SVD, (J, T) for
  * the ID, (Jr, Ucur) for the CUR (the CUR needs the ID, which is then computed
  * into the workspace when J/T are NULL; Jc = J[0..k)).  The workspace query
- * must be made with the same set of ops. */
+ * must be made with the same set of ops.  With the SVD and the ID / CUR both
+ * requested, the Jacobi runs on the handle's second stream beside the pivoted
+ * QRs, and the two wait-across-workgroup kernels together hold every compute
+ * unit: no other work may run on the device meanwhile (see co-residency). */
 int rsvd_decompose(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p, int q,
                    uint64_t seed, const void* A, int64_t lda, void* U, int64_t ldu,
                    double* S, void* V, int64_t ldv, int64_t* J, double* T, int64_t ldt,

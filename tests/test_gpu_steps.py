@@ -46,7 +46,13 @@ def test_sketch_matches_oracle(R, n, l, ldo):
     seed = 0x5EED0001
     om = R.sketch(n, l, seed, torch.float64, ldo=ldo).cpu().numpy()
     ref = OP.sketch(seed, n, l)
-    assert np.abs(om[:, :l] - ref).max() <= 64 * EPS * max(1.0, np.abs(ref).max())
+    # the same Philox words and Box-Muller formula on both sides; only the
+    # device and host libm log / sqrt / sin / cos differ, each by at most an
+    # ulp or two: per entry within 4 ulps of the oracle's value (measured: at
+    # most 3, with 96% of the entries bit-identical)
+    ulps = np.abs(om[:, :l] - ref) / np.spacing(np.abs(ref))
+    assert ulps.max() <= 4.0
+    assert np.mean(om[:, :l] == ref) >= 0.9
     assert np.all(om[:, l:] == 0.0)
     om32 = R.sketch(n, l, seed, torch.float32).cpu().numpy()
     # FP32 sketch = FP64 normals rounded to FP32 (a 1-ulp flip where the two
