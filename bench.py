@@ -744,6 +744,9 @@ def main():
                          "(for kernel traces of rsvd_svd_grad)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched section and print its JSON object")
+    ap.add_argument("--mhbm-only", action="store_true",
+                    help="run only the HBM-bound supplement (l = 30 on the 20000 x 10000 matrix) "
+                         "and print its JSON object")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the mixed-precision section (65536 x 32768, l = 576) and "
                          "print its JSON object")
@@ -799,6 +802,14 @@ def main():
     log("generated in %.1f s" % (time.perf_counter() - t0))
 
     h = api.handle(dev)
+    if args.mhbm_only:
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        r = mhbm_step(lib, h, A, args, stream, ctypes.c_void_p(stream.cuda_stream), P, e0, e1)
+        print(json.dumps({"mhbm": r}), flush=True)
+        return
     ops = api.OP_SVD | api.OP_ID | api.OP_CUR
     wb = lib.rsvd_workspace_bytes(ops, api.F64, m, n, k, p, q)
     work = torch.empty(wb, dtype=torch.uint8, device=dev)

@@ -36,6 +36,16 @@ hipError_t launch_gemm(GemmTypes ty, bool trans, const void* A, int64_t lda, con
                        int64_t ldx, void* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
                        const GemmPlan& p, void* part, size_t part_cap, hipStream_t s);
 
+// Narrow passes (L <= 64) in FP32 / FP64, A streamed from HBM straight into
+// the matrix-core operands: usable when lda is a multiple of 16 bytes' worth
+// of elements and A is 16-byte aligned; work: narrow_work_bytes bytes
+// (256-byte aligned).  C = op(A) X in A's type.
+bool narrow_applies(bool f32, int64_t lda, const void* A, int64_t L);
+size_t narrow_work_bytes(bool f32, bool trans, int64_t M, int64_t K, int64_t L, int ncu);
+hipError_t launch_narrow(bool f32, bool trans, const void* A, int64_t lda, const void* X,
+                         int64_t ldx, void* C, int64_t ldc, int64_t M, int64_t K, int64_t L,
+                         int ncu, void* work, size_t work_bytes, hipStream_t s);
+
 // BF16 passes: C (FP32) = op(A) X with A in BF16 (lda % 8 == 0, 16-byte
 // aligned) and Xt = X^T in BF16 (L x ldx, ldx = rup(K, 8)); L <= 256.
 GemmPlan plan_gemm_bf16(int64_t M, int64_t K, int64_t L, int ncu);

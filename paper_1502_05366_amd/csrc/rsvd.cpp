@@ -194,6 +194,10 @@ size_t max_part(const Shape& s) {
   };
   upd(s.m, s.n, s.l);
   upd(s.n, s.m, s.l);
+  if (!s.bf16 && !s.f8) {
+    b = std::max(b, narrow_work_bytes(s.f32, false, s.m, s.n, s.l, ncu));
+    b = std::max(b, narrow_work_bytes(s.f32, true, s.n, s.m, s.l, ncu));
+  }
   if (s.bf16) {
     b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.m, s.n, s.l, ncu)));
     b = std::max(b, gemm_bf16_part_bytes(plan_gemm_bf16(s.n, s.m, s.l, ncu)));
@@ -441,6 +445,10 @@ hipError_t pass(Ctx& c, int atype, bool trans, int64_t m, int64_t n, int l, cons
     return launch_gemm_f8(trans, static_cast<const uint8_t*>(A), lda, x1, ldt, c.f8.t + lp, rs,
                           static_cast<float*>(Y), ldy, M, K, l, pg, part, part_bytes, true, c.st);
   }
+  if (atype < 2 && narrow_applies(atype == 1, lda, A, l) &&
+      narrow_work_bytes(atype == 1, trans, M, K, l, std::min(c.ncu, NCU_CAP)) <= part_bytes)
+    return launch_narrow(atype == 1, trans, A, lda, X, ldx, Y, ldy, M, K, l,
+                         std::min(c.ncu, NCU_CAP), part, part_bytes, c.st);
   if (atype != 2) {
     const GemmPlan pg = plan_gemm(M, K, l, std::min(c.ncu, NCU_CAP), 0);
     return launch_gemm(atype == 1 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l,
@@ -1529,7 +1537,8 @@ size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int
     return gemm_bf16_part_bytes(plan_gemm_bf16(M, K, l, NCU_CAP)) + 256 +
            (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
   }
-  return gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8) + 256;
+  return std::max(gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8),
+                  narrow_work_bytes(dtype == RSVD_F32, trans != 0, M, K, l, NCU_CAP)) + 256;
 }
 
 size_t f8_pass_layout(int trans, int64_t m, int64_t n, int64_t l, void* base, F8Bufs* f,

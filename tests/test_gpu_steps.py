@@ -63,7 +63,8 @@ def test_sketch_matches_oracle(R, n, l, ldo):
 # -------------------------------------------------------------- passes ----
 
 @pytest.mark.parametrize("m,n,l", [(333, 517, 30), (1000, 2000, 220), (130, 70, 1), (16, 16, 16),
-                                   (2047, 129, 257 - 1)])
+                                   (2047, 129, 257 - 1), (2048, 1024, 64), (1001, 3000, 33),
+                                   (5000, 200, 48), (300, 20000, 17), (20000, 400, 30)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_pass_exact_on_integers(R, m, n, l, dtype):
     A = W.integer_matrix(m, n, seed=m + n)
@@ -76,7 +77,8 @@ def test_pass_exact_on_integers(R, m, n, l, dtype):
     assert np.array_equal(Z.astype(np.float64), A.T @ Xm)
 
 
-@pytest.mark.parametrize("m,n,l", [(2000, 1000, 30), (3001, 1777, 220)])
+@pytest.mark.parametrize("m,n,l", [(2000, 1000, 30), (3001, 1777, 220), (4000, 3000, 64),
+                                   (3001, 1776, 40)])
 def test_pass_random_vs_oracle(R, m, n, l):
     g = np.random.default_rng(1)
     A = g.standard_normal((m, n))
