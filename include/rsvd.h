@@ -260,8 +260,10 @@ int rsvd_svd_grad(rsvd_handle_t h, int dtype, int64_t m, int64_t n, int k, int p
  * Philox stream 0 with batch index i under the call's seed.  Limits:
  * l_i = min(k_i + p, m_i, n_i) <= 80.  Products on the FP32 matrix cores
  * (FP32 accumulation); orth (CholeskyQR2), the Jacobi SVD and U, V in FP64.
- * The orth does not replace dependent columns: a Cholesky pivot below
- * 1e-13 G_jj gives a unit row of R and sets info bit 1.
+ * A column that the orth finds dependent (Cholesky pivot below 1e-13 G_jj)
+ * is replaced by a fresh Gaussian column (Philox stream 7) before the second
+ * CholeskyQR pass, as in rsvd_orth, and sets info bit 1; a non-finite pivot
+ * sets info bit 8.
  *
  * rsvd_batch_create: host arrays m, n (int64) and k (int32) of `count`
  *   entries; the plan keeps its own copy.  Codes: -i for an invalid i-th

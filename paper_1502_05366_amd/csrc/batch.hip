@@ -20,8 +20,11 @@
 //    rows split over the waves), Cholesky (one barrier per step) and the
 //    inverse of R (four lanes per column) in LDS, Q = Y R^{-1} on FP64 MFMA;
 //    a pivot below 1e-13 G_jj marks a dependent column (unit row of R, info
-//    bit 1); the second pass is skipped when the first already left
-//    ||Q^T Q - I||_F <= 2^-30, far below the FP32 rounding of the bases;
+//    bit 1), which after the first pass is replaced by a fresh Gaussian
+//    column (Philox stream 7) for the second pass to orthonormalize, as the
+//    single-matrix orth does; a non-finite pivot sets info bit 8; the second
+//    pass is skipped when the first already left ||Q^T Q - I||_F <= 2^-30,
+//    far below the FP32 rounding of the bases;
 //  * the Jacobi SVD of the l x l factor in LDS (the rotations of the
 //    single-matrix small SVD, one column pair per 16 lanes);
 //  * U and V on FP64 MFMA, written in FP32.
@@ -67,6 +70,9 @@ struct alignas(16) BatchLds {
   } u;
   double sig[BLMAX];
   double dgn[BLMAX];
+  int depc[BLMAX];     // columns found dependent by the last Cholesky
+  int ndep;            // how many
+  int nonfinite;       // a non-finite pivot was met (this matrix)
   int flag;
   int item;
 };
@@ -413,13 +419,19 @@ __device__ __noinline__ void b_chol(int l, int lp) {
     R[r * SL + c] = (r == c && r >= l) ? 1.0 : 0.0;
   }
   for (int i = tid; i < l; i += BNT) g_lds.dgn[i] = G[i * SL + i];
+  if (tid == 0) g_lds.ndep = 0;
   __syncthreads();
   for (int j = 0; j < l; ++j) {
     const double d = G[j * SL + j];
     const bool dep = !(d > ETA_DEP * g_lds.dgn[j]);
+    if (tid == 0) g_lds.depc[j] = dep ? 1 : 0;
     if (dep) {
       for (int c = j + tid; c < l; c += BNT) R[j * SL + c] = (c == j) ? 1.0 : 0.0;
-      if (tid == 0) g_lds.flag = 1;
+      if (tid == 0) {
+        g_lds.flag = 1;
+        ++g_lds.ndep;
+        if (!(fabs(d) <= 1.7976931348623157e308)) g_lds.nonfinite = 1;
+      }
     } else {
       const double sq = sqrt(d);
       const double inv = 1.0 / d;
@@ -550,13 +562,44 @@ __device__ void b_copy(const double* T, int64_t rows, int lp, TO* Q) {
 // so the orthogonality of the stored basis is set by its own rounding.
 constexpr double ORTH_SKIP2 = 0x1.0p-60;   // (2^-30)^2
 
+// The columns of T (rows x lp) found dependent by the first Cholesky get
+// N(0, 1/rows) entries: normal number j*rows + i of Philox stream 7 with
+// batch word (orth call << 20 | matrix index), under the call's seed.
+__device__ __noinline__ void b_replace(double* T, int64_t rows, int l, int lp, uint32_t k0,
+                                       uint32_t k1, uint32_t word) {
+  const double scale = 1.0 / sqrt((double)rows);
+  for (int j = 0; j < l; ++j) {
+    if (!g_lds.depc[j]) continue;
+    for (int64_t i2 = threadIdx.x; 2 * i2 < rows; i2 += BNT) {
+      const uint64_t t = (uint64_t)j * (uint64_t)rows + 2 * (uint64_t)i2;   // even number
+      // normals t and t + 1 come from one counter when t is even; rows may be
+      // odd, so each value is computed from its own pair
+      double z[2];
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t th = t + h;
+        const uint64_t pr = th >> 1;
+        const Words w = philox10((uint32_t)pr, (uint32_t)(pr >> 32), 7u, word, k0, k1);
+        double z0, z1;
+        box_muller(w, z0, z1);
+        z[h] = (th & 1) ? z1 : z0;
+      }
+      const int64_t i = 2 * i2;
+      T[i * lp + j] = z[0] * scale;
+      if (i + 1 < rows) T[(i + 1) * lp + j] = z[1] * scale;
+    }
+  }
+  __syncthreads();
+}
+
 template <int NB, typename TI, typename TO>
-__device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q) {
+__device__ void b_orth(const TI* In, int64_t rows, int l, double* T, TO* Q, uint32_t k0,
+                       uint32_t k1, uint32_t word) {
   constexpr int lp = 16 * NB;
   b_gram<NB>(In, rows);
   b_chol(l, lp);
   b_rinv(l, lp);
   b_apply<NB>(In, rows, lp, T, (int64_t)lp);
+  if (g_lds.ndep > 0) b_replace(T, rows, l, lp, k0, k1, word);
   b_gram<NB>(T, rows);
   if (b_gram_offset2(l) <= ORTH_SKIP2) {
     b_copy(T, rows, lp, Q);
@@ -634,18 +677,22 @@ __device__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A, co
   constexpr int lp = 16 * NB;
   const int64_t m = d.m, n = d.n;
   const int l = d.l, k = d.k;
+  // batch word of the replacement columns: orth call (high bits), matrix
+  const uint32_t mw = (uint32_t)d.index & 0xFFFFFu;
+  uint32_t call = 0;
   b_pass_n<NB>(A, d.lda, m, n, Om, Y);
   for (int j = 0; j < g.q; ++j) {
-    b_orth<NB>(Y, m, l, T, Q);
+    b_orth<NB>(Y, m, l, T, Q, g.k0, g.k1, (call++ << 20) | mw);
     b_pass_t<NB>(A, d.lda, m, n, Q, Z);
-    b_orth<NB>(Z, n, l, T, Zq);
+    b_orth<NB>(Z, n, l, T, Zq, g.k0, g.k1, (call++ << 20) | mw);
     b_pass_n<NB>(A, d.lda, m, n, Zq, Y);
   }
-  b_orth<NB>(Y, m, l, T, Q);
+  b_orth<NB>(Y, m, l, T, Q, g.k0, g.k1, (call++ << 20) | mw);
   b_pass_t<NB>(A, d.lda, m, n, Q, Z);          // B^T
-  b_orth<NB>(Z, n, l, T, Qh);
+  b_orth<NB>(Z, n, l, T, Qh, g.k0, g.k1, (call++ << 20) | mw);
   b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
   if (threadIdx.x == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
+  if (threadIdx.x == 0 && g_lds.nonfinite) info_or(g.info, INFO_NONFINITE);
   b_jacobi<NB>(l, k, g.S + d.s_off, Uh, Vh, lp, g.info);
   b_load_small(Vh, l, k, lp);
   b_apply<NB>(Q, m, k, g.U + d.u_off, (int64_t)k);
@@ -674,7 +721,10 @@ __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
     const BatchDesc d = g.desc[it];
     const int lp = d.lp;
     const float* A = g.A + d.a_off;
-    if (tid == 0) g_lds.flag = 0;
+    if (tid == 0) {
+      g_lds.flag = 0;
+      g_lds.nonfinite = 0;
+    }
     __syncthreads();
     b_sketch(Om, d.n, d.l, lp, g.k0, g.k1, (uint32_t)d.index);
     switch (lp / 16) {
