@@ -8,6 +8,11 @@ Bar: sigma relative error <= 1e-10; U, V orthonormal and U^T A V = diag(S)
 skeleton and CUR row indices identical to the oracle's up to the first
 near-tie of the pivot norms (margin 1e-8); T and the CUR factor within a
 rounding-level tolerance where the indices agree.
+
+The same step with A stored in BF16, against the oracle run on the BF16
+values of A: sigma within 1e-3 relative, the range-finder residual
+||A - Q Q^T A||_F within 1% of the oracle's, and the skeleton identical up to
+the first pivot margin below 1e-2.
 """
 
 import numpy as np
@@ -139,3 +144,52 @@ def test_c2_qb(c2):
     assert np.abs(Q - d["Q"]).max() <= 1e-9
     assert np.abs(B - d["B"]).max() <= 1e-9
     assert abs(res - d["norms"][-1]) <= 1e-9
+
+
+@pytest.fixture(scope="module")
+def c2_bf16(c2):
+    """The same workload with A stored in BF16 (rounded to nearest even from
+    FP64), against the oracle run on those BF16 values."""
+    import paper_1502_05366_amd as R
+    from oracle import quant as QZ
+    Ab = QZ.bf16_round(c2["A"])
+    Ad = torch.as_tensor(Ab, device="cuda").to(torch.bfloat16)     # exact
+    print("C2 BF16: rsvd_decompose and rsvd_svd_ex on the GPU", flush=True)
+    out = R.decompose(Ad, K, P, Q, SEED)
+    _, Sx, _, info, Qb = R.svd_ex(Ad, K, P, Q, SEED, want_Q=True)
+    torch.cuda.synchronize()
+    print("C2 BF16: oracle", flush=True)
+    Uo, So, Vo, det = O.rsvd(Ab, K, P, Q, SEED, return_details=True)
+    c = O.cur(Ab, K, P, Q, SEED, Q=det["Q"])
+    return dict(Ab=Ab, out=out, Sx=Sx.cpu().numpy(), Qb=Qb.cpu().numpy().astype(np.float64),
+                So=So, Qo=det["Q"], c=c)
+
+
+def test_c2_bf16_sigma(c2_bf16):
+    d = c2_bf16
+    S = d["out"]["S"].cpu().numpy()
+    assert np.max(np.abs(S - d["So"]) / d["So"]) <= 1e-3
+    assert np.max(np.abs(d["Sx"] - d["So"]) / d["So"]) <= 1e-3
+    assert int(d["out"]["info"].cpu()[0]) == 0
+
+
+def test_c2_bf16_range_residual(c2_bf16):
+    # ||A - Q Q^T A||_F with the GPU's basis against the oracle's (same BF16 A)
+    d = c2_bf16
+    Ab, Qg, Qo = d["Ab"], d["Qb"], d["Qo"]
+    rg = np.linalg.norm(Ab - Qg @ (Qg.T @ Ab))
+    ro = np.linalg.norm(Ab - Qo @ (Qo.T @ Ab))
+    print("C2 BF16 ||A - QQ^T A||_F: GPU %.6e oracle %.6e" % (rg, ro), flush=True)
+    assert abs(rg / ro - 1.0) <= 1e-2
+
+
+def test_c2_bf16_skeleton_prefix(c2_bf16):
+    # identical skeleton up to the first pivot whose margin is below 1e-2 (the
+    # BF16 passes perturb B by ~1e-3 relative, so closer pivots may swap)
+    d = c2_bf16
+    J = d["out"]["J"].cpu().numpy()
+    c = d["c"]
+    npre = pivot_prefix(c["pivot_norms"], c["second_norms"], 1e-2)
+    print("C2 BF16 skeleton prefix with margin >= 1e-2: %d" % npre, flush=True)
+    assert np.array_equal(J[:npre], c["J"][:npre])
+    assert np.array_equal(np.sort(J), np.arange(len(J)))
