@@ -26,9 +26,8 @@ namespace rsvd {
 namespace {
 
 constexpr int JNT = 1024;
-// One workgroup up to l = 64 (2 * 64 * 64 * 8 B = 64 KB of LDS).  At l = 80 the
-// one-workgroup iteration measured 1.09 ms against 1.00 ms for the block
-// iteration on three workgroups, so larger factors take the block iteration.
+// One workgroup up to l = 64 (2 * 64 * 64 * 8 B = 64 KB of LDS); larger
+// factors take the block iteration.
 constexpr int LDS_MAX_L = 64;
 
 // l <= LDS_MAX_L: the whole iteration in one workgroup, W and V in LDS.
@@ -81,13 +80,13 @@ __global__ __launch_bounds__(JNT) void jacobi_lds_kernel(const double* __restric
 //
 // The l columns are cut into blocks of BS; blocks are paired by the same
 // round-robin schedule as columns, and each of the NB/2 workgroups of one
-// launch takes one block pair per round: it loads the 2*BS
-// columns of W and V into LDS, rotates every cross pair (x from the first
-// block, y from the second; in round 0 also the pairs inside each block),
-// and writes the columns back.  Between rounds the workgroups exchange
-// progress through per-workgroup tags (agent-scope release / acquire); a
-// sweep over all rounds visits every column pair exactly once.  The
-// iteration stops after the first sweep without a rotation.
+// launch takes one block pair per round: it rotates every cross pair (x from
+// the first block, y from the second; in round 0 also the pairs inside each
+// block) and writes the 2*BS columns of W and V back.  Between rounds the
+// workgroups exchange progress through per-workgroup tags (agent-scope
+// release / acquire); a sweep over all rounds visits every column pair
+// exactly once.  The iteration stops after the first sweep without a
+// rotation.
 constexpr int BS = 16;
 
 struct JacArgs {
@@ -122,221 +121,312 @@ __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   __syncthreads();
 }
 
-// The block kernel gives each column pair to one row of 16 lanes, so a wave
-// works on four pairs at once: lane (row g, position c) holds rows c + 16 e
-// (e = 0..15) of both W columns of its pair.  Sums over a pair are DPP
-// exchanges inside the row; the rotation is computed by every lane of the row
-// (rows whose pair is already orthogonal apply the identity).  V is not
-// rotated column by column: the rotations of a round are accumulated in a
-// 2BS x 2BS orthogonal J (two rows per lane), and the round ends with
-// V(:, pair blocks) <- V(:, pair blocks) J on the matrix cores.
-constexpr int JB_NT = 256;   // 4 waves x 4 pairs = BS pairs per step
-constexpr int JJ = 2 * BS;   // order of J
-// Rows per lane JRPL: 16 for l <= 256, 36 for l <= 576 (a column of W is
-// 16 JRPL rows, rows >= l zero).  LDS column stride of W: the rows + 16
-// doubles, so columns q and q+1 start on opposite halves of the LDS banks;
-// J's column stride alternates bank halves too.  At JRPL = 36 the two W blocks
-// and J fill 158 KB of the 160 KB of LDS.
+// The block kernel takes the rotation parameters from the Gram matrix of its
+// block pair instead of from the columns.  At the start of a round the
+// workgroup forms G = X^T X (X = W(:, pair blocks), 2BS columns) on the matrix
+// cores from fresh columns; each step of the round then reads alpha, beta,
+// gamma of its BS disjoint pairs from G, updates the touched entries of G by
+// the same rotations applied from both sides (on a rotated pair the diagonal
+// becomes alpha - t gamma, beta + t gamma and the pair entry 0), and
+// accumulates the rotations in a 2BS x 2BS orthogonal J.  The round ends with
+// W(:, pair) <- W(:, pair) J and V(:, pair) <- V(:, pair) J on the matrix
+// cores.  The pairs, their order and the rotation formulas are those of the
+// column iteration; only where alpha, beta, gamma come from differs, and the
+// test of a pair that has not moved in the round reads fresh inner products,
+// so the final sweep (no rotation) checks every pair on the columns
+// themselves.  A step touches 2BS x 2BS entries of G and J instead of the
+// 2 l entries of two columns, and the l-long work moves to the products.
+//
+// W and V are held padded, ROWS x (nbp BS) with ROWS = 16 JRPL rows (zero
+// beyond l rows and l columns), so that every tile access is in range.
+// Lane layout (g = lane / 16, c = lane % 16): row tile t of wave w covers
+// rows 16 (w RTW + t) + c; the lane holds W(row, col 4 kk + g), kk = 0..7, of
+// the block pair, the B operand of W_new^T = J^T W^T.  The Gram product needs
+// the rows along the reduction instead: each wave passes its tiles through a
+// small LDS area of its own and reads them back as W(16 t + 4 k + g, col c),
+// so W is read from memory once, coalesced, for both products.
+constexpr int JJ = 2 * BS;   // columns of a block pair
+constexpr int GLD = JJ + 1;  // LDS stride of G and J
+constexpr int TLD = 17;      // LDS stride of a wave's transposition area
 constexpr int JACOBI_MAX_L = 576;
-template <int JRPL> struct JacDims {
+// JRPL: 16-row tiles of a column; NW: waves (2 per SIMD).  The products
+// keep their operands in registers: W's are loaded at the start of the round
+// and kept through the steps; V's are loaded with them at JRPL = 16
+// (l <= 256) and after W's product at JRPL = 40 (l <= 576, register budget).
+template <int JRPL, int NW> struct JacDims {
+  static constexpr int NT = 64 * NW;
   static constexpr int ROWS = 16 * JRPL;
-  static constexpr int JLD = ROWS + 16;
-  static constexpr int JJS = JRPL > 16 ? 40 : 48;
-  static constexpr size_t LDS = (2 * (size_t)BS * JLD + (size_t)JJ * JJS) * sizeof(double);
+  static constexpr int RTW = JRPL / NW;        // row tiles per wave
+  static constexpr bool PRE = JRPL <= 16;      // V operands loaded at the start
+  static_assert(JRPL % NW == 0, "row tiles must split evenly over the waves");
+  static constexpr size_t LDS =
+      ((size_t)NW * 3 * 256 + (size_t)NW * JJ * TLD + 3 * (size_t)JJ * GLD) * sizeof(double);
 };
 
-__device__ __forceinline__ double row16_sum(double x) {
-  x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
-  x += dpp_d<0x4E>(x);     // quad_perm [2, 3, 0, 1]
-  x += dpp_d<0x141>(x);    // row_half_mirror
-  x += dpp_d<0x140>(x);    // row_mirror
-  return x;
+// Rotation of jacobi_rotation with t = s / c returned as well.
+__device__ __forceinline__ bool jacobi_rotation_t(double al, double be, double ga, double tol,
+                                                  double& cs, double& sn, double& tt) {
+  if (!(ga * ga > (tol * tol) * (al * be))) return false;
+  const double zeta = (be - al) * (0.5 * rcp_nr1(ga));
+  const double az = fabs(zeta);
+  double t;
+  if (az < 1e150) {
+    const double z2 = fma(zeta, zeta, 1.0);
+    t = rcp_nr1(az + z2 * rsq_nr(z2));
+  } else {
+    t = 0.5 * rcp_nr1(az);
+  }
+  t = zeta >= 0.0 ? t : -t;
+  cs = rsq_nr(fma(t, t, 1.0));
+  sn = cs * t;
+  tt = t;
+  return true;
 }
 
-template <int JRPL>
-__device__ __forceinline__ bool rotate_row16(double (&xw)[JRPL], double (&xj)[2],
-                                             double (&yw)[JRPL], double (&yj)[2], double tol) {
-  double al[2] = {0.0, 0.0}, be[2] = {0.0, 0.0}, ga[2] = {0.0, 0.0};   // two chains each
-#pragma unroll
-  for (int e = 0; e < JRPL; ++e) {
-    al[e & 1] = fma(xw[e], xw[e], al[e & 1]);
-    be[e & 1] = fma(yw[e], yw[e], be[e & 1]);
-    ga[e & 1] = fma(xw[e], yw[e], ga[e & 1]);
+// Columns (p, q) of pair P in step t: round 0 first visits the pairs inside
+// each block (BS - 1 round-robin steps, both blocks at once), then every
+// round visits the cross pairs (x_P, y_{(P + t) mod BS}), t = 0 .. BS - 1.
+__device__ __forceinline__ void pair_cols(bool inner, int t, int P, int& p, int& q) {
+  if (inner) {
+    const int half = P / (BS / 2), pi = P % (BS / 2);
+    p = rr_player(pi, t, BS);
+    q = rr_player(BS - 1 - pi, t, BS);
+    if (p > q) { const int x = p; p = q; q = x; }
+    p += half * BS;
+    q += half * BS;
+  } else {
+    p = P;
+    q = BS + (P + t) % BS;
   }
-  const double alpha = row16_sum(al[0] + al[1]);
-  const double beta = row16_sum(be[0] + be[1]);
-  const double gamma = row16_sum(ga[0] + ga[1]);
-  double cs, sn;
-  const bool rot = jacobi_rotation(alpha, beta, gamma, tol, cs, sn);
-  if (!rot) { cs = 1.0; sn = 0.0; }
-#pragma unroll
-  for (int e = 0; e < JRPL; ++e) {
-    const double a = xw[e], b = yw[e];
-    xw[e] = cs * a - sn * b;
-    yw[e] = sn * a + cs * b;
-  }
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const double c = xj[e], d = yj[e];
-    xj[e] = cs * c - sn * d;
-    yj[e] = sn * c + cs * d;
-  }
-  return rot;
 }
 
-template <int JRPL>
-__device__ __forceinline__ void lds_col_load(const double* base, int rl, double (&v)[JRPL]) {
-#pragma unroll
-  for (int e = 0; e < JRPL; ++e) v[e] = base[rl + 16 * e];
-}
-template <int JRPL>
-__device__ __forceinline__ void lds_col_store(double* base, int rl, const double (&v)[JRPL]) {
-#pragma unroll
-  for (int e = 0; e < JRPL; ++e) base[rl + 16 * e] = v[e];
-}
-template <int JJS>
-__device__ __forceinline__ void lds_j_load(const double* Jl, int col, int rl, double (&v)[2]) {
-  v[0] = Jl[col * JJS + rl];
-  v[1] = Jl[col * JJS + rl + 16];
-}
-template <int JJS>
-__device__ __forceinline__ void lds_j_store(double* Jl, int col, int rl, const double (&v)[2]) {
-  Jl[col * JJS + rl] = v[0];
-  Jl[col * JJS + rl + 16] = v[1];
-}
-
-template <int JRPL>
-__global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
-  constexpr int ROWS = JacDims<JRPL>::ROWS;
-  constexpr int JLD = JacDims<JRPL>::JLD;
-  constexpr int JJS = JacDims<JRPL>::JJS;
+template <int JRPL, int NW>
+__global__ __launch_bounds__(64 * NW) void jacobi_block_kernel(JacArgs a) {
+  using D = JacDims<JRPL, NW>;
+  constexpr int NT = D::NT, RTW = D::RTW;
   extern __shared__ double smem[];
-  __shared__ int rotated;
+  __shared__ int rotated, rround;
+  __shared__ int ptab[(BS - 1) * BS];       // inner steps: p | q << 8 of pair P in step t
+  double* Gp = smem;                        // [NW][3][16 x 16] partial Gram tiles
+  double* Ts = Gp + NW * 3 * 256;           // [NW][JJ][TLD] transposition areas
+  double* G = Ts + NW * JJ * TLD;           // [2][JJ][GLD], G(i, j) at i GLD + j, two copies
+  double* Jm = G + 2 * JJ * GLD;            // [JJ][GLD], J(c, j) at c GLD + j
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rl = lane & 15;
-  const int ps = wave * 4 + (lane >> 4);    // pair slot 0 .. BS-1
+  const int li = lane & 15, lg = lane >> 4;
   const int w = blockIdx.x;
-  const int l = a.l;
-  double* Wl = smem;                        // [2*BS][JLD]
-  double* Jl = smem + 2 * BS * JLD;         // [JJ][JJS], column-major
+  const int64_t ld = a.ld;
   uint32_t done = 0;
   int sweep = 0;
   bool converged = false;
   if (tid == 0) rotated = 0;
+  for (int e = tid; e < (BS - 1) * BS; e += NT) {
+    int p, q;
+    pair_cols(true, e / BS, e % BS, p, q);
+    ptab[e] = p | (q << 8);
+  }
   while (!converged && sweep < a.max_sweeps) {
     for (int r = 0; r < a.nbp - 1; ++r) {
       const int bi = rr_player(w, r, a.nbp), bj = rr_player(a.nbp - 1 - w, r, a.nbp);
       auto gcol_of = [&](int c) { return (c < BS) ? bi * BS + c : bj * BS + (c - BS); };
-      // load the two W blocks (columns >= l and rows >= l read as zero), each
-      // thread issuing all its loads before its LDS writes; J = I
+      // the block pair's rows of W (and at JRPL = 16 of V), coalesced
+      double wu[RTW][8], vu[RTW][8];
+      // the lane's rows of column c start at M + col_off(c); the tiles of a
+      // wave follow each other (16 rows apart)
+      const int64_t row0 = 16 * wave * RTW + li;
+      auto col_off = [&](int c) { return (int64_t)gcol_of(c) * ld + row0; };
+      auto load_upd = [&](const double* M, double (&u)[RTW][8]) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const double* pc = M + col_off(4 * kk + lg);
+#pragma unroll
+          for (int t = 0; t < RTW; ++t) u[t][kk] = ld_agent(pc + 16 * t);
+        }
+      };
+      load_upd(a.W, wu);
+      if (D::PRE) load_upd(a.V, vu);
+      for (int e = tid; e < JJ * JJ; e += NT)
+        Jm[(e / JJ) * GLD + e % JJ] = (e / JJ == e % JJ) ? 1.0 : 0.0;
+      if (tid == 0) rround = 0;
+      // G = X^T X: every wave sums its rows, the partial tiles are added in
+      // wave order
       {
-        // wave w takes columns w, w+4, .. of the 2 BS; lanes run down the
-        // rows (one column's loads per batch)
-        for (int cc = 0; cc < 2 * BS / 4; ++cc) {
-          const int c = wave + 4 * cc;
-          const int gcol = gcol_of(c);
-          double vv[ROWS / 64];
+        double* T = Ts + wave * JJ * TLD;
+        d4 axx = Mfma<double>::zero(), axy = Mfma<double>::zero(), ayy = Mfma<double>::zero();
 #pragma unroll
-          for (int t = 0; t < ROWS / 64; ++t) {
-            const int i = lane + 64 * t;
-            vv[t] = (i < l && gcol < l) ? ld_agent(a.W + (int64_t)gcol * a.ld + i) : 0.0;
+        for (int t = 0; t < RTW; ++t) {
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) T[(4 * kk + lg) * TLD + li] = wu[t][kk];
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double x = T[li * TLD + 4 * k + lg], y = T[(BS + li) * TLD + 4 * k + lg];
+            axx = Mfma<double>::mma(x, x, axx);
+            axy = Mfma<double>::mma(x, y, axy);
+            ayy = Mfma<double>::mma(y, y, ayy);
           }
-#pragma unroll
-          for (int t = 0; t < ROWS / 64; ++t) Wl[c * JLD + lane + 64 * t] = vv[t];
+          __syncthreads();
         }
 #pragma unroll
-        for (int e = 0; e < JJ * JJ / JB_NT; ++e) {
-          const int idx = tid + e * JB_NT;
-          Jl[(idx / JJ) * JJS + idx % JJ] = (idx / JJ == idx % JJ) ? 1.0 : 0.0;
+        for (int v = 0; v < 4; ++v) {
+          const int e = drow(lg, v) * 16 + li;
+          Gp[(wave * 3 + 0) * 256 + e] = axx[v];
+          Gp[(wave * 3 + 1) * 256 + e] = axy[v];
+          Gp[(wave * 3 + 2) * 256 + e] = ayy[v];
         }
       }
       __syncthreads();
-      bool rot = false;
-      double xw[JRPL], yw[JRPL], xj[2], yj[2];
-      if (r == 0) {
-        // pairs inside each block: BS-1 round-robin rounds, both blocks at once
-        for (int t = 0; t < BS - 1; ++t) {
-          const int half = ps / (BS / 2), pi = ps % (BS / 2);
-          int p = rr_player(pi, t, BS), q = rr_player(BS - 1 - pi, t, BS);
-          if (p > q) { const int x = p; p = q; q = x; }
-          p += half * BS; q += half * BS;
-          lds_col_load<JRPL>(Wl + p * JLD, rl, xw); lds_j_load<JJS>(Jl, p, rl, xj);
-          lds_col_load<JRPL>(Wl + q * JLD, rl, yw); lds_j_load<JJS>(Jl, q, rl, yj);
-          rot |= rotate_row16<JRPL>(xw, xj, yw, yj, a.tol);
-          lds_col_store<JRPL>(Wl + p * JLD, rl, xw); lds_j_store<JJS>(Jl, p, rl, xj);
-          lds_col_store<JRPL>(Wl + q * JLD, rl, yw); lds_j_store<JJS>(Jl, q, rl, yj);
-          __syncthreads();
-        }
-      }
-      // cross pairs (x_p, y_{(p+t) mod BS}), t = 0 .. BS-1: pair slot p keeps
-      // x_p in registers, the y columns move between slots through LDS
-      {
-        const int p = ps;
-        lds_col_load<JRPL>(Wl + p * JLD, rl, xw); lds_j_load<JJS>(Jl, p, rl, xj);
-        for (int t = 0; t < BS; ++t) {
-          const int q = BS + (p + t) % BS;
-          lds_col_load<JRPL>(Wl + q * JLD, rl, yw); lds_j_load<JJS>(Jl, q, rl, yj);
-          rot |= rotate_row16<JRPL>(xw, xj, yw, yj, a.tol);
-          lds_col_store<JRPL>(Wl + q * JLD, rl, yw); lds_j_store<JJS>(Jl, q, rl, yj);
-          __syncthreads();
-        }
-        lds_col_store<JRPL>(Wl + p * JLD, rl, xw); lds_j_store<JJS>(Jl, p, rl, xj);
-      }
-      if (rot) rotated = 1;
-      __syncthreads();
-      // W back to memory
-      {
-        for (int cc = 0; cc < 2 * BS / 4; ++cc) {
-          const int c = wave + 4 * cc;
-          const int gcol = gcol_of(c);
+      for (int e = tid; e < 256; e += NT) {
+        // partials read CH waves at a time, added in wave order
+        constexpr int CH = NW % 4 == 0 ? 4 : 2;
+        static_assert(NW % CH == 0, "");
+        double sxx = 0.0, sxy = 0.0, syy = 0.0;
 #pragma unroll
-          for (int t = 0; t < ROWS / 64; ++t) {
-            const int i = lane + 64 * t;
-            if (i < l && gcol < l) st_agent(a.W + (int64_t)gcol * a.ld + i, Wl[c * JLD + i]);
+        for (int v0 = 0; v0 < NW; v0 += CH) {
+          double px[CH], py[CH], pz[CH];
+#pragma unroll
+          for (int v = 0; v < CH; ++v) {
+            px[v] = Gp[((v0 + v) * 3 + 0) * 256 + e];
+            py[v] = Gp[((v0 + v) * 3 + 1) * 256 + e];
+            pz[v] = Gp[((v0 + v) * 3 + 2) * 256 + e];
+          }
+#pragma unroll
+          for (int v = 0; v < CH; ++v) {
+            sxx += px[v];
+            sxy += py[v];
+            syy += pz[v];
           }
         }
+        const int i = e / 16, j = e % 16;
+        G[i * GLD + j] = sxx;
+        G[(BS + i) * GLD + BS + j] = syy;
+        G[i * GLD + BS + j] = sxy;
+        G[(BS + j) * GLD + i] = sxy;
       }
-      // V(:, pair) <- V(:, pair) J: wave v takes row tiles v, v+4, v+8, ..
-      // (16 rows each, in groups of RG tiles) and both 16-column halves; it
-      // reads all rows of a group before it writes any, and no other wave
-      // touches them
-      {
-        constexpr int RT = JRPL / 4;           // row tiles per wave
-        constexpr int RG = RT % 3 == 0 ? 3 : RT;
-        const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-        for (int q0 = 0; q0 < RT; q0 += RG) {
-          double av[RG][JJ / 4];
-#pragma unroll
-          for (int q = 0; q < RG; ++q) {
-            const int row = (wave + 4 * (q0 + q)) * 16 + li;
-#pragma unroll
-            for (int kk = 0; kk < JJ / 4; ++kk) {
-              const int gcol = gcol_of(kk * 4 + lk);
-              av[q][kk] =
-                  (row < l && gcol < l) ? ld_agent(a.V + (int64_t)gcol * a.ld + row) : 0.0;
+      __syncthreads();
+      // the steps of the round on G and J.  Thread (I, K) of the first BS^2
+      // (I = tid / BS, K = lane % BS) owns the 2 x 2 blocks of G and of J on
+      // the rows of pair I and the columns of pair K (the pairs of a step
+      // partition the 2BS columns, so the blocks partition G and J).  Every
+      // lane computes the rotation of its pair K and takes that of pair I
+      // from a lane of its own row of 16 whose K is I, so one barrier per
+      // step suffices: G is read from one copy and written to the other,
+      // each J block is read and written by its owner only.
+      // A round in which no pair of the block pair passes the rotation test
+      // on the fresh G rotates nothing (G never changes), so its steps are
+      // skipped: the same decisions as running them.  Every sweep's last
+      // round set is such a check.
+      int any_pair = 0;
+      for (int e = tid; e < BS * BS; e += NT) {
+        const double tol2 = a.tol * a.tol;
+        const int i = e / BS, j = e % BS;
+        const double gc = G[i * GLD + BS + j];
+        int need = gc * gc > tol2 * (G[i * GLD + i] * G[(BS + j) * GLD + BS + j]);
+        if (r == 0 && i < j) {
+          const double gx = G[i * GLD + j], gy = G[(BS + i) * GLD + BS + j];
+          need |= gx * gx > tol2 * (G[i * GLD + i] * G[j * GLD + j]);
+          need |= gy * gy > tol2 * (G[(BS + i) * GLD + BS + i] * G[(BS + j) * GLD + BS + j]);
+        }
+        any_pair |= need;
+      }
+      const int ninner = (r == 0) ? BS - 1 : 0;
+      const int I = tid / BS, K = tid % BS;
+      const int srcI = (lane & ~(BS - 1)) | I;
+      // one step on the pairs (pI, qI) of thread row I and (pK, qK) of
+      // thread column K, G read from copy st & 1
+      auto step = [&](int st, int pI, int qI, int pK, int qK) {
+        const double* Gc = G + (st & 1) * JJ * GLD;
+        double* Gn = G + ((st + 1) & 1) * JJ * GLD;
+        const double aK = Gc[pK * GLD + pK], bK = Gc[qK * GLD + qK], gK = Gc[pK * GLD + qK];
+        const double gpp = Gc[pI * GLD + pK], gpq = Gc[pI * GLD + qK];
+        const double gqp = Gc[qI * GLD + pK], gqq = Gc[qI * GLD + qK];
+        const double jpp = Jm[pI * GLD + pK], jpq = Jm[pI * GLD + qK];
+        const double jqp = Jm[qI * GLD + pK], jqq = Jm[qI * GLD + qK];
+        double cK = 1.0, sK = 0.0, tK = 0.0;
+        const bool rK = jacobi_rotation_t(aK, bK, gK, a.tol, cK, sK, tK);
+        if (!rK) { cK = 1.0; sK = 0.0; }
+        // (1, 0) for a pair that does not turn: the products below are then
+        // exact copies
+        const double cI = __shfl(cK, srcI, 64), sI = __shfl(sK, srcI, 64);
+        if (I == K) {
+          if (rK) { rotated = 1; rround = 1; }
+          Gn[pK * GLD + pK] = rK ? aK - tK * gK : aK;
+          Gn[qK * GLD + qK] = rK ? bK + tK * gK : bK;
+          Gn[pK * GLD + qK] = rK ? 0.0 : gK;
+          Gn[qK * GLD + pK] = rK ? 0.0 : gK;
+        } else {
+          // rows by the rotation of pair I, then columns by that of pair K
+          const double rpp = cI * gpp - sI * gqp, rqp = sI * gpp + cI * gqp;
+          const double rpq = cI * gpq - sI * gqq, rqq = sI * gpq + cI * gqq;
+          Gn[pI * GLD + pK] = cK * rpp - sK * rpq;
+          Gn[pI * GLD + qK] = sK * rpp + cK * rpq;
+          Gn[qI * GLD + pK] = cK * rqp - sK * rqq;
+          Gn[qI * GLD + qK] = sK * rqp + cK * rqq;
+        }
+        // J <- J J_t on the block: its columns pK, qK turn by pair K
+        if (rK) {
+          Jm[pI * GLD + pK] = cK * jpp - sK * jpq;
+          Jm[pI * GLD + qK] = sK * jpp + cK * jpq;
+          Jm[qI * GLD + pK] = cK * jqp - sK * jqq;
+          Jm[qI * GLD + qK] = sK * jqp + cK * jqq;
+        }
+      };
+      if (__syncthreads_or(any_pair)) {
+#pragma unroll 1
+        for (int st = 0; st < ninner + BS; ++st) {
+          if (tid < BS * BS) {
+            int pI, qI, pK, qK;
+            if (st < ninner) {
+              const int eI = ptab[st * BS + I], eK = ptab[st * BS + K];
+              pI = eI & 0xFF; qI = eI >> 8; pK = eK & 0xFF; qK = eK >> 8;
+            } else {
+              const int t = st - ninner;
+              pI = I; qI = BS + ((I + t) & (BS - 1));
+              pK = K; qK = BS + ((K + t) & (BS - 1));
             }
+            step(st, pI, qI, pK, qK);
           }
+          __syncthreads();
+        }
+      }
+      // W(:, pair) <- W(:, pair) J and V(:, pair) <- V(:, pair) J as
+      // W_new^T = J^T W^T (A operand J^T from LDS, B operand the row tiles);
+      // lane (c, g) receives rows r0 + c of columns 16 jh + 4 v + g
+      if (rround) {
+        double ja[2][8];
 #pragma unroll
-          for (int ct = 0; ct < JJ / 16; ++ct) {
-            double bv[JJ / 4];
+        for (int jh = 0; jh < 2; ++jh)
 #pragma unroll
-            for (int kk = 0; kk < JJ / 4; ++kk) bv[kk] = Jl[(ct * 16 + li) * JJS + kk * 4 + lk];
+          for (int kk = 0; kk < 8; ++kk) ja[jh][kk] = Jm[(4 * kk + lg) * GLD + 16 * jh + li];
+        // TG row tiles at a time: 2 TG independent accumulator chains
+        constexpr int TG = RTW <= 2 ? RTW : 1;
+        auto apply = [&](const double (&u)[RTW][8], double* M) {
 #pragma unroll
-            for (int q = 0; q < RG; ++q) {
-              d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+          for (int t0 = 0; t0 < RTW; t0 += TG) {
+            d4 acc[TG][2];
 #pragma unroll
-              for (int kk = 0; kk < JJ / 4; ++kk)
-                acc = Mfma<double>::mma(av[q][kk], bv[kk], acc);
-              const int gcol = gcol_of(ct * 16 + li);
+            for (int t = 0; t < TG; ++t)
+#pragma unroll
+              for (int jh = 0; jh < 2; ++jh) acc[t][jh] = Mfma<double>::zero();
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+              for (int t = 0; t < TG; ++t)
+#pragma unroll
+                for (int jh = 0; jh < 2; ++jh)
+                  acc[t][jh] = Mfma<double>::mma(ja[jh][kk], u[t0 + t][kk], acc[t][jh]);
+#pragma unroll
+            for (int jh = 0; jh < 2; ++jh)
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
-                const int row = (wave + 4 * (q0 + q)) * 16 + drow(lk, v);
-                if (row < l && gcol < l) st_agent(a.V + (int64_t)gcol * a.ld + row, acc[v]);
+                double* pc = M + col_off(16 * jh + drow(lg, v)) + 16 * t0;
+#pragma unroll
+                for (int t = 0; t < TG; ++t) st_agent(pc + 16 * t, acc[t][jh][v]);
               }
-            }
           }
-        }
+        };
+        apply(wu, a.W);
+        if (!D::PRE) load_upd(a.V, vu);
+        apply(vu, a.V);
       }
       const bool last = (r == a.nbp - 2);
       if (last && tid == 0)
@@ -363,17 +453,20 @@ __global__ __launch_bounds__(JB_NT) void jacobi_block_kernel(JacArgs a) {
   }
 }
 
+// W = Rh (column j of W is row j of the row-major Rh), V = I, both padded
+// with zeros to ld rows and ncols columns
 __global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restrict__ Rh,
-                                                          int64_t ldr, int l,
+                                                          int64_t ldr, int l, int ncols,
                                                           double* __restrict__ W,
                                                           double* __restrict__ V, int64_t ld,
                                                           uint32_t* ctl, int nctl) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e < nctl) ctl[e] = 0;
-  if (e >= (int64_t)l * l) return;
-  const int j = (int)(e / l), i = (int)(e - (int64_t)j * l);
-  W[(int64_t)j * ld + i] = Rh[(int64_t)i * ldr + j];
-  V[(int64_t)j * ld + i] = (i == j) ? 1.0 : 0.0;
+  if (e >= ld * ncols) return;
+  const int j = (int)(e / ld), i = (int)(e - (int64_t)j * ld);
+  const bool in = i < l && j < l;
+  W[e] = in ? Rh[(int64_t)i * ldr + j] : 0.0;
+  V[e] = (in && i == j) ? 1.0 : 0.0;
 }
 
 __global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __restrict__ W,
@@ -393,20 +486,28 @@ __global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __rest
 // the abort flag (FLAG_STRIDE apart; at most 64 workgroups)
 constexpr int JCTL = 200;
 
-size_t jacobi_work_bytes(int l) {
-  // W, V (l x l each) and the control words of the block iteration
-  return 2 * (size_t)l * l * sizeof(double) + JCTL * FLAG_STRIDE * sizeof(uint32_t) + 256;
+// padded shape of W and V in the block iteration
+static int jac_rows(int l) { return l <= 256 ? 16 * 16 : 16 * 40; }
+static int jac_cols(int l) {
+  const int nb = (int)cdiv(l, BS);
+  return (nb + (nb & 1)) * BS;
 }
 
-template <int JRPL>
+size_t jacobi_work_bytes(int l) {
+  // W, V (padded) and the control words of the block iteration
+  return 2 * (size_t)jac_rows(l) * jac_cols(l) * sizeof(double) +
+         JCTL * FLAG_STRIDE * sizeof(uint32_t) + 256;
+}
+
+template <int JRPL, int NW>
 hipError_t launch_block(JacArgs& a, hipStream_t s) {
-  const size_t shm = JacDims<JRPL>::LDS;
-  hipError_t e = hipFuncSetAttribute((const void*)jacobi_block_kernel<JRPL>,
+  const size_t shm = JacDims<JRPL, NW>::LDS;
+  hipError_t e = hipFuncSetAttribute((const void*)jacobi_block_kernel<JRPL, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  return hipLaunchKernel((const void*)jacobi_block_kernel<JRPL>, dim3(a.G), dim3(JB_NT), args,
-                         shm, s);
+  return hipLaunchKernel((const void*)jacobi_block_kernel<JRPL, NW>, dim3(a.G),
+                         dim3(JacDims<JRPL, NW>::NT), args, shm, s);
 }
 
 hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* work, double* S,
@@ -426,13 +527,14 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
                        Vh, ldvh, max_sweeps, tol, info);
     return hipGetLastError();
   }
+  const int64_t ld = jac_rows(l);
+  const int ncols = jac_cols(l);
   double* W = work;
-  double* V = work + (size_t)l * l;
-  uint32_t* ctl = reinterpret_cast<uint32_t*>(V + (size_t)l * l);
-  const int nb = (int)cdiv(l, BS);
-  const int nbp = nb + (nb & 1);
+  double* V = work + (size_t)ld * ncols;
+  uint32_t* ctl = reinterpret_cast<uint32_t*>(V + (size_t)ld * ncols);
+  const int nbp = ncols / BS;
   JacArgs a;
-  a.W = W; a.V = V; a.ld = l; a.l = l; a.nbp = nbp; a.G = nbp / 2; a.max_sweeps = max_sweeps;
+  a.W = W; a.V = V; a.ld = ld; a.l = l; a.nbp = nbp; a.G = nbp / 2; a.max_sweeps = max_sweeps;
   a.tol = tol;
   a.tags = ctl;                                   // 64 flags
   a.rot = ctl + 64 * FLAG_STRIDE;                 // 2 x 64 flags
@@ -442,14 +544,14 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
   a.info = info;
   a.sweeps_out = sweeps_out;
   // one thread per element of W and per control word
-  const int64_t ninit = std::max<int64_t>((int64_t)l * l, (int64_t)JCTL * FLAG_STRIDE);
+  const int64_t ninit = std::max<int64_t>(ld * ncols, (int64_t)JCTL * FLAG_STRIDE);
   hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, Rh,
-                     ldr, l, W, V, (int64_t)l, ctl, JCTL * FLAG_STRIDE);
+                     ldr, l, ncols, W, V, ld, ctl, JCTL * FLAG_STRIDE);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = (l <= 256) ? launch_block<16>(a, s) : launch_block<36>(a, s);
+  e = (l <= 256) ? launch_block<16, 8>(a, s) : launch_block<40, 8>(a, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, (int64_t)l, l, k, S, Uh,
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, ld, l, k, S, Uh,
                      lduh, Vh, ldvh);
   return hipGetLastError();
 }
