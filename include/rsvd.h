@@ -289,6 +289,20 @@ int rsvd_batch_layout(rsvd_batch_t plan, int64_t* a_elems, int64_t* u_elems, int
                       int64_t* v_elems, int64_t* a_off, int64_t* lda, int64_t* u_off,
                       int64_t* s_off, int64_t* v_off);
 size_t rsvd_batch_workspace_bytes(rsvd_batch_t plan);
+/*
+ * rsvd_batch_set_variants: the shape of the passes over A for each matrix
+ *   (host int32 array of `count`, caller order), each in
+ *   0 .. RSVD_BATCH_VARIANTS - 1: 0 = 128-row tiles of A with 64-deep chunks,
+ *   1 = 256-row tiles with 32-deep chunks, 2 = 128-row tiles with 32-deep
+ *   chunks (A^T passes: columns).  A shape changes only the order of the FP32
+ *   sums of the passes.  Plans start at shape 0; the package's autotuner
+ *   measures the shapes per (m, n, l) bucket and stores the fastest in a
+ *   table that its BatchPlan applies.  The descriptors travel with
+ *   rsvd_batch_prepare, so call it again afterwards (rsvd_batch_svd returns
+ *   -7 until then).  Returns -2 on a NULL array or a value out of range.
+ */
+#define RSVD_BATCH_VARIANTS 3
+int rsvd_batch_set_variants(rsvd_batch_t plan, const int32_t* variant);
 int rsvd_batch_prepare(rsvd_batch_t plan, void* work, size_t work_bytes, void* stream);
 int rsvd_batch_svd(rsvd_batch_t plan, uint64_t seed, const float* A, float* U, double* S, float* V,
                    void* work, size_t work_bytes, int32_t* info, void* stream);

@@ -47,6 +47,7 @@ SIGNATURES = {
     "rsvd_batch_layout": (c_int, [c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr,
                                   c_ptr]),
     "rsvd_batch_workspace_bytes": (c_size, [c_ptr]),
+    "rsvd_batch_set_variants": (c_int, [c_ptr, c_ptr]),
     "rsvd_batch_prepare": (c_int, [c_ptr, c_ptr, c_size, c_ptr]),
     "rsvd_batch_svd": (c_int, [c_ptr, c_u64, c_ptr, c_ptr, c_ptr, c_ptr, c_ptr, c_size, c_ptr,
                                c_ptr]),

@@ -366,8 +366,11 @@ class BatchPlan:
     persistent kernel (capturable in a CUDA/HIP graph once prepared), unpack()
     splits U, S, V per matrix."""
 
-    def __init__(self, ms, ns, ks, p, q, device="cuda"):
+    def __init__(self, ms, ns, ks, p, q, device="cuda", variants=None):
+        """variants: pass shape per matrix (an int for all, a sequence, or None
+        for the autotuned table's choice; see batch_tune)."""
         import numpy as np
+        from . import batch_tune
         lib = _lib.load()
         self.device = torch.device(device)
         self.count = len(ms)
@@ -385,6 +388,13 @@ class BatchPlan:
                                    ctypes.byref(plan))
         _check(rc, "rsvd_batch_create")
         self._plan = plan
+        if variants is None:
+            ls = np.minimum(self.ks.astype(np.int64) + p, np.minimum(self.ms, self.ns))
+            variants = batch_tune.choose(self.ms, self.ns, ls)
+        self.variants = np.ascontiguousarray(
+            np.broadcast_to(np.asarray(variants, dtype=np.int32), (self.count,)))
+        rc = lib.rsvd_batch_set_variants(plan, self.variants.ctypes.data_as(ctypes.c_void_p))
+        _check(rc, "rsvd_batch_set_variants")
         tot = [ctypes.c_int64(0) for _ in range(4)]
         offs = [np.zeros(self.count, dtype=np.int64) for _ in range(5)]
         rc = lib.rsvd_batch_layout(plan, *[ctypes.byref(t) for t in tot],

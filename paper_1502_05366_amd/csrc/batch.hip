@@ -41,17 +41,28 @@ namespace {
 constexpr int BNT = 512;             // 8 waves
 constexpr int BLMAX = BATCH_MAX_LP;  // lp <= 80
 constexpr int SL = BLMAX + 1;        // LDS row stride of the small FP64 matrices
-constexpr int KC = 64;               // depth of a pass chunk
+// Pass shapes (the batch autotuner picks one per matrix): a pass over A
+// takes tiles of TM = 128 RPW rows of A (A^T: columns), RPW 16-row blocks
+// per wave, and KC-deep chunks of A and of the skinny operand, double
+// buffered in LDS.
+//   variant 0: TM = 128, KC = 64;  variant 1: TM = 256, KC = 32;
+//   variant 2: TM = 128, KC = 32.
 // LDS row strides (floats), chosen so that the operand reads of a wave hit
-// distinct banks: lane (li, lk) reads row li (stride 68 = 4 mod 64) at
-// column lk of the A tile, and row lk (stride 80 = 16 mod 64, 144 = 16 mod
-// 64) at column li of the skinny chunk and of the A^T tile
-constexpr int ALD = 68;              // pass: A tile row stride, 128 x KC
-constexpr int ATLD = 144;            // pass A^T: A tile row stride, KC x 128
+// distinct banks: lane (li, lk) reads row li (stride KC + 4 = 4 or 36 mod
+// 64) at column lk of the A tile, and row lk (stride 80 = 16 mod 64, TM + 16
+// = 16 mod 64) at column li of the skinny chunk and of the A^T tile.
+template <int RPW, int KC> struct PassShape {
+  static constexpr int TM = 128 * RPW;
+  static constexpr int ALD = KC + 4;           // A tile row stride, TM x KC
+  static constexpr int ATLD = TM + 16;         // A^T tile row stride, KC x TM
+  static constexpr int STAGE_N = 2 * (TM * ALD + KC * 80);
+  static constexpr int STAGE_T = 2 * (KC * ATLD + KC * 80);
+  static constexpr int STAGE = STAGE_N > STAGE_T ? STAGE_N : STAGE_T;
+};
 constexpr int XLD = 80;              // skinny chunk row stride, KC x lp
-constexpr int STAGE_N = 2 * (128 * ALD + KC * XLD);
-constexpr int STAGE_T = 2 * (KC * ATLD + KC * XLD);
-constexpr int STAGE_FLOATS = STAGE_N > STAGE_T ? STAGE_N : STAGE_T;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int STAGE_FLOATS = cmax(PassShape<1, 64>::STAGE,
+                                  cmax(PassShape<2, 32>::STAGE, PassShape<1, 32>::STAGE));
 constexpr double ETA_DEP = 1e-13;
 constexpr int JAC_MAX_SWEEPS = 40;
 
@@ -139,32 +150,38 @@ __device__ __forceinline__ void st4(float* p, const float4& v) {
 }
 
 // Y (m x lp) = A X, A m x n (FP32, lda % 4 == 0), X n x lp (FP32), lp = 16 NCB.
-// Row tiles of 128 (16 rows per wave), KC-deep chunks of A and X in LDS.
-template <int NCB>
+// Row tiles of TM (16 RPW rows per wave), KC-deep chunks of A and X in LDS.
+template <int NCB, int RPW, int KC>
 __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
                                       float* __restrict__ Y) {
-  constexpr int lp = 16 * NCB;
+  using S = PassShape<RPW, KC>;
+  constexpr int lp = 16 * NCB, TM = S::TM, ALD = S::ALD;
+  constexpr int AF4 = TM * KC / 4 / BNT;             // float4 of the A tile per thread
+  constexpr int KQ = KC / 4;                          // float4 per A tile row
+  constexpr int XF4 = (KC * 20 + BNT - 1) / BNT;      // float4 of the X chunk per thread (lp <= 80)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   float* st = g_lds.u.stage;
   const int xq = lp / 4;                                // float4 per X row
   const int xn = KC * xq;                               // float4 per X chunk
   const int64_t nkc = cdiv(n, KC);
-  for (int64_t row0 = 0; row0 < m; row0 += 128) {
-    f4 acc[NCB];
+  for (int64_t row0 = 0; row0 < m; row0 += TM) {
+    f4 acc[RPW][NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 av[4], xv[3];
+    for (int rb = 0; rb < RPW; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    float4 av[AF4], xv[XF4];
     auto gload = [&](int64_t kc) {
       const int64_t k0 = kc * KC;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < AF4; ++u) {
         const int idx = tid + BNT * u;
-        av[u] = ld_a4(A, lda, m, n, row0 + (idx >> 4), k0 + (idx & 15) * 4);
+        av[u] = ld_a4(A, lda, m, n, row0 + idx / KQ, k0 + (idx % KQ) * 4);
       }
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < XF4; ++u) {
         const int idx = tid + BNT * u;
         const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
         xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -172,15 +189,15 @@ __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, 
       }
     };
     auto sstore = [&](int b) {
-      float* as = st + b * (128 * ALD);
-      float* xs = st + 2 * 128 * ALD + b * (KC * XLD);
+      float* as = st + b * (TM * ALD);
+      float* xs = st + 2 * TM * ALD + b * (KC * XLD);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < AF4; ++u) {
         const int idx = tid + BNT * u;
-        st4(as + (idx >> 4) * ALD + (idx & 15) * 4, av[u]);
+        st4(as + (idx / KQ) * ALD + (idx % KQ) * 4, av[u]);
       }
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < XF4; ++u) {
         const int idx = tid + BNT * u;
         if (idx < xn) {
           const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
@@ -194,58 +211,70 @@ __device__ __noinline__ void b_pass_n(const float* __restrict__ A, int64_t lda, 
     for (int64_t kc = 0; kc < nkc; ++kc) {
       const bool more = kc + 1 < nkc;
       if (more) gload(kc + 1);
-      const float* as = st + (kc & 1) * (128 * ALD);
-      const float* xs = st + 2 * 128 * ALD + (kc & 1) * (KC * XLD);
+      const float* as = st + (kc & 1) * (TM * ALD);
+      const float* xs = st + 2 * TM * ALD + (kc & 1) * (KC * XLD);
 #pragma unroll
       for (int kk = 0; kk < KC / 4; ++kk) {
-        const float a = as[(wave * 16 + li) * ALD + kk * 4 + lk];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        for (int rb = 0; rb < RPW; ++rb) {
+          const float a = as[((wave * RPW + rb) * 16 + li) * ALD + kk * 4 + lk];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[rb][cb] =
+                Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[rb][cb]);
+        }
         if (kk % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
+    for (int rb = 0; rb < RPW; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = row0 + wave * 16 + Mfma<float>::row(lk, v);
-        if (r < m) Y[r * lp + cb * 16 + li] = acc[cb][v];
+      for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = row0 + (wave * RPW + rb) * 16 + Mfma<float>::row(lk, v);
+          if (r < m) Y[r * lp + cb * 16 + li] = acc[rb][cb][v];
+        }
       }
-    }
   }
   __syncthreads();
 }
 
 // Z (n x lp) = A^T X, A m x n (FP32, lda % 4 == 0), X m x lp (FP32), lp = 16 NCB.
-// Tiles of 128 columns of A (16 per wave), KC-row chunks of A and X in LDS.
-template <int NCB>
+// Tiles of TM columns of A (16 RPW per wave), KC-row chunks of A and X in LDS.
+template <int NCB, int RPW, int KC>
 __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, int64_t m,
                                       int64_t n, const float* __restrict__ X,
                                       float* __restrict__ Z) {
-  constexpr int lp = 16 * NCB;
+  using S = PassShape<RPW, KC>;
+  constexpr int lp = 16 * NCB, TM = S::TM, ATLD = S::ATLD;
+  constexpr int AF4 = TM * KC / 4 / BNT;
+  constexpr int TQ = TM / 4;                          // float4 per A tile row
+  constexpr int XF4 = (KC * 20 + BNT - 1) / BNT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   float* st = g_lds.u.stage;
   const int xq = lp / 4;
   const int xn = KC * xq;
   const int64_t nkc = cdiv(m, KC);
-  for (int64_t col0 = 0; col0 < n; col0 += 128) {
-    f4 acc[NCB];
+  for (int64_t col0 = 0; col0 < n; col0 += TM) {
+    f4 acc[RPW][NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f4{0.f, 0.f, 0.f, 0.f};
-    float4 av[4], xv[3];
+    for (int rb = 0; rb < RPW; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    float4 av[AF4], xv[XF4];
     auto gload = [&](int64_t kc) {
       const int64_t r0 = kc * KC;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < AF4; ++u) {
         const int idx = tid + BNT * u;
-        av[u] = ld_a4(A, lda, m, n, r0 + (idx >> 5), col0 + (idx & 31) * 4);
+        av[u] = ld_a4(A, lda, m, n, r0 + idx / TQ, col0 + (idx % TQ) * 4);
       }
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < XF4; ++u) {
         const int idx = tid + BNT * u;
         const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
         xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -256,12 +285,12 @@ __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, 
       float* as = st + b * (KC * ATLD);
       float* xs = st + 2 * KC * ATLD + b * (KC * XLD);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < AF4; ++u) {
         const int idx = tid + BNT * u;
-        st4(as + (idx >> 5) * ATLD + (idx & 31) * 4, av[u]);
+        st4(as + (idx / TQ) * ATLD + (idx % TQ) * 4, av[u]);
       }
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < XF4; ++u) {
         const int idx = tid + BNT * u;
         if (idx < xn) {
           const int xr = idx / xq, xc = (idx - (idx / xq) * xq) * 4;
@@ -279,24 +308,30 @@ __device__ __noinline__ void b_pass_t(const float* __restrict__ A, int64_t lda, 
       const float* xs = st + 2 * KC * ATLD + (kc & 1) * (KC * XLD);
 #pragma unroll
       for (int kk = 0; kk < KC / 4; ++kk) {
-        // A^T[col][row]: column wave*16 + li of the tile, row kk*4 + lk
-        const float a = as[(kk * 4 + lk) * ATLD + wave * 16 + li];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[cb]);
+        for (int rb = 0; rb < RPW; ++rb) {
+          // A^T[col][row]: column (wave RPW + rb) 16 + li of the tile, row kk*4 + lk
+          const float a = as[(kk * 4 + lk) * ATLD + (wave * RPW + rb) * 16 + li];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[rb][cb] =
+                Mfma<float>::mma(a, xs[(kk * 4 + lk) * XLD + cb * 16 + li], acc[rb][cb]);
+        }
         if (kk % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
       if (more) sstore((kc + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
+    for (int rb = 0; rb < RPW; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t c = col0 + wave * 16 + Mfma<float>::row(lk, v);
-        if (c < n) Z[c * lp + cb * 16 + li] = acc[cb][v];
+      for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t c = col0 + (wave * RPW + rb) * 16 + Mfma<float>::row(lk, v);
+          if (c < n) Z[c * lp + cb * 16 + li] = acc[rb][cb][v];
+        }
       }
-    }
   }
   __syncthreads();
 }
@@ -670,8 +705,9 @@ __device__ void b_load_small(const double* M, int l, int k, int lp) {
 }
 
 // The decomposition of one matrix after its sketch, for lp = 16 NB.
-template <int NB>
-__device__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A, const float* Om,
+template <int NB, int RPW, int KC>
+__device__ __noinline__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A,
+                                   const float* Om,
                       float* Y, float* Q, float* Z, float* Zq, double* T, double* Qh,
                       double* Uh, double* Vh) {
   constexpr int lp = 16 * NB;
@@ -680,15 +716,15 @@ __device__ void b_one(const BatchArgs& g, const BatchDesc& d, const float* A, co
   // batch word of the replacement columns: orth call (high bits), matrix
   const uint32_t mw = (uint32_t)d.index & 0xFFFFFu;
   uint32_t call = 0;
-  b_pass_n<NB>(A, d.lda, m, n, Om, Y);
+  b_pass_n<NB, RPW, KC>(A, d.lda, m, n, Om, Y);
   for (int j = 0; j < g.q; ++j) {
     b_orth<NB>(Y, m, l, T, Q, g.k0, g.k1, (call++ << 20) | mw);
-    b_pass_t<NB>(A, d.lda, m, n, Q, Z);
+    b_pass_t<NB, RPW, KC>(A, d.lda, m, n, Q, Z);
     b_orth<NB>(Z, n, l, T, Zq, g.k0, g.k1, (call++ << 20) | mw);
-    b_pass_n<NB>(A, d.lda, m, n, Zq, Y);
+    b_pass_n<NB, RPW, KC>(A, d.lda, m, n, Zq, Y);
   }
   b_orth<NB>(Y, m, l, T, Q, g.k0, g.k1, (call++ << 20) | mw);
-  b_pass_t<NB>(A, d.lda, m, n, Q, Z);          // B^T
+  b_pass_t<NB, RPW, KC>(A, d.lda, m, n, Q, Z);   // B^T
   b_orth<NB>(Z, n, l, T, Qh, g.k0, g.k1, (call++ << 20) | mw);
   b_xty(Qh, Z, n, lp);                         // Rh = Qh^T B^T
   if (threadIdx.x == 0 && g_lds.flag) info_or(g.info, INFO_ORTH_FALLBACK);
@@ -727,13 +763,21 @@ __global__ __launch_bounds__(BNT) void batch_rsvd_kernel(BatchArgs g) {
     }
     __syncthreads();
     b_sketch(Om, d.n, d.l, lp, g.k0, g.k1, (uint32_t)d.index);
+    // (lp / 16, pass shape) -> one instantiation
+#define RSVD_B1(NBV)                                                                     \
+  switch (d.variant) {                                                                   \
+    case 1: b_one<NBV, 2, 32>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;           \
+    case 2: b_one<NBV, 1, 32>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;           \
+    default: b_one<NBV, 1, 64>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;          \
+  }
     switch (lp / 16) {
-      case 1: b_one<1>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
-      case 2: b_one<2>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
-      case 3: b_one<3>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
-      case 4: b_one<4>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
-      default: b_one<5>(g, d, A, Om, Y, Q, Z, Zq, T, Qh, Uh, Vh); break;
+      case 1: RSVD_B1(1); break;
+      case 2: RSVD_B1(2); break;
+      case 3: RSVD_B1(3); break;
+      case 4: RSVD_B1(4); break;
+      default: RSVD_B1(5); break;
     }
+#undef RSVD_B1
   }
 }
 

@@ -226,10 +226,12 @@ hipError_t launch_add(double* X, int64_t ldx, const double* Y, int64_t ldy, int6
 // Batched randomized SVD of small FP32 matrices, one workgroup per matrix in
 // one persistent launch.
 constexpr int BATCH_MAX_LP = 80;     // l = min(k + p, m, n) <= 80
+constexpr int BATCH_VARIANTS = 3;    // pass shapes of the batch kernel
 struct BatchDesc {
   int64_t m, n, lda;                 // A_i: m x n row-major, lda % 4 == 0
   int64_t a_off, u_off, v_off, s_off;   // element offsets in the packed A, U, V, S
   int32_t k, l, lp, index;           // index: position in the caller's list
+  int32_t variant, pad;              // pass shape (0 .. BATCH_VARIANTS - 1)
 };
 struct BatchArgs {
   const BatchDesc* desc;             // in work-queue order

@@ -48,10 +48,21 @@ __device__ __forceinline__ int rr_player(int pos, int r, int N) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (N - 1)) + 1;
 }
 
+// Sum over a row of 16 lanes (a DPP row), returned in every lane of the
+// row: exchanges xor 1 and xor 2 inside quads, then the half-row and the
+// row mirror.  All 16 lanes of the row must be active.
+__device__ __forceinline__ double dpp_row16_sum(double x) {
+  x += dpp_d<0xB1>(x);     // quad_perm [1, 0, 3, 2]
+  x += dpp_d<0x4E>(x);     // quad_perm [2, 3, 0, 1]
+  x += dpp_d<0x141>(x);    // row_half_mirror
+  x += dpp_d<0x140>(x);    // row_mirror
+  return x;
+}
+
 // Rotation of the column pair (a, b) of W and V (columns contiguous, length
-// l <= 16 RPL) by one group of 16 lanes: lane li holds rows li, li + 16, ...;
-// the dot products are 16-lane butterfly sums (the same value on every lane
-// of the group).  Returns true when a rotation was applied.
+// l <= 16 RPL) by one group of 16 lanes, a DPP row: lane li holds rows li,
+// li + 16, ...; the dot products are DPP row sums (the same value on every
+// lane of the group).  Returns true when a rotation was applied.
 template <int RPL>
 __device__ __forceinline__ bool rotate_pair16(double* wa, double* wb, double* va, double* vb,
                                               int l, int li, double tol) {
@@ -66,12 +77,9 @@ __device__ __forceinline__ bool rotate_pair16(double* wa, double* wb, double* va
     be = fma(xb[t], xb[t], be);
     ga = fma(xa[t], xb[t], ga);
   }
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) {
-    al += __shfl_xor(al, off, 16);
-    be += __shfl_xor(be, off, 16);
-    ga += __shfl_xor(ga, off, 16);
-  }
+  al = dpp_row16_sum(al);
+  be = dpp_row16_sum(be);
+  ga = dpp_row16_sum(ga);
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll

@@ -1361,6 +1361,8 @@ int rsvd_batch_create(rsvd_handle_t h, int64_t count, const int64_t* m, const in
     e.l = (int32_t)std::min<int64_t>((int64_t)k[i] + p, std::min(m[i], n[i]));
     e.lp = (int32_t)rup(e.l, 16);
     e.index = (int32_t)i;
+    e.variant = 0;
+    e.pad = 0;
     ao += m[i] * ld;
     uo += m[i] * k[i];
     so += k[i];
@@ -1424,6 +1426,18 @@ int rsvd_batch_layout(rsvd_batch_t b, int64_t* a_elems, int64_t* u_elems, int64_
 }
 
 size_t rsvd_batch_workspace_bytes(rsvd_batch_t b) { return b ? b->work_bytes : 0; }
+
+static_assert(RSVD_BATCH_VARIANTS == rsvd::BATCH_VARIANTS, "pass shape count");
+
+int rsvd_batch_set_variants(rsvd_batch_t b, const int32_t* variant) {
+  if (!b) return -1;
+  if (!variant) return -2;
+  for (int64_t i = 0; i < b->count; ++i)
+    if (variant[i] < 0 || variant[i] >= rsvd::BATCH_VARIANTS) return -2;
+  for (auto& d : b->desc) d.variant = variant[d.index];
+  b->prepared = nullptr;   // the device copy of the descriptors is stale
+  return RSVD_OK;
+}
 
 int rsvd_batch_prepare(rsvd_batch_t b, void* work, size_t work_bytes, void* stream) {
   if (!b) return -1;

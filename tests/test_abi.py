@@ -199,3 +199,4 @@ def test_batch_create_argument_codes(lib):
     assert lib.rsvd_batch_workspace_bytes(NULLP) == 0
     assert lib.rsvd_batch_svd(NULLP, 1, PTR, PTR, PTR, PTR, PTR, 1, PTR, NULLP) == -1
     assert lib.rsvd_batch_prepare(NULLP, PTR, 1, NULLP) == -1
+    assert lib.rsvd_batch_set_variants(NULLP, PTR) == -1

@@ -43,8 +43,8 @@ def spectrum_batch(ms, ns, seed):
             .astype(np.float32) for i, (m, n) in enumerate(zip(ms, ns))]
 
 
-def run_batch(R, As, ms, ns, ks, p, q, seed=SEED):
-    plan = R.BatchPlan(ms, ns, ks, p, q)
+def run_batch(R, As, ms, ns, ks, p, q, seed=SEED, variants=None):
+    plan = R.BatchPlan(ms, ns, ks, p, q, variants=variants)
     buf = plan.pack([torch.from_numpy(A) for A in As])
     U, S, V, info = plan.run(buf, seed)
     torch.cuda.synchronize()
@@ -92,6 +92,32 @@ def test_batch_parity_uneven(R, q):
     res, info, _ = run_batch(R, As, ms, ns, ks, 8, q)
     assert info[0] == 0, info
     check_against_oracle(As, ks, res, 8, q)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_batch_pass_shapes(R, shape):
+    """Every pass shape of the autotuner's menu gives the oracle's result (the
+    shapes change only the order of the FP32 sums): sizes across one and
+    several row and column tiles of each shape (128 and 256), ragged."""
+    g = np.random.default_rng(60 + shape)
+    ms = np.r_[g.integers(16, 900, 9), 255, 257, 513]
+    ns = np.r_[g.integers(16, 700, 9), 300, 129, 64]
+    ks = np.minimum(np.r_[g.integers(1, 73, 9), 60, 8, 40], np.minimum(ms, ns))
+    print("batch pass shape %d" % shape, flush=True)
+    As = spectrum_batch(ms, ns, 300 + shape)
+    res, info, plan = run_batch(R, As, ms, ns, ks, 8, 1, variants=shape)
+    assert np.all(plan.variants == shape)
+    assert info[0] == 0, info
+    check_against_oracle(As, ks, res, 8, 1)
+
+
+def test_batch_plan_uses_tuned_table(R):
+    from paper_1502_05366_amd import batch_tune
+    ms, ns, ks = np.array([100, 600, 1500, 2000]), np.array([90, 1500, 300, 2000]), \
+        np.array([5, 40, 60, 20])
+    plan = R.BatchPlan(ms, ns, ks, 8, 1)
+    ls = np.minimum(ks + 8, np.minimum(ms, ns))
+    assert np.array_equal(plan.variants, batch_tune.choose(ms, ns, ls))
 
 
 def test_batch_edge_shapes(R):
