@@ -38,8 +38,8 @@ PEAK_FP8_TFLOPS = 5000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "87f0dd29a8d6de49b518b41fca2f7f251b590e259a4081ee7b2dc2765059ecda",
-                "bytes": 4588230000}
+PASS_TRAFFIC = {"sources": "3eb916b52bbb3f0885a0fcfdeb517bd2e43f92a247376d6f498c9c7765f36468",
+                "bytes": 4588310000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 
 
