@@ -95,7 +95,12 @@ __device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t
 __device__ __forceinline__ double sel_key(double s2) { return s2 == s2 ? s2 : -0.5; }
 
 constexpr int CQ_NW = CQ_NT / 64;
-constexpr int CQ_RPL = 16;         // rows per lane (16 lanes per column): r <= 256
+// A column is handled by one row of 16 lanes, RPL rows per lane (rows
+// rl + 16 e, e < RPL); the plan takes the smallest instantiated RPL with
+// 16 RPL >= r and a column stride rp >= 16 RPL, so every row a lane touches is
+// in its column (rows r .. 16 RPL - 1 hold zeros) and no access needs a
+// per-lane test.
+constexpr int CQ_RPLS[] = {2, 4, 8, 12, 13, 14, 16};
 
 // sum over the 16 lanes of a row, returned in each of them
 __device__ __forceinline__ double row16_sum(double x) {
@@ -106,7 +111,7 @@ __device__ __forceinline__ double row16_sum(double x) {
   return x;
 }
 
-template <typename TB>
+template <typename TB, int RPL>
 __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -137,6 +142,8 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     const int i = (int)(e - jj * rp);
     slab[e] = (i < r) ? (double)Bt[(j0 + jj) * a.ldb + i] : 0.0;
   }
+  // the reflector's rows >= r stay zero (the steps write rows s .. r-1)
+  for (int i = tid; i < rp; i += CQ_NT) v[i] = 0.0;
   __syncthreads();
   // initial norms, the workgroup's share of ||B||_F^2 and each lane's best
   // column (largest norm, lowest index on ties).  A column is handled by one
@@ -147,11 +154,11 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
   for (int64_t jb = 0; jb < ncols; jb += CQ_NW * 4) {
     const int64_t jj = jb + wave * 4 + cg;
     const bool act = jj < ncols;
+    const double* col = slab + (act ? jj : 0) * rp;
     double s2 = 0.0;
 #pragma unroll
-    for (int e = 0; e < CQ_RPL; ++e) {
-      const int i = rl + 16 * e;
-      const double x = (act && i < r) ? slab[jj * rp + i] : 0.0;
+    for (int e = 0; e < RPL; ++e) {
+      const double x = col[rl + 16 * e];
       s2 = fma(x, x, s2);
     }
     s2 = row16_sum(s2);
@@ -270,47 +277,58 @@ __global__ __launch_bounds__(CQ_NT) void cpqr_kernel(CpqrArgs a) {
     __syncthreads();
     const double beta = sh_beta, alpha = sh_alpha;
     // apply H to the unchosen owned columns, recompute their norms over rows
-    // s+1.. and track each lane's best column
+    // s+1.. and track each lane's best column.  Rows above s enter as exact
+    // zeros through v (selected per lane), rows r .. 16 RPL - 1 are zero in
+    // the slab and in v; a column's stores run under one test.
     bv = -1.0;
     bi = INT64_MAX;
+    double vr[RPL];
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const int i = rl + 16 * e;
+      const double vv = v[i];
+      vr[e] = i >= s ? vv : 0.0;
+    }
     for (int64_t jb = 0; jb < ncols; jb += CQ_NW * 4) {
       const int64_t jj = jb + wave * 4 + cg;
-      const bool act = (jj < ncols) ? (chosen_at[jj] < 0) : false;
+      const bool inr = jj < ncols;
+      const int64_t jc = inr ? jj : 0;       // a column of the slab for the loads
+      const bool act = inr && chosen_at[jc] < 0;
       const bool is_piv = act && (j0 + jj == gi);
-      double* col = slab + jj * rp;
-      double x[CQ_RPL], vr[CQ_RPL];
+      double* col = slab + jc * rp;
+      double x[RPL];
       double dp[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: short FMA chains
 #pragma unroll
-      for (int e = 0; e < CQ_RPL; ++e) {
-        const int i = rl + 16 * e;
-        vr[e] = (i >= s && i < r) ? v[i] : 0.0;
-        x[e] = (act && i < r) ? col[i] : 0.0;
+      for (int e = 0; e < RPL; ++e) {
+        x[e] = col[rl + 16 * e];
         dp[e & 3] = fma(vr[e], x[e], dp[e & 3]);
       }
       const double wdot = beta * row16_sum((dp[0] + dp[1]) + (dp[2] + dp[3]));
-      if (act && !is_piv && beta != 0.0) {
+      const bool upd = act && !is_piv && beta != 0.0;
 #pragma unroll
-        for (int e = 0; e < CQ_RPL; ++e) {
-          const int i = rl + 16 * e;
-          if (i >= s && i < r) {
-            x[e] = fma(-wdot, vr[e], x[e]);
-            col[i] = x[e];
-          }
-        }
+      for (int e = 0; e < RPL; ++e) {
+        const int i = rl + 16 * e;
+        const double y = fma(-wdot, vr[e], x[e]);
+        x[e] = (upd && i >= s) ? y : x[e];
+      }
+      if (upd) {
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) col[rl + 16 * e] = x[e];
       }
       if (is_piv) {
 #pragma unroll
-        for (int e = 0; e < CQ_RPL; ++e) {
+        for (int e = 0; e < RPL; ++e) {
           const int i = rl + 16 * e;
-          if (i >= s && i < r) col[i] = (i == s) ? alpha : 0.0;
+          col[i] = (i == s) ? alpha : (i > s ? 0.0 : x[e]);
         }
         if (rl == 0) { chosen_at[jj] = s; nrm[jj] = 0.0; }
       }
       double sp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int e = 0; e < CQ_RPL; ++e) {
+      for (int e = 0; e < RPL; ++e) {
         const int i = rl + 16 * e;
-        if (i > s && i < r) sp[e & 3] = fma(x[e], x[e], sp[e & 3]);
+        const double f = fma(x[e], x[e], sp[e & 3]);
+        sp[e & 3] = i > s ? f : sp[e & 3];
       }
       const double s2 = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
       if (act && !is_piv) {
@@ -460,9 +478,13 @@ size_t cpqr_lds_bytes(int64_t cs, int rp, int k) {
 
 CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
   CpqrPlan p;
+  // rows per lane: the smallest instantiated RPL with 16 RPL >= r
+  p.rpl = 0;
+  for (int v : CQ_RPLS)
+    if (p.rpl == 0 && 16 * v >= r) p.rpl = v;
   // column stride of the LDS slab: rp = 16 (mod 32) doubles puts consecutive
-  // columns on opposite halves of the LDS banks
-  p.rp = (int)(rup(r + 16, 32) - 16);
+  // columns on opposite halves of the LDS banks; rp >= 16 RPL
+  p.rp = (int)(rup(std::max(r, 16 * p.rpl) + 16, 32) - 16);
   int64_t G = cdiv(c, 32);
   if (G > ncu) G = ncu;
   if (G < 1) G = 1;
@@ -470,7 +492,7 @@ CpqrPlan plan_cpqr(int r, int64_t c, int k, int ncu) {
   p.cs = cdiv(c, G);
   p.lds = cpqr_lds_bytes(p.cs, p.rp, k);
   p.slot_len = 3 + p.rp;
-  p.ok = p.lds <= 150 * 1024 && r <= 256 && k <= 256 && k <= r && k <= c;
+  p.ok = p.lds <= 150 * 1024 && r <= 256 && k <= 256 && k <= r && k <= c && p.rpl > 0;
   return p;
 }
 
@@ -498,7 +520,13 @@ hipError_t launch_cpqr(bool b_f32, const void* Bt, int64_t ldb, int r, int64_t c
   hipError_t e = launch_fill_u32(a.tags, 0u, (2 * p.G + 1) * FLAG_STRIDE, s);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  const void* fn = b_f32 ? (const void*)cpqr_kernel<float> : (const void*)cpqr_kernel<double>;
+  const void* fn = nullptr;
+#define RSVD_CQ(V)                                                                       \
+  if (p.rpl == V)                                                                        \
+    fn = b_f32 ? (const void*)cpqr_kernel<float, V> : (const void*)cpqr_kernel<double, V>;
+  RSVD_CQ(2) RSVD_CQ(4) RSVD_CQ(8) RSVD_CQ(12) RSVD_CQ(13) RSVD_CQ(14) RSVD_CQ(16)
+#undef RSVD_CQ
+  if (!fn) return hipErrorInvalidValue;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
   if (e != hipSuccess) return e;
   e = hipLaunchKernel(fn, dim3(p.G), dim3(CQ_NT), args, p.lds, s);

@@ -148,7 +148,7 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
 struct CpqrPlan {
   int G;
   int64_t cs;
-  int rp;
+  int rp, rpl;                       // LDS column stride, rows per lane / 16
   size_t lds;
   int64_t slot_len;
   bool ok;
