@@ -4,9 +4,9 @@
 // applied twice (CholeskyQR2) so that Q is orthonormal to working precision.
 //
 // Kernels here:
-//  * chol_kernel: one workgroup of 8 waves factors an lp x lp Gram matrix
-//    (lp <= 256) held in 16x16 matrix-core accumulator tiles (right-looking,
-//    block size 16).  It writes R (upper triangular, zero below), the inverses
+//  * chol_kernel: one workgroup factors an lp x lp Gram matrix (lp <= 256)
+//    held in 16x16 matrix-core accumulator tiles (right-looking, block size
+//    16, one-step lookahead).  It writes R (upper triangular, zero below), the inverses
 //    of its 16x16 diagonal blocks, and a flag per column.  A column whose
 //    Schur pivot is not above eta * G_jj (numerically dependent on the
 //    columns before it) gets a unit row in R, so it is removed from the
@@ -37,12 +37,10 @@ constexpr double NI_TAU2 = 2.5e-17;   // bound on ||G - I||_F^2 (about a quarter
 // ||G - I||_F^2 of the second Gram below which an FP32 basis is the first
 // pass rounded to FP32: (2^-30)^2, far below the FP32 unit roundoff 2^-24
 constexpr double TRSM_SKIP2 = 0x1.0p-60;
-constexpr int CH_NT = 512;
-constexpr int CH_NW = CH_NT / 64;  // waves
 constexpr int MAXNB = 16;          // lp <= 256
-constexpr int MAXT = MAXNB * (MAXNB + 1) / 2;
-
-__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+// LDS row stride of the Cholesky's panel row (doubles): rows k and k+1 fall
+// on different halves of the banks
+constexpr int CH_LDP = 272;
 
 // Tile t of the row-major enumeration of the upper triangle of an nb x nb
 // tile grid: row a starts at t = a*nb - a*(a-1)/2.  Arguments are uniform.
@@ -65,24 +63,37 @@ __device__ __forceinline__ d4 load_gtile(const double* G, int64_t ldg, int l, in
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = a * 16 + drow(lane >> 4, v);
-    double x;
-    if (row < l && col < l) {
-      x = (row <= col) ? G[(int64_t)row * ldg + col] : G[(int64_t)col * ldg + row];
-    } else {
-      x = (row == col) ? 1.0 : 0.0;
-    }
-    t[v] = x;
+    // one load per element (clamped address), no branches
+    const bool in = row < l && col < l;
+    const int64_t off = in ? (int64_t)min(row, col) * ldg + max(row, col) : 0;
+    const double g = G[off];
+    t[v] = in ? g : ((row == col) ? 1.0 : 0.0);
   }
   return t;
 }
 
-template <int TPW>   // tiles per wave: ceil(nb (nb + 1) / 2 / 16)
-__global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ G, int64_t ldg,
-                                                     int l, int lp, double eta,
-                                                     double* __restrict__ R, int64_t ldr,
-                                                     double* __restrict__ Rdinv,
-                                                     int32_t* __restrict__ dep, int32_t* info,
-                                                     const double* __restrict__ ni_part) {
+// Right-looking block Cholesky with a one-step lookahead, one workgroup of
+// NW waves.  Waves 1 .. NW-1 hold the upper 16x16 tiles of G in matrix-core
+// accumulator layout (tile t of the row-major enumeration of the upper
+// triangle lives in slot t / (NW-1) of wave 1 + t % (NW-1)); wave 0 owns no
+// tile and factors the diagonal blocks.  Block step s has two phases:
+//   1. wave 0 takes the diagonal tile (s, s), which its owner handed over in
+//      the previous step with the panels 0 .. s-2 applied, applies panel
+//      s-1 and factors it (R_ss and X = R_ss^{-1}); meanwhile the other waves
+//      apply panel s-1 to every tile of rows >= s, and the owner of
+//      (s+1, s+1) hands that tile over for the next step;
+//   2. the owners of the tiles (s, b), b > s, form the panel row
+//      R_sb = X^T G_sb (rows of dependent columns zeroed) in LDS and in R.
+// The panel lives in LDS (16 x lp, one buffer: phase 2 of a step writes it
+// after phase 1 has read the previous one).
+template <int NW, int TPW>
+__global__ __launch_bounds__(64 * NW) void chol_kernel(const double* __restrict__ G, int64_t ldg,
+                                                       int l, int lp, double eta,
+                                                       double* __restrict__ R, int64_t ldr,
+                                                       double* __restrict__ Rdinv,
+                                                       int32_t* __restrict__ dep, int32_t* info,
+                                                       const double* __restrict__ ni_part) {
+  constexpr int NT = 64 * NW, NU = NW - 1;
   const int nb = lp / 16;
   if (ni_part != nullptr) {
     // the near-identity test: the blocks' parts of ||G - I||_F^2, added in a
@@ -95,108 +106,110 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
 
-  __shared__ double Dss[16 * 17];        // diagonal block being factored
-  __shared__ double Xss[16 * 16];        // its inverse
-  __shared__ double P[16 * 256];         // row panel of R (rows s*16 .. s*16+15)
-  __shared__ double Tw[CH_NW][16 * 16]; // per-wave transpose scratch
-  __shared__ int depblk[16];
+  __shared__ double P[16 * CH_LDP];     // panel row of R (rows 16s .. 16s+15)
+  __shared__ double Dn[2][16 * 17];     // diagonal tile handed to wave 0
+  __shared__ double Dw[16 * 17];        // wave 0: the updated diagonal tile
+  __shared__ double Rs[16 * 16];        // R_ss, row-major
+  __shared__ double Xs[16 * 16];        // R_ss^{-1}, row-major
+  __shared__ double dinvs[16];          // 1 / R_ss[j][j]
   __shared__ double diag0[256];
-  __shared__ double rowb[16];           // row j of R_ss (diagonal-block step j)
-  __shared__ double xcb[16];            // column j of R_ss^{-1}
+  __shared__ int depblk[16];
 
-  for (int j = tid; j < lp; j += CH_NT) diag0[j] = (j < l) ? G[(int64_t)j * ldg + j] : 1.0;
+  for (int j = tid; j < lp; j += NT) diag0[j] = (j < l) ? G[(int64_t)j * ldg + j] : 1.0;
   // zero the strictly lower part of R
-  for (int r = 1 + (tid >> 6); r < lp; r += CH_NT / 64)
-    for (int c = tid & 63; c < r; c += 64) R[(int64_t)r * ldr + c] = 0.0;
-  __syncthreads();
-  const int ntiles = nb * (nb + 1) / 2;
+  for (int r = 1 + wave; r < lp; r += NW)
+    for (int c = lane; c < r; c += 64) R[(int64_t)r * ldr + c] = 0.0;
 
+  // slot table of an update wave: lane q holds (a | b << 8) of slot q's tile
+  // (a = 255: no tile)
+  const int ntiles = nb * (nb + 1) / 2;
+  int coord = 255;
+  if (wave > 0 && lane < TPW) {
+    const int t = (wave - 1) + NU * lane;
+    if (t < ntiles) {
+      int a = 0;
+      while (a + 1 < nb && (a + 1) * nb - (a + 1) * a / 2 <= t) ++a;
+      const int b = a + (t - (a * nb - a * (a - 1) / 2));
+      coord = a | (b << 8);
+    }
+  }
   d4 acc[TPW];
-  int ta[TPW], tb[TPW];      // tile coordinates (wave-uniform); ta = nb marks no tile
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int t = wave + CH_NW * q;
-    ta[q] = (t < ntiles) ? tile_row(t, nb) : nb;
-    tb[q] = (t < ntiles) ? tile_col(t, nb) : nb;
-    if (t < ntiles) acc[q] = load_gtile(G, ldg, l, ta[q], tb[q], lane);
-    else acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  }
-
-  for (int s = 0; s < nb; ++s) {
-    // (a) the owner of tile (s, s) hands it to LDS
+    const int ab = __builtin_amdgcn_readlane(coord, q);
+    const int a = ab & 255, b = ab >> 8;
+    // (a slot without a tile reads identity values: no branch around the loads)
+    acc[q] = load_gtile(G, ldg, l, a, b, lane);
+    if (a == 0 && b == 0) {
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      if (ta[q] == s && tb[q] == s) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Dss[drow(lk, v) * 17 + li] = acc[q][v];
-      }
+      for (int v = 0; v < 4; ++v) Dn[0][drow(lk, v) * 17 + li] = acc[q][v];
     }
-    __syncthreads();
-    // (b) wave 0 factors the 16x16 block held in its 64 lanes (accumulator
-    // layout: lane (g, c) element v is row 4v + g, column c) and builds
-    // X = R_ss^{-1} alongside, column by column:
-    //   X[r][j] = (delta_rj - S_r[j]) / R[j][j],  S_r[b] += X[r][j] R[j][b] (b > j),
-    // where S_r[b] = sum_{a<b} X[r][a] R[a][b] waits in element (r, b) of y.
-    // Row j of R and column j of X reach every lane through two 16-entry
-    // LDS buffers; the pivot is read as a uniform value.
-    if (wave == 0) {
-      const int g = lk, c = li;
-      double x[4], y[4];
+  }
+  __syncthreads();
+
+  // Wave 0 and the update waves run separate loops over s that meet at the
+  // same two barriers per step, so the tiles' registers are live only in the
+  // update waves' loop.
+  if (wave == 0) {
+    for (int s = 0; s < nb; ++s) {
+      // (1, wave 0) the diagonal tile with panel s-1 applied, in accumulator
+      // layout, then as columns: lane c (all four row groups alike) holds
+      // x[a] = G'[a][c]
+      d4 t;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { x[v] = Dss[drow(g, v) * 17 + c]; y[v] = 0.0; }
-      // lane c holds the dependence threshold of column c of the block; the
-      // column flags are collected in two wave-uniform masks and written
-      // after the block
+      for (int v = 0; v < 4; ++v) t[v] = Dn[s & 1][drow(lk, v) * 17 + li];
+      if (s > 0) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double pv = P[(4 * kk + lk) * CH_LDP + s * 16 + li];
+          t = Mfma<double>::mma(-pv, pv, t);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dw[drow(lk, v) * 17 + li] = t[v];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // c = li through an opaque move, so that the per-lane constants derived
+      // from it are formed here and not kept live across the whole s loop
+      int c;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(c) : "v"(li));
+      double x[16];
+#pragma unroll
+      for (int a = 0; a < 16; ++a) x[a] = Dw[a * 17 + c];
+      // right-looking elimination inside the block: step j takes the pivot
+      // d = G'[j][j] from lane j and turns x[j] into row j of R (lane c >= j
+      // gets x[j] / sqrt(d), which is sqrt(d) itself in lane j), then
+      // subtracts R[j][a] R[j][c] from the rows a > j.  Lanes c < j compute
+      // values that are never read (rows below the diagonal are dropped at
+      // the end).  A column whose pivot is not above eta * G_jj gets a unit
+      // row.
       const double thr = eta * diag0[s * 16 + c];
       uint32_t okm = 0u, nfm = 0u;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int vj = j >> 2, gj = j & 3;
-        const double d = readlane_d(x[vj], 16 * gj + j);      // Schur pivot G'[j][j]
-        const bool finite = isfinite(d);
+        const double d = readlane_d(x[j], j);
+        const bool finite = __builtin_isfinite(d);
         const bool ok = finite && d > readlane_d(thr, j);
         okm |= ok ? (1u << j) : 0u;
         nfm |= finite ? 0u : (1u << j);
-        const double inv = ok ? rsq_nr(d) : 1.0;             // 1 / R[j][j]
-        const double rjj = ok ? d * inv : 1.0;
-        if (g == gj) {
-          // this lane holds G'[j][c]: row j of R, and (lane c == j) column j of X
-          double rj;
-          if (c == j) rj = rjj;
-          else if (c > j) rj = ok ? x[vj] * inv : 0.0;
-          else rj = 0.0;
-          rowb[c] = rj;
-        }
-        if (c == j) {
+        // branch-free: the estimate is formed for any d and then selected
+        const double inv0 = rsq_nr(d);
+        const double inv = ok ? inv0 : 1.0;
+        const double r = ok ? x[j] * inv0 : ((c == j) ? 1.0 : 0.0);
+        x[j] = r;
+        if (lane == 0) dinvs[j] = inv;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = drow(g, v);
-            y[v] = ((r == j ? 1.0 : 0.0) - y[v]) * inv;
-            xcb[r] = y[v];
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double rjc = rowb[c];                           // R[j][c]
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = drow(g, v);
-          const double rja = rowb[a];                         // R[j][a]
-          const double xaj = xcb[a];                          // X[a][j]
-          if (a > j && a <= c) x[v] = fma(-rja, rjc, x[v]);
-          if (a == j) x[v] = rjc;
-          if (c > j) y[v] = fma(xaj, rjc, y[v]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int a = j + 1; a < 16; ++a) x[a] = fma(-readlane_d(r, a), r, x[a]);
       }
+      // R_ss to LDS (the four row groups of the wave hold the same columns
+      // and store the same values); the update waves copy it to R in phase 2
+#pragma unroll
+      for (int a = 0; a < 16; ++a) Rs[a * 16 + c] = (a <= c) ? x[a] : 0.0;
       if (lane < 16) {
-        const int gcol = s * 16 + lane;
-        const int dj = ((okm >> lane) & 1u) ? 0 : 1;
-        depblk[lane] = dj;
-        if (gcol < l) dep[gcol] = dj;
+        const int dj = ((okm >> c) & 1u) ? 0 : 1;
+        depblk[c] = dj;
+        if (s * 16 + c < l) dep[s * 16 + c] = dj;
       }
       if (lane == 0) {
         // columns of the block below l that failed the test
@@ -205,63 +218,94 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const double* __restrict__ 
         if ((bad & nfm) != 0u) info_or(info, INFO_NONFINITE);
         if ((bad & ~nfm) != 0u) info_or(info, INFO_ORTH_FALLBACK);
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // X = R_ss^{-1}, column c in lane c by back substitution (the entries
+      // below the diagonal come out zero).  Row a of R is read from LDS (the
+      // same address in every lane); the terms of rows b > a+1 are summed in
+      // two chains before X[a+1] is known, so each row adds one product to
+      // the dependent chain.
+      double X[16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = drow(g, v);
-        if (a > c) x[v] = 0.0;
-        R[(int64_t)(s * 16 + a) * ldr + s * 16 + c] = x[v];
-        Xss[a * 16 + c] = y[v];
-        Rdinv[(int64_t)s * 256 + a * 16 + c] = y[v];
+      for (int a = 15; a >= 0; --a) {
+        double u0 = (a == c) ? 1.0 : 0.0, u1 = 0.0;
+#pragma unroll
+        for (int b = 15; b > a + 1; --b) {
+          if ((b & 1) == 0) u0 = fma(-Rs[a * 16 + b], X[b], u0);
+          else u1 = fma(-Rs[a * 16 + b], X[b], u1);
+        }
+        double u = u0 + u1;
+        if (a < 15) u = fma(-Rs[a * 16 + a + 1], X[a + 1], u);
+        X[a] = u * dinvs[a];
       }
+#pragma unroll
+      for (int a = 0; a < 16; ++a) Xs[a * 16 + c] = X[a];
+      __syncthreads();
+      __syncthreads();   // (2) the update waves form the panel row
     }
-    __syncthreads();
-    // (c) panel: R_sb = R_ss^{-T} G_sb for b > s, zero rows of dependent columns
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      if (ta[q] == s && tb[q] > s && tb[q] < nb) {
-        const int b = tb[q];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Tw[wave][drow(lk, v) * 16 + li] = acc[q][v];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        d4 r = d4{0.0, 0.0, 0.0, 0.0};
+  } else {
+    for (int s = 0; s < nb; ++s) {
+      // (1, update waves) panel s-1 on every tile of rows >= s but (s, s);
+      // the k-steps run outermost so that consecutive products go to
+      // different tiles
+      if (s > 0) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + lk;
-          const double av = Xss[k * 16 + li];          // (R_ss^{-T})[li][k]
-          const double bv = Tw[wave][k * 16 + li];     // G_sb[k][li]
-          r = Mfma<double>::mma(av, bv, r);
-        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = drow(lk, v);
-          const double x = depblk[row] ? 0.0 : r[v];
-          r[v] = x;
-          P[row * 256 + b * 16 + li] = x;
-          R[(int64_t)(s * 16 + row) * ldr + b * 16 + li] = x;
+          for (int q = 0; q < TPW; ++q) {
+            const int ab = __builtin_amdgcn_readlane(coord, q);
+            const int a = ab & 255, b = ab >> 8;
+            if (a >= s && a < nb && b > s) {
+              const double av = -P[k * CH_LDP + a * 16 + li];
+              const double bv = P[k * CH_LDP + b * 16 + li];
+              acc[q] = Mfma<double>::mma(av, bv, acc[q]);
+            }
+          }
+          // (operands of one k-step at a time in registers)
+          __builtin_amdgcn_sched_barrier(0);
         }
-        acc[q] = r;
       }
-    }
-    __syncthreads();
-    // (d) trailing update: G_ab -= R_sa^T R_sb for s < a <= b; the k-steps
-    // run outermost so that consecutive products go to different tiles
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kk + lk;
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        if (ta[q] > s && ta[q] < nb) {
-          const double av = -P[k * 256 + ta[q] * 16 + li];
-          const double bv = P[k * 256 + tb[q] * 16 + li];
-          acc[q] = Mfma<double>::mma(av, bv, acc[q]);
+        const int ab = __builtin_amdgcn_readlane(coord, q);
+        if (ab == ((s + 1) | ((s + 1) << 8))) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Dn[(s + 1) & 1][drow(lk, v) * 17 + li] = acc[q][v];
         }
       }
+      __syncthreads();
+      // (2) panel row s: R_sb = X^T G_sb.  The accumulator layout of G_sb is
+      // the B-operand layout of the k-steps (element kk of lane (i, g) is
+      // row 4 kk + g, column i).  The update waves also copy R_ss and its
+      // inverse from LDS to R and Rdinv.
+      for (int e = tid - 64; e < 512; e += NT - 64) {
+        if (e < 256) R[(int64_t)(s * 16 + (e >> 4)) * ldr + s * 16 + (e & 15)] = Rs[e];
+        else Rdinv[(int64_t)s * 256 + (e - 256)] = Xs[e - 256];
+      }
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int ab = __builtin_amdgcn_readlane(coord, q);
+        const int a = ab & 255, b = ab >> 8;
+        if (a == s && b > s) {
+          d4 r = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            r = Mfma<double>::mma(Xs[(4 * kk + lk) * 16 + li], acc[q][kk], r);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = drow(lk, v);
+            const double x = depblk[row] ? 0.0 : r[v];
+            P[row * CH_LDP + b * 16 + li] = x;
+            R[(int64_t)(s * 16 + row) * ldr + b * 16 + li] = x;
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
-
 
 // Workgroup c takes rows 16c .. 16c+15: it writes those rows of R = I + Phi(G - I)
 // (zero below the diagonal, identity in the padding), the inverse
@@ -315,13 +359,17 @@ __global__ __launch_bounds__(NI_NT) void chol_ni_kernel(const double* __restrict
   }
 }
 
-// Q = Y R^{-1}: one wave per 16 rows of Y, column block by column block, in
-// transposed form Q_c^T = R_cc^{-T} (Y_c^T - sum_{b<c} R_bc^T Q_b^T).  The
-// accumulator layout of a 16x16 product (lane (j, g) holds rows 4v + g of
-// column j) is also the B-operand layout of the next products, so every
-// Q_b^T stays in registers (4 doubles per lane) from the step that makes it
-// to the last column block, and the wave needs no LDS and no barrier.
-// R_bc^T and R_cc^{-T} are read as A operands straight from memory (L2).
+// Q = Y R^{-1}: a workgroup of 4 waves takes 64 rows of Y (a wave 16),
+// column block by column block, in transposed form
+// Q_c^T = R_cc^{-T} (Y_c^T - sum_{b<c} R_bc^T Q_b^T).  The accumulator layout
+// of a 16x16 product (lane (j, g) holds rows 4v + g of column j) is also the
+// B-operand layout of the next products, so every Q_b^T stays in registers
+// (4 doubles per lane) from the step that makes it to the last column block.
+// The A operands of column block c (-R_bc for b < c, then R_cc^{-1}) are
+// staged in LDS in operand order, shared by the four waves and double
+// buffered: thread (kk, lane) fetches the k-step kk operands of the next
+// column (and each wave its next Y values) into registers while the current
+// column is multiplied, and one barrier per column block separates the two.
 template <typename TY, typename TQ, int NB>
 __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int64_t ldy,
                                                    int64_t M, int l, int lp,
@@ -329,18 +377,20 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
                                                    const double* __restrict__ Rdinv,
                                                    TQ* __restrict__ Q, int64_t ldq,
                                                    const double* __restrict__ skip_part) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double Rb[2][NB * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  if (row0 >= M) return;
   const int nb = lp / 16;
-  const int64_t r = row0 + li;
+  // (a wave past the last row still stages its share of the operands)
+  const int64_t r = ((int64_t)blockIdx.x * 4 + wave) * 16 + li;
   const bool rok = r < M;
   const TY* yr = Y + (rok ? r : 0) * ldy;
   TQ* qr = Q + (rok ? r : 0) * ldq;
   if (skip_part) {
-    // ||Y^T Y - I||_F^2 from its parts (the same order on every thread): when
-    // Y is orthonormal to within TRSM_SKIP2, Q = Y rounded to TQ
+    // ||Y^T Y - I||_F^2 from its parts (the same order on every thread, so
+    // the whole workgroup takes the same branch): when Y is orthonormal to
+    // within TRSM_SKIP2, Q = Y rounded to TQ
     double e2 = 0.0;
     for (int c = 0; c < nb; ++c) e2 += skip_part[c];
     if (e2 <= TRSM_SKIP2) {
@@ -354,36 +404,55 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
       return;
     }
   }
+  double pre[NB], ypre[4];
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i < c) pre[i] = -R[(int64_t)(i * 16 + 4 * wave + lk) * ldr + c * 16 + li];
+      else if (i == c) pre[i] = Rdinv[(int64_t)c * 256 + (4 * wave + lk) * 16 + li];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = c * 16 + 4 * v + lk;
+      ypre[v] = (rok && col < l) ? (double)yr[col] : 0.0;
+    }
+  };
+  auto stash = [&](int c) {
+    double* rb = Rb[c & 1];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      if (i <= c) rb[i * 256 + wave * 64 + lane] = pre[i];
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
   d4 qt[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < nb) {
       d4 acc;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = c * 16 + 4 * v + lk;
-        acc[v] = (rok && col < l) ? (double)yr[col] : 0.0;
-      }
+      for (int v = 0; v < 4; ++v) acc[v] = ypre[v];
+      if (c + 1 < nb) fetch(c + 1);
+      const double* rb = Rb[c & 1];
 #pragma unroll
       for (int b = 0; b < c; ++b) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const double av = -R[(int64_t)(b * 16 + 4 * kk + lk) * ldr + c * 16 + li];  // R_bc[k][i]
-          acc = Mfma<double>::mma(av, qt[b][kk], acc);
-        }
+        for (int kk = 0; kk < 4; ++kk)
+          acc = Mfma<double>::mma(rb[b * 256 + kk * 64 + lane], qt[b][kk], acc);  // -R_bc[k][i]
       }
       d4 out = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double av = Rdinv[(int64_t)c * 256 + (4 * kk + lk) * 16 + li];  // Rinv_cc[k][i]
-        out = Mfma<double>::mma(av, acc[kk], out);
-      }
+      for (int kk = 0; kk < 4; ++kk)
+        out = Mfma<double>::mma(rb[c * 256 + kk * 64 + lane], acc[kk], out);  // Rinv_cc[k][i]
       qt[c] = out;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = c * 16 + 4 * v + lk;
         if (rok && col < l) qr[col] = (TQ)out[v];
       }
+      if (c + 1 < nb) stash(c + 1);
+      __syncthreads();
     }
   }
 }
@@ -682,23 +751,25 @@ hipError_t launch_chol(const double* G, int64_t ldg, int l, int lp, double eta, 
                        double* ni_part) {
   if (lp > 256 || lp % 16) return hipErrorInvalidValue;
   const int nb = lp / 16;
-  const int tpw = (int)cdiv(nb * (nb + 1) / 2, CH_NW);
+  const int tiles = nb * (nb + 1) / 2;
   if (ni_part != nullptr) {
     hipLaunchKernelGGL(chol_ni_kernel, dim3(nb), dim3(NI_NT), 0, s, G, ldg, l, lp, R, ldr, Rdinv,
                        dep, ni_part);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-#define RSVD_CHOL(T)                                                                          \
-  hipLaunchKernelGGL(chol_kernel<T>, dim3(1), dim3(CH_NT), 0, s, G, ldg, l, lp, eta, R, ldr, \
+  // 8 waves: wave 0 factors the diagonal blocks, 7 hold the tiles (2 waves
+  // per SIMD leave each up to 256 registers)
+#define RSVD_CHOL(T)                                                                        \
+  hipLaunchKernelGGL((chol_kernel<8, T>), dim3(1), dim3(512), 0, s, G, ldg, l, lp, eta, R, ldr, \
                      Rdinv, dep, info, ni_part)
+  const int tpw = (int)cdiv(tiles, 7);
   if (tpw <= 1) RSVD_CHOL(1);
   else if (tpw <= 2) RSVD_CHOL(2);
   else if (tpw <= 4) RSVD_CHOL(4);
-  else if (tpw <= 7) RSVD_CHOL(7);
-  else if (tpw <= 10) RSVD_CHOL(10);
-  else if (tpw <= 14) RSVD_CHOL(14);
-  else RSVD_CHOL(17);
+  else if (tpw <= 8) RSVD_CHOL(8);
+  else if (tpw <= 15) RSVD_CHOL(15);
+  else RSVD_CHOL(20);
 #undef RSVD_CHOL
   return hipGetLastError();
 }
