@@ -26,6 +26,8 @@
 //  * replace_kernel: overwrites flagged columns of Q with fresh Gaussian
 //    vectors (Philox stream 7) scaled to unit expected norm.
 //  * trmm_kernel: R = R2 R1 for the two passes.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -41,6 +43,17 @@ constexpr int MAXNB = 16;          // lp <= 256
 // LDS row stride of the Cholesky's panel row (doubles): rows k and k+1 fall
 // on different halves of the banks
 constexpr int CH_LDP = 272;
+
+// f(integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices)
+template <int I, int N, typename F> __device__ __forceinline__ void static_for_(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>());
+    static_for_<I + 1, N>(f);
+  }
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F&& f) {
+  static_for_<0, N>(f);
+}
 
 // Tile t of the row-major enumeration of the upper triangle of an nb x nb
 // tile grid: row a starts at t = a*nb - a*(a-1)/2.  Arguments are uniform.
@@ -405,16 +418,22 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
     }
   }
   double pre[NB], ypre[4];
-  auto fetch = [&](int c) {
+  // operands of column block c (compile-time slot count) read at column cf
+  // (equal to c but past the last block, where the values go unused); no
+  // branches around the loads, so they stay in flight across the products
+  auto fetch = [&](auto cc, int cf) {
+    constexpr int c = decltype(cc)::value;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      if (i < c) pre[i] = -R[(int64_t)(i * 16 + 4 * wave + lk) * ldr + c * 16 + li];
-      else if (i == c) pre[i] = Rdinv[(int64_t)c * 256 + (4 * wave + lk) * 16 + li];
+      if (i < c) pre[i] = -R[(int64_t)(i * 16 + 4 * wave + lk) * ldr + cf * 16 + li];
+      else if (i == c) pre[i] = Rdinv[(int64_t)cf * 256 + (4 * wave + lk) * 16 + li];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int col = c * 16 + 4 * v + lk;
-      ypre[v] = (rok && col < l) ? (double)yr[col] : 0.0;
+      const int col = cf * 16 + 4 * v + lk;
+      const bool ok = rok && col < l;
+      const double y = (double)yr[ok ? col : 0];
+      ypre[v] = ok ? y : 0.0;
     }
   };
   auto stash = [&](int c) {
@@ -423,17 +442,19 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
     for (int i = 0; i < NB; ++i)
       if (i <= c) rb[i * 256 + wave * 64 + lane] = pre[i];
   };
-  fetch(0);
+  fetch(std::integral_constant<int, 0>(), 0);
   stash(0);
   __syncthreads();
   d4 qt[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
+  static_for<NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
     if (c < nb) {
       d4 acc;
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[v] = ypre[v];
-      if (c + 1 < nb) fetch(c + 1);
+      if constexpr (c + 1 < NB) fetch(std::integral_constant<int, c + 1>(), min(c + 1, nb - 1));
+      // (the loads issue before the products)
+      __builtin_amdgcn_sched_barrier(0);
       const double* rb = Rb[c & 1];
 #pragma unroll
       for (int b = 0; b < c; ++b) {
@@ -454,7 +475,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(const TY* __restrict__ Y, int
       if (c + 1 < nb) stash(c + 1);
       __syncthreads();
     }
-  }
+  });
 }
 
 // Replace every flagged column j of Q (M rows) by N(0, 1/M) entries from

@@ -92,16 +92,18 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 #pragma unroll
       for (int j = 0; j < CBW; ++j) acc[i][j] = Mfma<TC>::zero();
 
-    TC ra[4];
-    TC rx[CBW];
-
-    // Next-step loads.  FP64 (CLAMP): clamped addresses, so every load is
-    // issued without a branch around it, and out-of-range elements are
-    // zeroed only when they are written to LDS (no wait for the loads comes
-    // before that).  FP32: guarded loads, which measured faster there.
+    // One step's loads in registers (a stage).  FP64 (CLAMP): clamped
+    // addresses, so every load is issued without a branch around it, and
+    // out-of-range elements are zeroed only when they are written to LDS (no
+    // wait for the loads comes before that).  FP32: guarded loads, which
+    // measured faster there.
     constexpr bool CLAMP = sizeof(TC) == 8;
-    bool oka[4], okx[CBW];
-    auto gload = [&](int64_t kt) {
+    struct Stage {
+      TC ra[4];
+      TC rx[CBW];
+      bool oka[4], okx[CBW];
+    };
+    auto gload = [&](Stage& st, int64_t kt) {
       const int64_t k0 = kt * BK;
       if (!TRANS) {
         const int64_t gi = row0 + a_r;
@@ -110,9 +112,9 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int64_t gk = k0 + a_c + c;
-          oka[c] = rok && gk < g.K;
-          if (CLAMP) ra[c] = (TC)A[gic * g.lda + (gk < g.K ? gk : g.K - 1)];
-          else ra[c] = oka[c] ? (TC)A[gi * g.lda + gk] : TC(0);
+          st.oka[c] = rok && gk < g.K;
+          if (CLAMP) st.ra[c] = (TC)A[gic * g.lda + (gk < g.K ? gk : g.K - 1)];
+          else st.ra[c] = st.oka[c] ? (TC)A[gi * g.lda + gk] : TC(0);
         }
       } else {
         const int64_t gk = k0 + a_r;
@@ -121,9 +123,9 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int64_t gi = row0 + a_c + c;
-          oka[c] = kok && gi < g.M;
-          if (CLAMP) ra[c] = (TC)A[gkc * g.lda + (gi < g.M ? gi : g.M - 1)];
-          else ra[c] = oka[c] ? (TC)A[gk * g.lda + gi] : TC(0);
+          st.oka[c] = kok && gi < g.M;
+          if (CLAMP) st.ra[c] = (TC)A[gkc * g.lda + (gi < g.M ? gi : g.M - 1)];
+          else st.ra[c] = st.oka[c] ? (TC)A[gk * g.lda + gi] : TC(0);
         }
       }
       const int64_t gk = k0 + x_r;
@@ -132,50 +134,81 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 #pragma unroll
       for (int c = 0; c < CBW; ++c) {
         const int64_t gj = col0 + x_c + c;
-        okx[c] = kok && gj < g.L;
-        if (CLAMP) rx[c] = (TC)X[gkc * g.ldx + (gj < g.L ? gj : g.L - 1)];
-        else rx[c] = okx[c] ? (TC)X[gk * g.ldx + gj] : TC(0);
+        st.okx[c] = kok && gj < g.L;
+        if (CLAMP) st.rx[c] = (TC)X[gkc * g.ldx + (gj < g.L ? gj : g.L - 1)];
+        else st.rx[c] = st.okx[c] ? (TC)X[gk * g.ldx + gj] : TC(0);
       }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](const Stage& st, int buf) {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        As[buf][a_r * ALD + a_c + c] = (CLAMP && !oka[c]) ? TC(0) : ra[c];
+        As[buf][a_r * ALD + a_c + c] = (CLAMP && !st.oka[c]) ? TC(0) : st.ra[c];
 #pragma unroll
       for (int c = 0; c < CBW; ++c)
-        Xs[buf][x_r * BN + x_c + c] = (CLAMP && !okx[c]) ? TC(0) : rx[c];
+        Xs[buf][x_r * BN + x_c + c] = (CLAMP && !st.okx[c]) ? TC(0) : st.rx[c];
     };
-
-    gload(kb);
-    sstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t kt = kb; kt < ke; ++kt) {
-      const bool more = kt + 1 < ke;
-      if (!CLAMP && more) gload(kt + 1);
+    // the products of one k-step from LDS buffer b; at_kk0 runs inside the
+    // unrolled k loop before its first products (the scheduler spreads the
+    // next loads among them: measured Y = AX 1.75 -> 1.62 ms)
+    auto compute = [&](int b, auto&& at_kk0) {
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        // FP64: issued inside the unrolled k loop, which lets the scheduler
-        // spread the loads among the first MFMAs (measured: Y = AX 1.75 ->
-        // 1.62 ms)
-        if (CLAMP && kk == 0 && more) gload(kt + 1);
+        if (kk == 0) at_kk0();
         const int k = kk * 4 + lk;
         TC av[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
           const int i = wr * 32 + rb * 16 + li;
-          av[rb] = TRANS ? As[buf][k * ALD + i] : As[buf][i * ALD + k];
+          av[rb] = TRANS ? As[b][k * ALD + i] : As[b][i * ALD + k];
         }
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb) {
-          const TC bv = Xs[buf][k * BN + wc * 16 * CBW + cb * 16 + li];
+          const TC bv = Xs[b][k * BN + wc * 16 * CBW + cb * 16 + li];
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) acc[rb][cb] = Mfma<TC>::mma(av[rb], bv, acc[rb][cb]);
         }
       }
-      if (more) sstore(buf ^ 1);
+    };
+
+    if constexpr (CLAMP && CBW <= 7) {
+      // FP64: two stages, so that a step's loads are issued two steps before
+      // they are stored to LDS (the latency of loads under the pass's
+      // traffic exceeds one step's products).  Two steps per iteration keep
+      // each stage in its own registers.  Loads past the range re-read its
+      // last step; their stores are skipped.  (CBW = 8 keeps one stage: the
+      // second does not fit its registers; measured slower.)
+      Stage s0, s1;
+      gload(s0, kb);
+      sstore(s0, 0);
+      gload(s1, min(kb + 1, ke - 1));
       __syncthreads();
-      buf ^= 1;
+      for (int64_t kt = kb; kt < ke; kt += 2) {
+        // step kt (buffer 0): s1 holds step kt + 1, s0 receives kt + 2
+        compute(0, [&]() { gload(s0, min(kt + 2, ke - 1)); });
+        if (kt + 1 < ke) sstore(s1, 1);
+        __syncthreads();
+        if (kt + 1 >= ke) break;
+        // step kt + 1 (buffer 1): s0 holds step kt + 2, s1 receives kt + 3
+        compute(1, [&]() { gload(s1, min(kt + 3, ke - 1)); });
+        if (kt + 2 < ke) sstore(s0, 0);
+        __syncthreads();
+      }
+    } else {
+      Stage s0;
+      gload(s0, kb);
+      sstore(s0, 0);
+      __syncthreads();
+      int buf = 0;
+      for (int64_t kt = kb; kt < ke; ++kt) {
+        const bool more = kt + 1 < ke;
+        if (!CLAMP && more) gload(s0, kt + 1);
+        compute(buf, [&]() {
+          if (CLAMP && more) gload(s0, kt + 1);
+        });
+        if (more) sstore(s0, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
     }
 
     const bool full = (kb == 0) && (ke == g.KI);
