@@ -38,8 +38,8 @@ PEAK_FP8_TFLOPS = 5000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "3eb916b52bbb3f0885a0fcfdeb517bd2e43f92a247376d6f498c9c7765f36468",
-                "bytes": 4588310000}
+PASS_TRAFFIC = {"sources": "aa1e8aa7df0265214626108cfb544e287dc5d31924b6a306756870eeb87e605f",
+                "bytes": 4589000000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 
 
