@@ -230,6 +230,158 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
   }
 }
 
+// Y = A Xt for a row-major A (the non-transposed pass) with both operands
+// moved from HBM to LDS by the direct-to-LDS loads (global_load_lds_dwordx4),
+// so that several k-steps are in flight without staging registers: four LDS
+// stages of 32-deep k-steps, three of them loading while the fourth is
+// multiplied; one barrier per k-step.  A wave's 16-byte load writes 64
+// consecutive 16-byte slots of LDS, so a staged row (32 k, 64 bytes) holds
+// its four 16-byte chunks in a rotated order (chunk s of row r in slot
+// s ^ ((r >> 2) & 3)): the 16 lanes that read one chunk of 16 consecutive
+// rows then hit 16 different 4-bank groups.  Rows past M or L re-read the last
+// row; k past K re-reads A's last chunk against the zero padding of Xt (so
+// the launch needs K and lda multiples of 8, A 16-byte aligned and
+// ldx >= 32 * ceil(K / 32), Xt zero beyond K).
+constexpr int DK = 32;
+constexpr int DNS = 4;
+typedef __attribute__((address_space(3))) void* lds_vp;
+typedef __attribute__((address_space(1))) void* gbl_vp;
+
+template <int CBW> struct DmaDims {
+  static constexpr int BN = 32 * CBW;
+  static constexpr int ROWS = BM + BN;                 // staged rows per k-step
+  static constexpr int NI = ROWS / 16;                 // 1 KB wave loads per k-step
+  static constexpr int LPW = (NI + NT / 64 - 1) / (NT / 64);   // per wave (a few repeated)
+  static constexpr int STAGE = ROWS * DK;              // elements
+  static constexpr size_t LDS = (size_t)DNS * STAGE * sizeof(uint16_t);
+};
+
+// s_waitcnt that waits until at most n vector-memory operations are in
+// flight (lgkm and exp counters left alone)
+template <int N> __device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int CBW>
+__global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
+  using D = DmaDims<CBW>;
+  constexpr int BN = D::BN;
+  extern __shared__ __attribute__((aligned(16))) uint16_t dsm[];   // DNS x ROWS x DK
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave & 3;
+  const int wc = wave >> 2;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+
+  const int64_t w = blockIdx.x;
+  int64_t u = range_begin(w, g.U, g.G);
+  const int64_t uend = range_begin(w + 1, g.U, g.G);
+
+  while (u < uend) {
+    const int64_t tile = u / g.KI;
+    const int64_t kb = u - tile * g.KI;
+    const int64_t ke = min(g.KI, kb + (uend - u));
+    u += ke - kb;
+    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t col0 = (tile % g.nct) * BN;
+
+    f4 acc[RB][CBW];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // the loads of k-step kt into stage b
+    auto issue = [&](int64_t kt, int b) {
+      const int64_t k0 = kt * DK;
+#pragma unroll
+      for (int q = 0; q < D::LPW; ++q) {
+        int j = wave + (NT / 64) * q;
+        if (j >= D::NI) j -= D::NI;               // (a repeated load: same data, same slots)
+        const int r = j * 16 + (lane >> 2);       // staged row
+        const int sch = (lane & 3) ^ ((r >> 2) & 3);   // the chunk this slot holds
+        const uint16_t* src;
+        if (r < BM) {
+          const int64_t gi = min(row0 + r, g.M - 1);
+          const int64_t gk = min(k0 + 8 * sch, g.K - 8);
+          src = g.A + gi * g.lda + gk;
+        } else {
+          const int64_t gj = min(col0 + (r - BM), g.L - 1);
+          src = g.X + gj * g.ldx + k0 + 8 * sch;
+        }
+        uint16_t* dst = dsm + (size_t)b * D::STAGE + (size_t)j * 16 * DK;
+        __builtin_amdgcn_global_load_lds((gbl_vp)src, (lds_vp)dst, 16, 0, 0);
+      }
+    };
+
+    const int64_t nst = ke - kb;
+#pragma unroll
+    for (int p = 0; p < DNS - 1; ++p) issue(min(kb + p, ke - 1), p);
+    for (int64_t t = 0; t < nst; ++t) {
+      // this wave's loads of step t are done when at most the later
+      // DNS - 2 steps' loads are in flight; the barrier makes every wave's
+      // visible and frees the stage read at step t - 1
+      wait_vm<(DNS - 2) * D::LPW>();
+      // a plain barrier: __syncthreads' release fence would wait for every
+      // load in flight (the direct-to-LDS loads count as LDS writes)
+      asm volatile("s_barrier" ::: "memory");
+      issue(min(kb + t + DNS - 1, ke - 1), (int)((t + DNS - 1) % DNS));
+      const uint16_t* st = dsm + (size_t)(t % DNS) * D::STAGE;
+      bf8 av[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int r = wr * 16 * RB + rb * 16 + li;
+        av[rb] = *reinterpret_cast<const bf8*>(st + r * DK + 8 * (lk ^ ((r >> 2) & 3)));
+      }
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) {
+        const int r = BM + wc * 16 * CBW + cb * 16 + li;
+        const bf8 bv = *reinterpret_cast<const bf8*>(st + r * DK + 8 * (lk ^ ((r >> 2) & 3)));
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], bv, acc[rb][cb], 0, 0, 0);
+      }
+    }
+    // no load may still be writing LDS when the next tile's first loads go out
+    wait_vm<0>();
+    __syncthreads();
+
+    const bool full = (kb == 0) && (ke == g.KI);
+    if (full) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
+            if (r < g.M && c < g.L) {
+              float* cp = g.C + r * g.ldc + c;
+              *cp = g.accumulate ? *cp + acc[rb][cb][v] : acc[rb][cb][v];
+            }
+          }
+    } else {
+      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      float* P = g.part + slot * (int64_t)(BM * BN);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int c = wc * 16 * CBW + cb * 16 + li;
+            P[r * BN + c] = acc[rb][cb][v];
+          }
+    }
+  }
+}
+
 // Sums the partial tiles of every split tile in workgroup order.
 constexpr int FIX_CHUNK = 1024;
 
@@ -273,6 +425,38 @@ hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
     e = hipGetLastError();
   }
   return e;
+}
+
+template <int CBW>
+hipError_t run_bf16_dma(const Bf16Args& g, hipStream_t s) {
+  const size_t shm = DmaDims<CBW>::LDS;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_dma_kernel<CBW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_bf16_dma_kernel<CBW>), dim3((unsigned)g.G), dim3(NT), shm, s, g);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t T = g.U / g.KI;
+  if (g.G != T) {
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((bf16_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s, g);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t dispatch_bf16_dma(const Bf16Args& g, int cbw, hipStream_t s) {
+  switch (cbw) {
+    case 1: return run_bf16_dma<1>(g, s);
+    case 2: return run_bf16_dma<2>(g, s);
+    case 3: return run_bf16_dma<3>(g, s);
+    case 4: return run_bf16_dma<4>(g, s);
+    case 5: return run_bf16_dma<5>(g, s);
+    case 6: return run_bf16_dma<6>(g, s);
+    case 7: return run_bf16_dma<7>(g, s);
+    case 8: return run_bf16_dma<8>(g, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <bool TRANS>
@@ -366,6 +550,15 @@ hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t*
   g.nct = p.nct; g.KI = p.KI; g.U = p.U; g.G = p.G;
   g.part = static_cast<float*>(part);
   g.accumulate = accumulate ? 1 : 0;
+  // the direct-to-LDS kernel (32-deep k-steps, the same workgroups and tiles)
+  // where its alignment and padding conditions hold
+  const int64_t kid = cdiv(K, DK);
+  if (!trans && K >= 8 && K % 8 == 0 && lda % 8 == 0 && ldx % 8 == 0 && ldx >= kid * DK &&
+      (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(Xt) & 15) == 0) {
+    g.KI = kid;
+    g.U = (p.nrt * p.nct) * kid;
+    return dispatch_bf16_dma(g, p.cbw, s);
+  }
   return trans ? dispatch_bf16<true>(g, p.cbw, s) : dispatch_bf16<false>(g, p.cbw, s);
 }
 }  // namespace

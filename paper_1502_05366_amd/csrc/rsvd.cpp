@@ -245,7 +245,7 @@ size_t layout(const Shape& s, void* base, Bufs* out) {
   b.Q = a.take<char>((size_t)s.m * s.lp * s.dsz);
   b.Z = a.take<char>((size_t)s.n * s.lp * s.dsz);
   b.Zq = a.take<char>((size_t)s.n * s.lp * s.dsz);
-  if (s.bf16) b.Xt = a.take<uint16_t>((size_t)s.lp * rup(std::max(s.m, s.n), 8));
+  if (s.bf16) b.Xt = a.take<uint16_t>((size_t)s.lp * rup(std::max(s.m, s.n), 32));
   if (s.f8) {
     b.f8.xt = a.take<uint8_t>((size_t)2 * s.lp * rup(std::max(s.m, s.n), 16));
     b.f8.t = a.take<float>((size_t)2 * s.lp);
@@ -418,7 +418,7 @@ hipError_t orth(Ctx& c, const OrthBufs& ob, bool y_f32, const void* Y, int64_t l
 
 // One pass over A: Y = A X (trans false) or Y = A^T X (trans true).  atype 0 / 1:
 // X and Y in A's type; atype 2 (BF16 A): X and Y in FP32, X rounded to BF16
-// into xt (l x rup(K, 8)) first.  With split, X = X_hi + X_lo is applied as
+// into xt (l x rup(K, 32), zero past K) first.  With split, X = X_hi + X_lo is applied as
 // two BF16 passes whose FP32 results are added (X kept to ~16 bits).
 hipError_t pass(Ctx& c, int atype, bool trans, int64_t m, int64_t n, int l, const void* A,
                 int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* part,
@@ -454,7 +454,7 @@ hipError_t pass(Ctx& c, int atype, bool trans, int64_t m, int64_t n, int l, cons
     return launch_gemm(atype == 1 ? GEMM_FFFF : GEMM_DDDD, trans, A, lda, X, ldx, Y, ldy, M, K, l,
                        pg, part, part_bytes, c.st);
   }
-  const int64_t ldt = rup(K, 8);
+  const int64_t ldt = rup(K, 32);   // (the BF16 passes read whole 32-deep k-steps of Xt)
   const GemmPlan pg = plan_gemm_bf16(M, K, l, std::min(c.ncu, NCU_CAP));
   RSVD_TRY(launch_convert_bf16(true, X, ldx, K, l, xt, ldt, c.st));
   RSVD_TRY(launch_gemm_bf16(trans, static_cast<const uint16_t*>(A), lda, xt, ldt,
@@ -585,7 +585,7 @@ size_t layout_left(const Shape& s, void* base, LeftBufs* out) {
   b.Ym = a.take<char>((size_t)s.m * s.lp * s.dsz);
   b.Qm = a.take<char>((size_t)s.m * s.lp * s.dsz);
   b.Qn = a.take<char>((size_t)s.n * s.lp * s.dsz);
-  b.Xt = s.bf16 ? a.take<uint16_t>((size_t)s.lp * rup(rmax, 8)) : nullptr;
+  b.Xt = s.bf16 ? a.take<uint16_t>((size_t)s.lp * rup(rmax, 32)) : nullptr;
   b.ob = take_orth(a, rmax, s.lp, max_part(s));
   b.cq_work = a.take<char>(cpqr_work_bytes(plan_cpqr(s.l, s.n, s.k, NCU_CAP)));
   b.S11t = a.take<double>((size_t)s.k * s.kp);
@@ -1549,7 +1549,7 @@ size_t rsvd_pass_workspace_bytes(int dtype, int trans, int64_t m, int64_t n, int
   if (dtype == RSVD_BF16) {
     if (l > MAX_L_SVD) return 0;
     return gemm_bf16_part_bytes(plan_gemm_bf16(M, K, l, NCU_CAP)) + 256 +
-           (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
+           (size_t)rup(l, 16) * rup(K, 32) * sizeof(uint16_t) + 256;
   }
   return std::max(gemm_part_bytes(plan_gemm(M, K, l, NCU_CAP, 0), 8),
                   narrow_work_bytes(dtype == RSVD_F32, trans != 0, M, K, l, NCU_CAP)) + 256;
@@ -1629,7 +1629,7 @@ int rsvd_pass(rsvd_handle_t h, int dtype, int trans, int64_t m, int64_t n, int64
   if (dtype == RSVD_BF16) {
     if (l > MAX_L_SVD) return RSVD_ERR_UNSUPPORTED;
     const int64_t K = trans ? m : n;
-    const size_t xt_bytes = (size_t)rup(l, 16) * rup(K, 8) * sizeof(uint16_t) + 256;
+    const size_t xt_bytes = (size_t)rup(l, 16) * rup(K, 32) * sizeof(uint16_t) + 256;
     char* wb = static_cast<char*>(work);
     uint16_t* xt = reinterpret_cast<uint16_t*>(wb);
     return finish(pass(c, 2, trans == 1, m, n, (int)l, A, lda, X, ldx, Y, ldy, wb + xt_bytes,
