@@ -43,6 +43,10 @@ struct Bf16Args {
   int64_t nct, KI, U, G;
   float* part;
   int accumulate;                     // C += op(A) Xt instead of C = op(A) Xt
+  // S > 0 (the direct-to-LDS pass only): workgroup w takes one (row tile,
+  // column tile, k split) in an XCD-aware order instead of a stream-K range
+  int S;
+  int64_t nrt;
 };
 
 __device__ __forceinline__ int64_t range_begin(int64_t w, int64_t U, int64_t G) {
@@ -278,14 +282,40 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
   const int lk = lane >> 4;
 
   const int64_t w = blockIdx.x;
-  int64_t u = range_begin(w, g.U, g.G);
-  const int64_t uend = range_begin(w + 1, g.U, g.G);
+  int64_t u = 0, uend = 0;
+  int64_t sp_tile = 0, sp_s = 0;
+  if (g.S == 0) {
+    u = range_begin(w, g.U, g.G);
+    uend = range_begin(w + 1, g.U, g.G);
+  } else {
+    // split mode.  Workgroups are dealt to the XCDs in turn (w % 8), so the
+    // workgroups of one XCD that run at the same time take the same column
+    // tile and k split of different row tiles: their operand Xt k-slices are
+    // the same lines of that XCD's L2.
+    const int64_t x = w % 8, j = w / 8;
+    const int64_t rq_n = (g.nrt + 7) / 8;
+    const int64_t rq = j % rq_n, cs = j / rq_n;
+    const int64_t ct = cs / g.S, rt = x + 8 * rq;
+    if (rt >= g.nrt || ct >= g.nct) return;   // (the whole workgroup)
+    sp_tile = rt * g.nct + ct;
+    sp_s = cs - ct * g.S;
+    u = 0;
+    uend = 1;
+  }
 
   while (u < uend) {
-    const int64_t tile = u / g.KI;
-    const int64_t kb = u - tile * g.KI;
-    const int64_t ke = min(g.KI, kb + (uend - u));
-    u += ke - kb;
+    int64_t tile, kb, ke;
+    if (g.S == 0) {
+      tile = u / g.KI;
+      kb = u - tile * g.KI;
+      ke = min(g.KI, kb + (uend - u));
+      u += ke - kb;
+    } else {
+      tile = sp_tile;
+      kb = (sp_s * g.KI) / g.S;
+      ke = ((sp_s + 1) * g.KI) / g.S;
+      u = uend;
+    }
     const int64_t row0 = (tile / g.nct) * BM;
     const int64_t col0 = (tile % g.nct) * BN;
 
@@ -366,7 +396,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
             }
           }
     } else {
-      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      const int64_t slot = (g.S > 0) ? tile * g.S + sp_s : 2 * w + (kb == 0 ? 1 : 0);
       float* P = g.part + slot * (int64_t)(BM * BN);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -413,6 +443,26 @@ __global__ __launch_bounds__(256) void bf16_fixup_kernel(Bf16Args g) {
   }
 }
 
+// Split mode: C = the sum of the S partial tiles of each tile, in split order.
+template <int CBW>
+__global__ __launch_bounds__(256) void bf16_split_fixup_kernel(Bf16Args g) {
+  constexpr int BN = 32 * CBW;
+  const int64_t tile = blockIdx.x;
+  const int64_t row0 = (tile / g.nct) * BM;
+  const int64_t col0 = (tile % g.nct) * BN;
+  const int e0 = blockIdx.y * FIX_CHUNK;
+  const int e1 = min(e0 + FIX_CHUNK, BM * BN);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t r = row0 + e / BN;
+    const int64_t c = col0 + e % BN;
+    if (r >= g.M || c >= g.L) continue;
+    float sum = 0.f;
+    for (int sp = 0; sp < g.S; ++sp) sum += g.part[(tile * g.S + sp) * (int64_t)(BM * BN) + e];
+    float* cp = g.C + r * g.ldc + c;
+    *cp = g.accumulate ? *cp + sum : sum;
+  }
+}
+
 template <bool TRANS, int CBW>
 hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
   hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
@@ -437,7 +487,13 @@ hipError_t run_bf16_dma(const Bf16Args& g, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;
-  if (g.G != T) {
+  if (g.S > 1) {
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((bf16_split_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s,
+                       g);
+    return hipGetLastError();
+  }
+  if (g.S == 0 && g.G != T) {
     const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
     hipLaunchKernelGGL((bf16_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s, g);
     e = hipGetLastError();
@@ -550,13 +606,22 @@ hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t*
   g.nct = p.nct; g.KI = p.KI; g.U = p.U; g.G = p.G;
   g.part = static_cast<float*>(part);
   g.accumulate = accumulate ? 1 : 0;
-  // the direct-to-LDS kernel (32-deep k-steps, the same workgroups and tiles)
-  // where its alignment and padding conditions hold
+  g.S = 0;
+  g.nrt = p.nrt;
+  // the direct-to-LDS kernel (32-deep k-steps) where its alignment and
+  // padding conditions hold, in split mode: S = the splits per tile that keep
+  // the tiles x splits within the CUs (one tile per workgroup when there are
+  // more tiles than CUs), the partial tiles within the workspace
   const int64_t kid = cdiv(K, DK);
   if (!trans && K >= 8 && K % 8 == 0 && lda % 8 == 0 && ldx % 8 == 0 && ldx >= kid * DK &&
       (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(Xt) & 15) == 0) {
+    const int64_t T = p.nrt * p.nct;
+    int64_t S = std::max<int64_t>(1, std::min<int64_t>(kid / 8, (int64_t)p.G / T));
+    while (S > 1 && (size_t)(T * S) * (size_t)(BM * 32 * p.cbw) * sizeof(float) > part_cap) --S;
     g.KI = kid;
-    g.U = (p.nrt * p.nct) * kid;
+    g.U = T * kid;
+    g.S = (int)S;
+    g.G = 8 * p.nct * S * cdiv(p.nrt, 8);
     return dispatch_bf16_dma(g, p.cbw, s);
   }
   return trans ? dispatch_bf16<true>(g, p.cbw, s) : dispatch_bf16<false>(g, p.cbw, s);
