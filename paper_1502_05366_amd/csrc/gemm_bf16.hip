@@ -76,8 +76,24 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
   const int lk = lane >> 4;
 
   const int64_t w = blockIdx.x;
-  int64_t u = range_begin(w, g.U, g.G);
-  const int64_t uend = range_begin(w + 1, g.U, g.G);
+  int64_t u = 0, uend = 0;
+  int64_t sp_tile = 0, sp_s = 0;
+  if (g.S == 0) {
+    u = range_begin(w, g.U, g.G);
+    uend = range_begin(w + 1, g.U, g.G);
+  } else {
+    // split mode, as in the direct-to-LDS kernel: the workgroups of one XCD
+    // share the column tile and k split
+    const int64_t x = w % 8, j = w / 8;
+    const int64_t rq_n = (g.nrt + 7) / 8;
+    const int64_t rq = j % rq_n, cs = j / rq_n;
+    const int64_t ct = cs / g.S, rt = x + 8 * rq;
+    if (rt >= g.nrt || ct >= g.nct) return;   // (the whole workgroup)
+    sp_tile = rt * g.nct + ct;
+    sp_s = cs - ct * g.S;
+    u = 0;
+    uend = 1;
+  }
 
   // staging in 8-element (16-byte) chunks: APT per thread for A, XPT (the
   // last one partial) for Xt
@@ -87,10 +103,18 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
   constexpr int XPT = (XCH + NT - 1) / NT;
 
   while (u < uend) {
-    const int64_t tile = u / g.KI;
-    const int64_t kb = u - tile * g.KI;
-    const int64_t ke = min(g.KI, kb + (uend - u));
-    u += ke - kb;
+    int64_t tile, kb, ke;
+    if (g.S == 0) {
+      tile = u / g.KI;
+      kb = u - tile * g.KI;
+      ke = min(g.KI, kb + (uend - u));
+      u += ke - kb;
+    } else {
+      tile = sp_tile;
+      kb = (sp_s * g.KI) / g.S;
+      ke = ((sp_s + 1) * g.KI) / g.S;
+      u = uend;
+    }
     const int64_t row0 = (tile / g.nct) * BM;
     const int64_t col0 = (tile % g.nct) * BN;
 
@@ -218,7 +242,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
             }
           }
     } else {
-      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      const int64_t slot = (g.S > 0) ? tile * g.S + sp_s : 2 * w + (kb == 0 ? 1 : 0);
       float* P = g.part + slot * (int64_t)(BM * BN);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -469,7 +493,13 @@ hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;
-  if (g.G != T) {
+  if (g.S > 1) {
+    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    hipLaunchKernelGGL((bf16_split_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s,
+                       g);
+    return hipGetLastError();
+  }
+  if (g.S == 0 && g.G != T) {
     const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
     hipLaunchKernelGGL((bf16_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s, g);
     e = hipGetLastError();
@@ -623,6 +653,17 @@ hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t*
     g.S = (int)S;
     g.G = 8 * p.nct * S * cdiv(p.nrt, 8);
     return dispatch_bf16_dma(g, p.cbw, s);
+  }
+  // the register-staged kernel (64-deep k-steps; the transposed pass) in the
+  // same split mode when the tiles are fewer than the CUs
+  {
+    const int64_t T = p.nrt * p.nct;
+    int64_t S = std::min<int64_t>(p.KI / 4, (int64_t)p.G / T);
+    while (S > 1 && (size_t)(T * S) * (size_t)(BM * 32 * p.cbw) * sizeof(float) > part_cap) --S;
+    if (S >= 2) {
+      g.S = (int)S;
+      g.G = 8 * p.nct * S * cdiv(p.nrt, 8);
+    }
   }
   return trans ? dispatch_bf16<true>(g, p.cbw, s) : dispatch_bf16<false>(g, p.cbw, s);
 }
