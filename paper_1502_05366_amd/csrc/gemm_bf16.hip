@@ -275,13 +275,15 @@ constexpr int DNS = 4;
 typedef __attribute__((address_space(3))) void* lds_vp;
 typedef __attribute__((address_space(1))) void* gbl_vp;
 
-template <int CBW> struct DmaDims {
+template <int RBW, int CBW> struct DmaDims {
+  static constexpr int BMv = 64 * RBW;                 // tile rows (4 waves of 16 * RBW)
   static constexpr int BN = 32 * CBW;
-  static constexpr int ROWS = BM + BN;                 // staged rows per k-step
+  static constexpr int ROWS = BMv + BN;                // staged rows per k-step
   static constexpr int NI = ROWS / 16;                 // 1 KB wave loads per k-step
   static constexpr int LPW = (NI + NT / 64 - 1) / (NT / 64);   // per wave (a few repeated)
   static constexpr int STAGE = ROWS * DK;              // elements
-  static constexpr size_t LDS = (size_t)DNS * STAGE * sizeof(uint16_t);
+  static constexpr int NS = (RBW == 4) ? DNS : 3;     // LDS stages (wide tiles: three)
+  static constexpr size_t LDS = (size_t)NS * STAGE * sizeof(uint16_t);
 };
 
 // s_waitcnt that waits until at most n vector-memory operations are in
@@ -291,10 +293,12 @@ template <int N> __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int CBW>
+template <int RBW, int CBW>
 __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
-  using D = DmaDims<CBW>;
+  using D = DmaDims<RBW, CBW>;
   constexpr int BN = D::BN;
+  constexpr int BMv = D::BMv;
+  constexpr int NS = D::NS;
   extern __shared__ __attribute__((aligned(16))) uint16_t dsm[];   // DNS x ROWS x DK
 
   const int tid = threadIdx.x;
@@ -340,12 +344,12 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
       ke = ((sp_s + 1) * g.KI) / g.S;
       u = uend;
     }
-    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t row0 = (tile / g.nct) * BMv;
     const int64_t col0 = (tile % g.nct) * BN;
 
-    f4 acc[RB][CBW];
+    f4 acc[RBW][CBW];
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+    for (int i = 0; i < RBW; ++i)
 #pragma unroll
       for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -359,12 +363,12 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
         const int r = j * 16 + (lane >> 2);       // staged row
         const int sch = (lane & 3) ^ ((r >> 2) & 3);   // the chunk this slot holds
         const uint16_t* src;
-        if (r < BM) {
+        if (r < BMv) {
           const int64_t gi = min(row0 + r, g.M - 1);
           const int64_t gk = min(k0 + 8 * sch, g.K - 8);
           src = g.A + gi * g.lda + gk;
         } else {
-          const int64_t gj = min(col0 + (r - BM), g.L - 1);
+          const int64_t gj = min(col0 + (r - BMv), g.L - 1);
           src = g.X + gj * g.ldx + k0 + 8 * sch;
         }
         uint16_t* dst = dsm + (size_t)b * D::STAGE + (size_t)j * 16 * DK;
@@ -374,29 +378,29 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
 
     const int64_t nst = ke - kb;
 #pragma unroll
-    for (int p = 0; p < DNS - 1; ++p) issue(min(kb + p, ke - 1), p);
+    for (int p = 0; p < NS - 1; ++p) issue(min(kb + p, ke - 1), p);
     for (int64_t t = 0; t < nst; ++t) {
       // this wave's loads of step t are done when at most the later
       // DNS - 2 steps' loads are in flight; the barrier makes every wave's
       // visible and frees the stage read at step t - 1
-      wait_vm<(DNS - 2) * D::LPW>();
+      wait_vm<(NS - 2) * D::LPW>();
       // a plain barrier: __syncthreads' release fence would wait for every
       // load in flight (the direct-to-LDS loads count as LDS writes)
       asm volatile("s_barrier" ::: "memory");
-      issue(min(kb + t + DNS - 1, ke - 1), (int)((t + DNS - 1) % DNS));
-      const uint16_t* st = dsm + (size_t)(t % DNS) * D::STAGE;
-      bf8 av[RB];
+      issue(min(kb + t + NS - 1, ke - 1), (int)((t + NS - 1) % NS));
+      const uint16_t* st = dsm + (size_t)(t % NS) * D::STAGE;
+      bf8 av[RBW];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int r = wr * 16 * RB + rb * 16 + li;
+      for (int rb = 0; rb < RBW; ++rb) {
+        const int r = wr * 16 * RBW + rb * 16 + li;
         av[rb] = *reinterpret_cast<const bf8*>(st + r * DK + 8 * (lk ^ ((r >> 2) & 3)));
       }
 #pragma unroll
       for (int cb = 0; cb < CBW; ++cb) {
-        const int r = BM + wc * 16 * CBW + cb * 16 + li;
+        const int r = BMv + wc * 16 * CBW + cb * 16 + li;
         const bf8 bv = *reinterpret_cast<const bf8*>(st + r * DK + 8 * (lk ^ ((r >> 2) & 3)));
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RBW; ++rb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], bv, acc[rb][cb], 0, 0, 0);
       }
     }
@@ -407,12 +411,12 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
     const bool full = (kb == 0) && (ke == g.KI);
     if (full) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t r = row0 + wr * 16 * RBW + rb * 16 + 4 * lk + v;
             const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
             if (r < g.M && c < g.L) {
               float* cp = g.C + r * g.ldc + c;
@@ -421,14 +425,14 @@ __global__ __launch_bounds__(NT) void gemm_bf16_dma_kernel(Bf16Args g) {
           }
     } else {
       const int64_t slot = (g.S > 0) ? tile * g.S + sp_s : 2 * w + (kb == 0 ? 1 : 0);
-      float* P = g.part + slot * (int64_t)(BM * BN);
+      float* P = g.part + slot * (int64_t)(BMv * BN);
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int r = wr * 16 * RBW + rb * 16 + 4 * lk + v;
             const int c = wc * 16 * CBW + cb * 16 + li;
             P[r * BN + c] = acc[rb][cb][v];
           }
@@ -507,17 +511,18 @@ hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
   return e;
 }
 
-template <int CBW>
+template <int RBW, int CBW>
 hipError_t run_bf16_dma(const Bf16Args& g, hipStream_t s) {
-  const size_t shm = DmaDims<CBW>::LDS;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_dma_kernel<CBW>,
+  const size_t shm = DmaDims<RBW, CBW>::LDS;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_bf16_dma_kernel<RBW, CBW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((gemm_bf16_dma_kernel<CBW>), dim3((unsigned)g.G), dim3(NT), shm, s, g);
+  hipLaunchKernelGGL((gemm_bf16_dma_kernel<RBW, CBW>), dim3((unsigned)g.G), dim3(NT), shm, s, g);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;
   if (g.S > 1) {
+    // (the 256-row tiles only: the wide tiles run with S = 1)
     const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
     hipLaunchKernelGGL((bf16_split_fixup_kernel<CBW>), dim3((unsigned)T, nch), dim3(256), 0, s,
                        g);
@@ -533,14 +538,24 @@ hipError_t run_bf16_dma(const Bf16Args& g, hipStream_t s) {
 
 hipError_t dispatch_bf16_dma(const Bf16Args& g, int cbw, hipStream_t s) {
   switch (cbw) {
-    case 1: return run_bf16_dma<1>(g, s);
-    case 2: return run_bf16_dma<2>(g, s);
-    case 3: return run_bf16_dma<3>(g, s);
-    case 4: return run_bf16_dma<4>(g, s);
-    case 5: return run_bf16_dma<5>(g, s);
-    case 6: return run_bf16_dma<6>(g, s);
-    case 7: return run_bf16_dma<7>(g, s);
-    case 8: return run_bf16_dma<8>(g, s);
+    case 1: return run_bf16_dma<4, 1>(g, s);
+    case 2: return run_bf16_dma<4, 2>(g, s);
+    case 3: return run_bf16_dma<4, 3>(g, s);
+    case 4: return run_bf16_dma<4, 4>(g, s);
+    case 5: return run_bf16_dma<4, 5>(g, s);
+    case 6: return run_bf16_dma<4, 6>(g, s);
+    case 7: return run_bf16_dma<4, 7>(g, s);
+    case 8: return run_bf16_dma<4, 8>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// wide tiles: 128 rows x 32 * cbw columns (cbw 12, 16 or 18), the whole L
+hipError_t dispatch_bf16_dma_wide(const Bf16Args& g, int cbw, hipStream_t s) {
+  switch (cbw) {
+    case 12: return run_bf16_dma<2, 12>(g, s);
+    case 16: return run_bf16_dma<2, 16>(g, s);
+    case 18: return run_bf16_dma<2, 18>(g, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -643,8 +658,24 @@ hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t*
   // the tiles x splits within the CUs (one tile per workgroup when there are
   // more tiles than CUs), the partial tiles within the workspace
   const int64_t kid = cdiv(K, DK);
-  if (!trans && K >= 8 && K % 8 == 0 && lda % 8 == 0 && ldx % 8 == 0 && ldx >= kid * DK &&
-      (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(Xt) & 15) == 0) {
+  const bool dma_ok = !trans && K >= 8 && K % 8 == 0 && lda % 8 == 0 && ldx % 8 == 0 &&
+                      ldx >= kid * DK && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(Xt) & 15) == 0;
+  // wide tiles (l > 256): 128 rows x all columns per workgroup, so that A is
+  // read once instead of once per 256-column tile; one tile per workgroup
+  // (no partial sums) when the row tiles fill the CUs
+  if (dma_ok && p.nct > 1 && L <= 576 && cdiv(M, 128) >= p.G) {
+    const int cw = (L <= 384) ? 12 : (L <= 512) ? 16 : 18;
+    const int64_t nrt = cdiv(M, 128);
+    g.nct = 1;
+    g.nrt = nrt;
+    g.KI = kid;
+    g.U = nrt * kid;
+    g.S = 1;
+    g.G = 8 * cdiv(nrt, 8);
+    return dispatch_bf16_dma_wide(g, cw, s);
+  }
+  if (dma_ok) {
     const int64_t T = p.nrt * p.nct;
     int64_t S = std::max<int64_t>(1, std::min<int64_t>(kid / 8, (int64_t)p.G / T));
     while (S > 1 && (size_t)(T * S) * (size_t)(BM * 32 * p.cbw) * sizeof(float) > part_cap) --S;
