@@ -61,11 +61,17 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-template <bool TRANS, int CBW>
+// RBW row blocks per wave (tile rows 64 * RBW), k-steps BKW deep: <TRANS, 4,
+// CBW, 64> for the 256-row tiles, <true, 2, CBW, 32> for the whole-width tiles
+// of the transposed pass at l > 256
+template <bool TRANS, int RBW, int CBW, int BKW>
 __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
   constexpr int BN = 32 * CBW;
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * KP];
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BN * KP];
+  constexpr int BMv = 64 * RBW;
+  constexpr int KPv = BKW + 8;         // padded k extent of an LDS row
+  constexpr int KCH = BKW / 8;         // 16-byte k chunks per row
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BMv * KPv];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BN * KPv];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -97,9 +103,10 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
 
   // staging in 8-element (16-byte) chunks: APT per thread for A, XPT (the
   // last one partial) for Xt
-  constexpr int ACH = BM * BK / 8;
+  constexpr int ACH = BMv * BKW / 8;
   constexpr int APT = ACH / NT;
-  constexpr int XCH = BK * BN / 8;
+  static_assert(APT >= 1 && APT * NT == ACH, "A staging");
+  constexpr int XCH = BKW * BN / 8;
   constexpr int XPT = (XCH + NT - 1) / NT;
 
   while (u < uend) {
@@ -115,12 +122,12 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
       ke = ((sp_s + 1) * g.KI) / g.S;
       u = uend;
     }
-    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t row0 = (tile / g.nct) * BMv;
     const int64_t col0 = (tile % g.nct) * BN;
 
-    f4 acc[RB][CBW];
+    f4 acc[RBW][CBW];
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+    for (int i = 0; i < RBW; ++i)
 #pragma unroll
       for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -128,15 +135,15 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
     us8 rx[XPT];
 
     auto gload = [&](int64_t kt) {
-      const int64_t k0 = kt * BK;
+      const int64_t k0 = kt * BKW;
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
         const int ch = tid + q * NT;
         us8 v;
         if (!TRANS) {
-          // row ch / 8, k chunk (ch % 8) * 8
-          const int64_t gi = row0 + (ch >> 3);
-          const int64_t gk = k0 + (ch & 7) * 8;
+          // row ch / KCH, k chunk (ch % KCH) * 8
+          const int64_t gi = row0 + ch / KCH;
+          const int64_t gk = k0 + (ch % KCH) * 8;
           const uint16_t* p = g.A + gi * g.lda + gk;
           if (gi < g.M && gk + 8 <= g.K) {
             v = *reinterpret_cast<const us8*>(p);
@@ -145,10 +152,10 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
             for (int j = 0; j < 8; ++j) v[j] = (gi < g.M && gk + j < g.K) ? p[j] : (uint16_t)0;
           }
         } else {
-          // k row ch % 64, i chunk (ch / 64) * 8: consecutive lanes take
+          // k row ch % BKW, i chunk (ch / BKW) * 8: consecutive lanes take
           // consecutive k, so the transposing LDS writes do not collide
-          const int64_t gk = k0 + (ch & 63);
-          const int64_t gi = row0 + (ch >> 6) * 8;
+          const int64_t gk = k0 + (ch % BKW);
+          const int64_t gi = row0 + (ch / BKW) * 8;
           const uint16_t* p = g.A + gk * g.lda + gi;
           if (gk < g.K && gi + 8 <= g.M) {
             v = *reinterpret_cast<const us8*>(p);
@@ -164,9 +171,9 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
         const int ch = tid + q * NT;
         us8 v = us8{0, 0, 0, 0, 0, 0, 0, 0};
         if (ch < XCH) {
-          // column ch / 8 of the tile, k chunk (ch % 8) * 8
-          const int64_t gj = col0 + (ch >> 3);
-          const int64_t gk = k0 + (ch & 7) * 8;
+          // column ch / KCH of the tile, k chunk (ch % KCH) * 8
+          const int64_t gj = col0 + ch / KCH;
+          const int64_t gk = k0 + (ch % KCH) * 8;
           const uint16_t* p = g.X + gj * g.ldx + gk;
           if (gj < g.L && gk + 8 <= g.K) {
             v = *reinterpret_cast<const us8*>(p);
@@ -183,17 +190,17 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
       for (int q = 0; q < APT; ++q) {
         const int ch = tid + q * NT;
         if (!TRANS) {
-          *reinterpret_cast<us8*>(&As[buf][(ch >> 3) * KP + (ch & 7) * 8]) = ra[q];
+          *reinterpret_cast<us8*>(&As[buf][(ch / KCH) * KPv + (ch % KCH) * 8]) = ra[q];
         } else {
-          const int kr = ch & 63, i0 = (ch >> 6) * 8;
+          const int kr = ch % BKW, i0 = (ch / BKW) * 8;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) As[buf][(i0 + j) * KP + kr] = ra[q][j];
+          for (int j = 0; j < 8; ++j) As[buf][(i0 + j) * KPv + kr] = ra[q][j];
         }
       }
 #pragma unroll
       for (int q = 0; q < XPT; ++q) {
         const int ch = tid + q * NT;
-        if (ch < XCH) *reinterpret_cast<us8*>(&Xs[buf][(ch >> 3) * KP + (ch & 7) * 8]) = rx[q];
+        if (ch < XCH) *reinterpret_cast<us8*>(&Xs[buf][(ch / KCH) * KPv + (ch % KCH) * 8]) = rx[q];
       }
     };
 
@@ -205,19 +212,19 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
       const bool more = kt + 1 < ke;
       if (more) gload(kt + 1);
 #pragma unroll
-      for (int kk = 0; kk < BK / 32; ++kk) {
-        bf8 av[RB];
+      for (int kk = 0; kk < BKW / 32; ++kk) {
+        bf8 av[RBW];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int i = wr * 16 * RB + rb * 16 + li;
-          av[rb] = *reinterpret_cast<const bf8*>(&As[buf][i * KP + kk * 32 + lk * 8]);
+        for (int rb = 0; rb < RBW; ++rb) {
+          const int i = wr * 16 * RBW + rb * 16 + li;
+          av[rb] = *reinterpret_cast<const bf8*>(&As[buf][i * KPv + kk * 32 + lk * 8]);
         }
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb) {
           const int j = wc * 16 * CBW + cb * 16 + li;
-          const bf8 bv = *reinterpret_cast<const bf8*>(&Xs[buf][j * KP + kk * 32 + lk * 8]);
+          const bf8 bv = *reinterpret_cast<const bf8*>(&Xs[buf][j * KPv + kk * 32 + lk * 8]);
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
+          for (int rb = 0; rb < RBW; ++rb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], bv, acc[rb][cb], 0, 0, 0);
         }
       }
@@ -229,12 +236,12 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
     const bool full = (kb == 0) && (ke == g.KI);
     if (full) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t r = row0 + wr * 16 * RBW + rb * 16 + 4 * lk + v;
             const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
             if (r < g.M && c < g.L) {
               float* cp = g.C + r * g.ldc + c;
@@ -243,14 +250,14 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
           }
     } else {
       const int64_t slot = (g.S > 0) ? tile * g.S + sp_s : 2 * w + (kb == 0 ? 1 : 0);
-      float* P = g.part + slot * (int64_t)(BM * BN);
+      float* P = g.part + slot * (int64_t)(BMv * BN);
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CBW; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int r = wr * 16 * RBW + rb * 16 + 4 * lk + v;
             const int c = wc * 16 * CBW + cb * 16 + li;
             P[r * BN + c] = acc[rb][cb][v];
           }
@@ -491,9 +498,10 @@ __global__ __launch_bounds__(256) void bf16_split_fixup_kernel(Bf16Args g) {
   }
 }
 
-template <bool TRANS, int CBW>
+template <bool TRANS, int CBW, int RBW = 4, int BKW = BK>
 hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, RBW, CBW, BKW>), dim3((unsigned)g.G), dim3(NT), 0, s,
+                     g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;
@@ -546,6 +554,16 @@ hipError_t dispatch_bf16_dma(const Bf16Args& g, int cbw, hipStream_t s) {
     case 6: return run_bf16_dma<4, 6>(g, s);
     case 7: return run_bf16_dma<4, 7>(g, s);
     case 8: return run_bf16_dma<4, 8>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the transposed pass in whole-width tiles (128 rows, 32-deep k-steps)
+hipError_t dispatch_bf16_wide_t(const Bf16Args& g, int cbw, hipStream_t s) {
+  switch (cbw) {
+    case 12: return run_bf16<true, 12, 2, 32>(g, s);
+    case 16: return run_bf16<true, 16, 2, 32>(g, s);
+    case 18: return run_bf16<true, 18, 2, 32>(g, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -684,6 +702,19 @@ hipError_t gemm_bf16(bool trans, const uint16_t* A, int64_t lda, const uint16_t*
     g.S = (int)S;
     g.G = 8 * p.nct * S * cdiv(p.nrt, 8);
     return dispatch_bf16_dma(g, p.cbw, s);
+  }
+  // the transposed pass at l > 256 in whole-width tiles as well (A
+  // transposed on its way into LDS, 32-deep k-steps), one tile per workgroup
+  if (trans && p.nct > 1 && L <= 576 && cdiv(M, 128) >= p.G) {
+    const int cw = (L <= 384) ? 12 : (L <= 512) ? 16 : 18;
+    const int64_t nrt = cdiv(M, 128), kiw = cdiv(K, 32);
+    g.nct = 1;
+    g.nrt = nrt;
+    g.KI = kiw;
+    g.U = nrt * kiw;
+    g.S = 1;
+    g.G = 8 * cdiv(nrt, 8);
+    return dispatch_bf16_wide_t(g, cw, s);
   }
   // the register-staged kernel (64-deep k-steps; the transposed pass) in the
   // same split mode when the tiles are fewer than the CUs

@@ -35,9 +35,11 @@ def bf16(x):
     return t.cuda(), t.to(torch.float64).numpy()
 
 
-# (the last two: l > 256 with enough 128-row tiles for the whole-width tiles)
+# (the last four: l > 256 with enough 128-row output tiles for the whole-width
+# tiles of Y = A X and of Z = A^T X)
 @pytest.mark.parametrize("m,n,l", [(333, 520, 30), (1000, 2000, 220), (130, 72, 1), (2047, 136, 256),
-                                   (257, 1003, 17), (33000, 256, 300), (32900, 128, 576)])
+                                   (257, 1003, 17), (33000, 256, 300), (32900, 128, 576),
+                                   (256, 33000, 300), (128, 32900, 576)])
 def test_bf16_pass_exact_on_integers(R, m, n, l):
     A = W.integer_matrix(m, n, seed=m + n)
     Xn = W.integer_matrix(n, l, seed=l + 1)
