@@ -72,6 +72,11 @@ __device__ __forceinline__ uint32_t gather_byte(const uint32_t (&w)[4], int b) {
          (((w[3] >> sh) & 0xFFu) << 24);
 }
 
+// mask of the first n bytes of a word (n clamped to 0..4)
+__device__ __forceinline__ uint32_t byte_mask(int64_t n) {
+  return n >= 4 ? 0xFFFFFFFFu : n <= 0 ? 0u : (0xFFFFFFFFu >> (32 - 8 * (int)n));
+}
+
 template <bool TRANS, int CBW>
 __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
   constexpr int BN = 32 * CBW;
@@ -118,6 +123,12 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
       u4v ra[APT];                 // A chunks (transposed: 4 k rows of one i quad each)
     u4v rx[XPT];
 
+    // Loads are unconditional, from a clamped address, and a select zeroes
+    // what lies outside the operands: a branch around a load would make the
+    // compiler wait for it at the join.  Rows of A are 16-byte aligned with a
+    // leading dimension of 16k bytes and Xt rows are zero-padded to 16k, so a
+    // word or chunk that starts inside a row lies inside its storage; the
+    // bytes of A past the last column (row padding) are masked.
     auto gload = [&](int64_t kt) {
       const int64_t k0 = kt * BK;
       if (!TRANS) {
@@ -126,38 +137,27 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
           const int ch = tid + q * NT;
           const int64_t gi = row0 + (ch >> 3);
           const int64_t gk = k0 + (ch & 7) * 16;
-          const uint8_t* p = g.A + gi * g.lda + gk;
-          u4v v;
-          if (gi < g.M && gk + 16 <= g.K) {
-            v = *reinterpret_cast<const u4v*>(p);
-          } else {
-            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+          const bool ok = gi < g.M && gk < g.K;
+          const u4v v = *reinterpret_cast<const u4v*>(g.A + (ok ? gi * g.lda + gk : 0));
+          const int64_t nb = g.K - gk;          // bytes of the chunk inside the row
+          u4v m;
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (gi < g.M && gk + j < g.K) wv[j >> 2] |= (uint32_t)p[j] << (8 * (j & 3));
-            v = u4v{wv[0], wv[1], wv[2], wv[3]};
-          }
-          ra[q] = v;
+          for (int w = 0; w < 4; ++w) m[w] = ok ? byte_mask(nb - 4 * w) : 0u;
+          ra[q] = v & m;
         }
       } else {
         // word r of chunk q: k row KR kq + 4 q + r, bytes i = 4 ir .. 4 ir + 3
         const int64_t gi = row0 + 4 * ir;
+        const uint32_t im = byte_mask(g.M - gi);
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
           uint32_t wv[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int64_t gk = k0 + KR * kq + 4 * q + r;
-            const uint8_t* p = g.A + gk * g.lda + gi;
-            uint32_t x = 0u;
-            if (gk < g.K && gi + 4 <= g.M) {
-              x = *reinterpret_cast<const uint32_t*>(p);
-            } else {
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (gk < g.K && gi + j < g.M) x |= (uint32_t)p[j] << (8 * j);
-            }
-            wv[r] = x;
+            const bool ok = gk < g.K && im != 0u;
+            const uint32_t x = *reinterpret_cast<const uint32_t*>(g.A + (ok ? gk * g.lda + gi : 0));
+            wv[r] = ok ? (x & im) : 0u;
           }
           ra[q] = u4v{wv[0], wv[1], wv[2], wv[3]};
         }
@@ -165,22 +165,11 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
 #pragma unroll
       for (int q = 0; q < XPT; ++q) {
         const int ch = tid + q * NT;
-        u4v v = u4v{0u, 0u, 0u, 0u};
-        if (ch < XCH) {
-          const int64_t gj = col0 + (ch >> 3);
-          const int64_t gk = k0 + (ch & 7) * 16;
-          const uint8_t* p = g.X + gj * g.ldx + gk;
-          if (gj < g.L && gk + 16 <= g.K) {
-            v = *reinterpret_cast<const u4v*>(p);
-          } else {
-            uint32_t wv[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (gj < g.L && gk + j < g.K) wv[j >> 2] |= (uint32_t)p[j] << (8 * (j & 3));
-            v = u4v{wv[0], wv[1], wv[2], wv[3]};
-          }
-        }
-        rx[q] = v;
+        const int64_t gj = col0 + (ch >> 3);
+        const int64_t gk = k0 + (ch & 7) * 16;
+        const bool ok = ch < XCH && gj < g.L && gk < g.K;
+        const u4v v = *reinterpret_cast<const u4v*>(g.X + (ok ? gj * g.ldx + gk : 0));
+        rx[q] = ok ? v : u4v{0u, 0u, 0u, 0u};
       }
     };
     auto sstore = [&](int buf) {
@@ -213,7 +202,10 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
     int buf = 0;
     for (int64_t kt = kb; kt < ke; ++kt) {
       const bool more = kt + 1 < ke;
-      if (more) gload(kt + 1);
+      // unconditional (the last step loads its own k-step again): under a
+      // branch the staged registers would become phis that the compiler
+      // fills by copies, waiting for the loads before the products
+      gload(more ? kt + 1 : kt);
       i8v av[RB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
@@ -239,6 +231,166 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
       __syncthreads();
       buf ^= 1;
     }
+
+    const bool full = (kb == 0) && (ke == g.KI);
+    if (full) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int64_t c = col0 + wc * 16 * CBW + cb * 16 + li;
+            if (r < g.M && c < g.L) {
+              float* cp = g.C + r * g.ldc + c;
+              const float x = acc[rb][cb][v] * out_scale(g, r, c);
+              *cp = g.accumulate ? *cp + x : x;
+            }
+          }
+    } else {
+      const int64_t slot = 2 * w + (kb == 0 ? 1 : 0);
+      float* P = g.part + slot * (int64_t)(BM * BN);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = wr * 16 * RB + rb * 16 + 4 * lk + v;
+            const int c = wc * 16 * CBW + cb * 16 + li;
+            P[r * BN + c] = acc[rb][cb][v];
+          }
+    }
+  }
+}
+
+// ---- Y = A X with both operands streamed straight into LDS -----------------
+//
+// The same tiles, work ranges and partial slots as gemm_f8_kernel, for the
+// pass whose operands both hold k contiguously (A rows and Xt rows) and K a
+// multiple of BK: the direct-to-LDS loads (global_load_lds_dwordx4) move
+// each 128-byte k-step row from HBM into LDS without staging registers,
+// three LDS stages deep (two k-steps in flight while the third is
+// multiplied).  Staged rows are unpadded; the 16-byte chunk c of staged row
+// r sits in slot c ^ (r & 7), so that the 8 lanes of one operand read
+// (8 rows, one chunk) hit 8 different slots.  Rows past M or L are clamped
+// to the last one (their products are discarded).
+typedef __attribute__((address_space(3))) void* lds_vp;
+typedef __attribute__((address_space(1))) void* gbl_vp;
+
+template <int CBW> struct F8Dma {
+  static constexpr int BN = 32 * CBW;
+  static constexpr int ROWS = BM + BN;                 // staged rows per k-step
+  static constexpr int NI = ROWS / 8;                  // 1 KB wave loads per k-step
+  static constexpr int LPW = (NI + NT / 64 - 1) / (NT / 64);   // per wave (a few repeated)
+  static constexpr int STAGE = ROWS * BK;              // bytes
+  static constexpr int NS = 3;
+  static constexpr size_t LDS = (size_t)NS * STAGE;
+  static_assert(LDS <= 160 * 1024, "three stages fit the LDS");
+};
+
+// s_waitcnt that waits until at most n vector-memory operations are in
+// flight (lgkm and exp counters left alone)
+template <int N> __device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int CBW>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_f8_dma_kernel(F8Args g) {
+  using D = F8Dma<CBW>;
+  constexpr int BN = D::BN;
+  constexpr int NS = D::NS;
+  extern __shared__ __attribute__((aligned(16))) uint8_t dsm[];   // NS x ROWS x BK
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave & 3;
+  const int wc = wave >> 2;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+
+  const int64_t w = blockIdx.x;
+  int64_t u = range_begin(w, g.U, g.G);
+  const int64_t uend = range_begin(w + 1, g.U, g.G);
+
+  while (u < uend) {
+    const int64_t tile = u / g.KI;
+    const int64_t kb = u - tile * g.KI;
+    const int64_t ke = min(g.KI, kb + (uend - u));
+    u += ke - kb;
+    const int64_t row0 = (tile / g.nct) * BM;
+    const int64_t col0 = (tile % g.nct) * BN;
+
+    f4 acc[RB][CBW];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // the loads of k-step kt into stage b: wave load j fills staged rows
+    // 8 j .. 8 j + 7, lane l the slot l % 8 of row 8 j + l / 8
+    auto issue = [&](int64_t kt, int b) {
+      const int64_t k0 = kt * BK;
+#pragma unroll
+      for (int q = 0; q < D::LPW; ++q) {
+        int j = wave + (NT / 64) * q;
+        if (j >= D::NI) j -= D::NI;               // (a repeated load: same data, same slots)
+        const int r = j * 8 + (lane >> 3);
+        const int sch = (lane & 7) ^ (r & 7);     // the chunk this slot holds
+        const uint8_t* src;
+        if (r < BM) {
+          const int64_t gi = min(row0 + r, g.M - 1);
+          src = g.A + gi * g.lda + k0 + 16 * sch;
+        } else {
+          const int64_t gj = min(col0 + (r - BM), g.L - 1);
+          src = g.X + gj * g.ldx + k0 + 16 * sch;
+        }
+        uint8_t* dst = dsm + (size_t)b * D::STAGE + (size_t)j * 8 * BK;
+        __builtin_amdgcn_global_load_lds((gbl_vp)src, (lds_vp)dst, 16, 0, 0);
+      }
+    };
+
+    const int64_t nst = ke - kb;
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p) issue(min(kb + p, ke - 1), p);
+    for (int64_t t = 0; t < nst; ++t) {
+      // this wave's loads of step t are done when at most the later NS - 2
+      // steps' loads are in flight; the barrier makes every wave's visible
+      // and frees the stage read at step t - 1
+      wait_vm<(NS - 2) * D::LPW>();
+      // a plain barrier: __syncthreads' release fence would wait for every
+      // load in flight (the direct-to-LDS loads count as LDS writes)
+      asm volatile("s_barrier" ::: "memory");
+      issue(min(kb + t + NS - 1, ke - 1), (int)((t + NS - 1) % NS));
+      const uint8_t* st = dsm + (size_t)(t % NS) * D::STAGE;
+      auto oread = [&](int r) {
+        const int x = r & 7;
+        const u4v lo = *reinterpret_cast<const u4v*>(st + r * BK + 16 * ((2 * lk) ^ x));
+        const u4v hi = *reinterpret_cast<const u4v*>(st + r * BK + 16 * ((2 * lk + 1) ^ x));
+        return i8v{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                   (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      };
+      i8v av[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) av[rb] = oread(wr * 16 * RB + rb * 16 + li);
+      // every operand read before the first product: read one column block
+      // at a time, the compiler waits for each read just before its products
+      i8v bv[CBW];
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) bv[cb] = oread(BM + wc * 16 * CBW + cb * 16 + li);
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              av[rb], bv[cb], acc[rb][cb], 0, 0, 0, SCALE_ONE, 0, SCALE_ONE);
+    }
+    // no load may still be writing LDS when the next tile's first loads go out
+    wait_vm<0>();
+    __syncthreads();
 
     const bool full = (kb == 0) && (ke == g.KI);
     if (full) {
@@ -305,10 +457,27 @@ __global__ __launch_bounds__(256) void f8_fixup_kernel(F8Args g) {
   }
 }
 
+// the direct-to-LDS kernel takes Y = A X when K is a multiple of BK (its
+// k-steps then never leave the rows); the leading dimensions and the
+// operands' 16-byte alignment hold for every FP8 pass
+template <bool TRANS> bool f8_dma_ok(const F8Args& g) {
+  return !TRANS && g.K % BK == 0 && g.lda % 16 == 0 && g.ldx % 16 == 0 &&
+         (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.X) & 15) == 0;
+}
+
 template <bool TRANS, int CBW>
 hipError_t run_f8(const F8Args& g, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_f8_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (f8_dma_ok<TRANS>(g)) {
+    const size_t shm = F8Dma<CBW>::LDS;
+    e = hipFuncSetAttribute((const void*)gemm_f8_dma_kernel<CBW>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((gemm_f8_dma_kernel<CBW>), dim3((unsigned)g.G), dim3(NT), shm, s, g);
+  } else {
+    hipLaunchKernelGGL((gemm_f8_kernel<TRANS, CBW>), dim3((unsigned)g.G), dim3(NT), 0, s, g);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;
   if (g.G != T) {

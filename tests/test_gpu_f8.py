@@ -66,7 +66,10 @@ def test_quantize_bit_exact(R):
 
 
 @pytest.mark.parametrize("m,n,l", [(300, 520, 30), (1000, 2000, 220), (130, 72, 1),
-                                   (2047, 136, 256), (700, 900, 576), (257, 1003, 17)])
+                                   (2047, 136, 256), (700, 900, 576), (257, 1003, 17),
+                                   # n a multiple of 128: A X on the direct-to-LDS kernel
+                                   (1000, 1024, 220), (300, 2048, 576), (129, 128, 17),
+                                   (4100, 256, 300)])
 def test_f8_pass_exact_on_integers(R, m, n, l):
     g = np.random.default_rng(m + n + l)
     A = g.integers(-8, 9, size=(m, n)).astype(np.float64)
