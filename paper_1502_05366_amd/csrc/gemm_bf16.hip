@@ -63,8 +63,16 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 
 // RBW row blocks per wave (tile rows 64 * RBW), k-steps BKW deep: <TRANS, 4,
 // CBW, 64> for the 256-row tiles, <true, 2, CBW, 32> for the whole-width tiles
-// of the transposed pass at l > 256
-template <bool TRANS, int RBW, int CBW, int BKW>
+// of the transposed pass at l > 256.  EX: every 16-byte chunk of A that starts
+// inside the matrix lies wholly inside it (the chunks' direction a multiple
+// of 8 long, lda a multiple of 8, A 16-byte aligned).  The loads of the next
+// k-step are then unconditional, from a clamped address, and go out before
+// the products (scheduling barriers hold the order); the select that zeroes
+// chunks outside the operands is taken when they are stored after the
+// products.  A branch around a load, or a select right after it, makes the
+// compiler wait for the load there.  Without EX, chunks that cross the edge
+// are read element by element.
+template <bool TRANS, int RBW, int CBW, int BKW, bool EX>
 __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
   constexpr int BN = 32 * CBW;
   constexpr int BMv = 64 * RBW;
@@ -133,8 +141,45 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
 
     us8 ra[APT];
     us8 rx[XPT];
+    // EX: whether each staged chunk lies inside its operand (the zeroing
+    // select waits for the load, so it is taken when the chunk is stored)
+    bool aok[APT], xok[XPT];
 
+    auto gload_ex = [&](int64_t kt) {
+      const int64_t k0 = kt * BKW;
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        const int ch = tid + q * NT;
+        int64_t gi, gk;
+        if (!TRANS) {
+          gi = row0 + ch / KCH;
+          gk = k0 + (ch % KCH) * 8;
+        } else {
+          gk = k0 + (ch % BKW);
+          gi = row0 + (ch / BKW) * 8;
+        }
+        const bool ok = gi < g.M && gk < g.K;
+        const int64_t off = !TRANS ? gi * g.lda + gk : gk * g.lda + gi;
+        ra[q] = *reinterpret_cast<const us8*>(g.A + (ok ? off : 0));
+        aok[q] = ok;
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        // Xt rows are zero-padded to whole k-steps: a chunk that starts
+        // below K lies inside its row
+        const int ch = tid + q * NT;
+        const int64_t gj = col0 + ch / KCH;
+        const int64_t gk = k0 + (ch % KCH) * 8;
+        const bool ok = ch < XCH && gj < g.L && gk < g.K;
+        rx[q] = *reinterpret_cast<const us8*>(g.X + (ok ? gj * g.ldx + gk : 0));
+        xok[q] = ok;
+      }
+    };
     auto gload = [&](int64_t kt) {
+      if constexpr (EX) {
+        gload_ex(kt);
+        return;
+      }
       const int64_t k0 = kt * BKW;
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
@@ -186,6 +231,13 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
       }
     };
     auto sstore = [&](int buf) {
+      if constexpr (EX) {
+        const us8 z = us8{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < APT; ++q) ra[q] = aok[q] ? ra[q] : z;
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) rx[q] = xok[q] ? rx[q] : z;
+      }
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
         const int ch = tid + q * NT;
@@ -210,7 +262,17 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
     int buf = 0;
     for (int64_t kt = kb; kt < ke; ++kt) {
       const bool more = kt + 1 < ke;
-      if (more) gload(kt + 1);
+      if constexpr (EX) {
+        // unconditional (the last step loads its own k-step again): under a
+        // branch the staged registers become phis filled by copies, which
+        // wait for the loads before the products
+        gload(more ? kt + 1 : kt);
+        // the loads go out before the products (left alone, the compiler
+        // sinks them to the stores that use them)
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        if (more) gload(kt + 1);
+      }
 #pragma unroll
       for (int kk = 0; kk < BKW / 32; ++kk) {
         bf8 av[RBW];
@@ -228,7 +290,14 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(Bf16Args g) {
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], bv, acc[rb][cb], 0, 0, 0);
         }
       }
-      if (more) sstore(buf ^ 1);
+      if constexpr (EX) {
+        // (on the last step too: the stage written is read by no one), after
+        // every product, where the wait for the staged loads goes
+        __builtin_amdgcn_sched_barrier(0);
+        sstore(buf ^ 1);
+      } else {
+        if (more) sstore(buf ^ 1);
+      }
       __syncthreads();
       buf ^= 1;
     }
@@ -500,8 +569,26 @@ __global__ __launch_bounds__(256) void bf16_split_fixup_kernel(Bf16Args g) {
 
 template <bool TRANS, int CBW, int RBW = 4, int BKW = BK>
 hipError_t run_bf16(const Bf16Args& g, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, RBW, CBW, BKW>), dim3((unsigned)g.G), dim3(NT), 0, s,
-                     g);
+  // chunks run along k (A X) or along the rows of the result (A^T X).  The
+  // 256-row tiles keep the conditional loads: with 4 row blocks per wave
+  // their registers do not hold a step's loads in flight across the products
+  const int64_t run = TRANS ? g.M : g.K;
+  const bool ex = RBW == 2 && run % 8 == 0 && g.lda % 8 == 0 &&
+                  (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && g.ldx % 8 == 0 &&
+                  (reinterpret_cast<uintptr_t>(g.X) & 15) == 0;
+  if constexpr (RBW == 2) {
+    if (ex) {
+      hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, RBW, CBW, BKW, true>), dim3((unsigned)g.G),
+                         dim3(NT), 0, s, g);
+    } else {
+      hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, RBW, CBW, BKW, false>), dim3((unsigned)g.G),
+                         dim3(NT), 0, s, g);
+    }
+  } else {
+    (void)ex;
+    hipLaunchKernelGGL((gemm_bf16_kernel<TRANS, RBW, CBW, BKW, false>), dim3((unsigned)g.G),
+                       dim3(NT), 0, s, g);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t T = g.U / g.KI;

@@ -81,7 +81,10 @@ template <bool TRANS, int CBW>
 __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
   constexpr int BN = 32 * CBW;
   __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * KP];
-  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][BN * KP];
+  // Xs rows up to the staging's last chunk: the chunks past BN rows (zero)
+  // are stored unconditionally, a branch there would split the loop body
+  constexpr int XROWS = ((32 * CBW * BK / 16 + NT - 1) / NT) * NT / 8;
+  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][XROWS * KP];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -101,6 +104,7 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
   constexpr int APT = BM * BK / 16 / NT;
   constexpr int XCH = BN * BK / 16;
   constexpr int XPT = (XCH + NT - 1) / NT;
+  static_assert(XPT * NT / 8 == XROWS, "staged Xs rows");
   constexpr int IQ = BM / 4;                 // i quads of a transposed tile
   constexpr int KR = BK / (NT / IQ);         // k rows per thread (= 4 APT)
   static_assert(KR == 4 * APT, "transposed staging covers the tile");
@@ -123,12 +127,13 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
       u4v ra[APT];                 // A chunks (transposed: 4 k rows of one i quad each)
     u4v rx[XPT];
 
-    // Loads are unconditional, from a clamped address, and a select zeroes
-    // what lies outside the operands: a branch around a load would make the
-    // compiler wait for it at the join.  Rows of A are 16-byte aligned with a
-    // leading dimension of 16k bytes and Xt rows are zero-padded to 16k, so a
-    // word or chunk that starts inside a row lies inside its storage; the
-    // bytes of A past the last column (row padding) are masked.
+    // Loads are unconditional, from a clamped address; what lies outside the
+    // operands is zeroed when the staged step is stored (a branch around a
+    // load makes the compiler wait for it at the join, and so does a select
+    // right after it).  Rows of A are 16-byte aligned with a leading
+    // dimension of 16k bytes and Xt rows are zero-padded to 16k, so a word or
+    // chunk that starts inside a row lies inside its storage; the bytes of A
+    // past the last column (row padding) are masked.
     auto gload = [&](int64_t kt) {
       const int64_t k0 = kt * BK;
       if (!TRANS) {
@@ -138,29 +143,19 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
           const int64_t gi = row0 + (ch >> 3);
           const int64_t gk = k0 + (ch & 7) * 16;
           const bool ok = gi < g.M && gk < g.K;
-          const u4v v = *reinterpret_cast<const u4v*>(g.A + (ok ? gi * g.lda + gk : 0));
-          const int64_t nb = g.K - gk;          // bytes of the chunk inside the row
-          u4v m;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) m[w] = ok ? byte_mask(nb - 4 * w) : 0u;
-          ra[q] = v & m;
+          ra[q] = *reinterpret_cast<const u4v*>(g.A + (ok ? gi * g.lda + gk : 0));
         }
       } else {
         // word r of chunk q: k row KR kq + 4 q + r, bytes i = 4 ir .. 4 ir + 3
         const int64_t gi = row0 + 4 * ir;
-        const uint32_t im = byte_mask(g.M - gi);
 #pragma unroll
-        for (int q = 0; q < APT; ++q) {
-          uint32_t wv[4];
+        for (int q = 0; q < APT; ++q)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int64_t gk = k0 + KR * kq + 4 * q + r;
-            const bool ok = gk < g.K && im != 0u;
-            const uint32_t x = *reinterpret_cast<const uint32_t*>(g.A + (ok ? gk * g.lda + gi : 0));
-            wv[r] = ok ? (x & im) : 0u;
+            const bool ok = gk < g.K && gi < g.M;
+            ra[q][r] = *reinterpret_cast<const uint32_t*>(g.A + (ok ? gk * g.lda + gi : 0));
           }
-          ra[q] = u4v{wv[0], wv[1], wv[2], wv[3]};
-        }
       }
 #pragma unroll
       for (int q = 0; q < XPT; ++q) {
@@ -168,11 +163,45 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
         const int64_t gj = col0 + (ch >> 3);
         const int64_t gk = k0 + (ch & 7) * 16;
         const bool ok = ch < XCH && gj < g.L && gk < g.K;
-        const u4v v = *reinterpret_cast<const u4v*>(g.X + (ok ? gj * g.ldx + gk : 0));
-        rx[q] = ok ? v : u4v{0u, 0u, 0u, 0u};
+        rx[q] = *reinterpret_cast<const u4v*>(g.X + (ok ? gj * g.ldx + gk : 0));
       }
     };
-    auto sstore = [&](int buf) {
+    // zero what the loads of k-step kt read from outside the operands
+    auto gmask = [&](int64_t kt) {
+      const int64_t k0 = kt * BK;
+      if (!TRANS) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const int ch = tid + q * NT;
+          const int64_t gi = row0 + (ch >> 3);
+          const int64_t gk = k0 + (ch & 7) * 16;
+          const bool ok = gi < g.M && gk < g.K;
+          const int64_t nb = g.K - gk;          // bytes of the chunk inside the row
+#pragma unroll
+          for (int w = 0; w < 4; ++w) ra[q][w] &= ok ? byte_mask(nb - 4 * w) : 0u;
+        }
+      } else {
+        const int64_t gi = row0 + 4 * ir;
+        const uint32_t im = byte_mask(g.M - gi);
+#pragma unroll
+        for (int q = 0; q < APT; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gk = k0 + KR * kq + 4 * q + r;
+            ra[q][r] &= gk < g.K ? im : 0u;
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) {
+        const int ch = tid + q * NT;
+        const int64_t gj = col0 + (ch >> 3);
+        const int64_t gk = k0 + (ch & 7) * 16;
+        const bool ok = ch < XCH && gj < g.L && gk < g.K;
+        rx[q] = ok ? rx[q] : u4v{0u, 0u, 0u, 0u};
+      }
+    };
+    auto sstore = [&](int buf, int64_t kt) {
+      gmask(kt);
       if (!TRANS) {
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
@@ -192,20 +221,23 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
 #pragma unroll
       for (int q = 0; q < XPT; ++q) {
         const int ch = tid + q * NT;
-        if (ch < XCH) *reinterpret_cast<u4v*>(&Xs[buf][(ch >> 3) * KP + (ch & 7) * 16]) = rx[q];
+        *reinterpret_cast<u4v*>(&Xs[buf][(ch >> 3) * KP + (ch & 7) * 16]) = rx[q];
       }
     };
 
     gload(kb);
-    sstore(0);
+    sstore(0, kb);
     __syncthreads();
     int buf = 0;
     for (int64_t kt = kb; kt < ke; ++kt) {
-      const bool more = kt + 1 < ke;
+      const int64_t kn = kt + 1 < ke ? kt + 1 : kt;
       // unconditional (the last step loads its own k-step again): under a
       // branch the staged registers would become phis that the compiler
       // fills by copies, waiting for the loads before the products
-      gload(more ? kt + 1 : kt);
+      gload(kn);
+      // the loads go out before the products (left alone, the compiler sinks
+      // them to the stores that use them)
+      __builtin_amdgcn_sched_barrier(0);
       i8v av[RB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
@@ -227,7 +259,10 @@ __global__ __launch_bounds__(NT) void gemm_f8_kernel(F8Args g) {
           acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
               av[rb], bv, acc[rb][cb], 0, 0, 0, SCALE_ONE, 0, SCALE_ONE);
       }
-      if (more) sstore(buf ^ 1);
+      // the staged step goes to the other buffer after every product (on the
+      // last step too, where no one reads it): the wait for its loads goes here
+      __builtin_amdgcn_sched_barrier(0);
+      sstore(buf ^ 1, kn);
       __syncthreads();
       buf ^= 1;
     }
