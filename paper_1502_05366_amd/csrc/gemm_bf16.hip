@@ -680,40 +680,42 @@ hipError_t dispatch_bf16(const Bf16Args& g, int cbw, hipStream_t s) {
   }
 }
 
-// Xt[c * ldo + k] = bf16(X[k * ldi + c]) for c < cols, k < rows; the padding
-// k in [rows, ldo) is zero.  One thread per output element, k fastest.
-template <typename T>
+// Xt[c * ldo + k] = bf16(x) (MODE 0) or bf16(x - bf16(x)) (MODE 1: the low
+// part of a two-term BF16 split; the subtraction is exact in FP32), x =
+// X[k][c] rounded to FP32, for c < cols, k < rows; the padding k in [rows,
+// ldo) is zero.  One 64 x 64 tile per workgroup passes through LDS, so that
+// the reads (c contiguous) and the writes (k contiguous) are both coalesced.
+constexpr int TT = 64;
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void convert_bf16_kernel(const T* __restrict__ in, int64_t ldi,
                                                            int64_t rows, int cols,
                                                            uint16_t* __restrict__ out,
                                                            int64_t ldo) {
-  const int64_t total = (int64_t)cols * ldo;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / ldo);
-    const int64_t k = e - (int64_t)c * ldo;
-    out[e] = (k < rows) ? to_bf16((float)in[k * ldi + c]) : (uint16_t)0;
-  }
-}
-
-// Xt[c * ldo + k] = bf16(X[k][c] - bf16(X[k][c])): the low part of a two-term
-// BF16 split (the subtraction is exact in FP32).
-__global__ __launch_bounds__(256) void bf16_residual_kernel(const float* __restrict__ in,
-                                                            int64_t ldi, int64_t rows, int cols,
-                                                            uint16_t* __restrict__ out,
-                                                            int64_t ldo) {
-  const int64_t total = (int64_t)cols * ldo;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / ldo);
-    const int64_t k = e - (int64_t)c * ldo;
+  __shared__ uint16_t tile[TT][TT + 2];
+  const int64_t k0 = (int64_t)blockIdx.x * TT;
+  const int c0 = blockIdx.y * TT;
+  const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+  for (int i = hi; i < TT; i += 4) {
+    const int64_t k = k0 + i;
+    const int c = c0 + lo;
     uint16_t v = 0;
-    if (k < rows) {
-      const float x = in[k * ldi + c];
-      const float hi = __uint_as_float((uint32_t)to_bf16(x) << 16);
-      v = to_bf16(x - hi);
+    if (k < rows && c < cols) {
+      const float x = (float)in[k * ldi + c];
+      if (MODE == 0) {
+        v = to_bf16(x);
+      } else {
+        const float h = __uint_as_float((uint32_t)to_bf16(x) << 16);
+        v = to_bf16(x - h);
+      }
     }
-    out[e] = v;
+    tile[i][lo] = v;
+  }
+  __syncthreads();
+  for (int i = hi; i < TT; i += 4) {
+    const int c = c0 + i;
+    const int64_t k = k0 + lo;
+    if (c < cols && k < ldo) out[(int64_t)c * ldo + k] = tile[lo][i];
   }
 }
 
@@ -834,23 +836,21 @@ hipError_t launch_gemm_bf16_acc(bool trans, const uint16_t* A, int64_t lda, cons
 hipError_t launch_bf16_residual(const float* X, int64_t ldx, int64_t rows, int cols,
                                 uint16_t* out, int64_t ldo, hipStream_t s) {
   if (cols <= 0 || ldo <= 0) return hipSuccess;
-  int64_t grid = cdiv((int64_t)cols * ldo, 256);
-  if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(bf16_residual_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, ldx, rows,
-                     cols, out, ldo);
+  const dim3 grid((unsigned)cdiv(ldo, TT), (unsigned)cdiv(cols, TT));
+  hipLaunchKernelGGL((convert_bf16_kernel<float, 1>), grid, dim3(256), 0, s, X, ldx, rows, cols,
+                     out, ldo);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_bf16(bool in_f32, const void* in, int64_t ldi, int64_t rows, int cols,
                                uint16_t* out, int64_t ldo, hipStream_t s) {
   if (cols <= 0 || ldo <= 0) return hipSuccess;
-  int64_t grid = cdiv((int64_t)cols * ldo, 256);
-  if (grid > 8192) grid = 8192;
+  const dim3 grid((unsigned)cdiv(ldo, TT), (unsigned)cdiv(cols, TT));
   if (in_f32)
-    hipLaunchKernelGGL(convert_bf16_kernel<float>, dim3((unsigned)grid), dim3(256), 0, s,
-                       (const float*)in, ldi, rows, cols, out, ldo);
+    hipLaunchKernelGGL((convert_bf16_kernel<float, 0>), grid, dim3(256), 0, s, (const float*)in,
+                       ldi, rows, cols, out, ldo);
   else
-    hipLaunchKernelGGL(convert_bf16_kernel<double>, dim3((unsigned)grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((convert_bf16_kernel<double, 0>), grid, dim3(256), 0, s,
                        (const double*)in, ldi, rows, cols, out, ldo);
   return hipGetLastError();
 }

@@ -613,19 +613,45 @@ __global__ __launch_bounds__(256) void colscale_kernel(const uint32_t* tmax, int
   t[c] = m > 0.f ? m / 448.f : 1.f;
 }
 
-// Xt[c][k] = e4m3(X'(k, c) / t[c]); padding k in [rows, ldo) zero.
+// Xt[c][k] = e4m3(X'(k, c) / t[c]); padding k in [rows, ldo) zero.  One 64 x
+// 64 tile per workgroup: s_k X(k, c) goes through LDS (read with c
+// contiguous), the residual term and the code are formed with k contiguous
+// (the reads of prev and the writes of Xt), so all three are coalesced.  The
+// arithmetic is xval's, in its order.
+constexpr int TT = 64;
+
 template <typename TX>
 __global__ __launch_bounds__(256) void encode_kernel(const TX* __restrict__ X, int64_t ldx,
                                                      int64_t rows, int cols, const float* s,
                                                      const uint8_t* prev, int64_t ldp,
                                                      const float* t0, const float* t,
                                                      uint8_t* __restrict__ Xt, int64_t ldo) {
-  const int64_t total = (int64_t)cols * ldo;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / ldo);
-    const int64_t k = e - (int64_t)c * ldo;
-    Xt[e] = k < rows ? e4m3_from_float(xval(X, ldx, s, k, c, prev, ldp, t0) / t[c]) : (uint8_t)0;
+  __shared__ float tile[TT][TT + 1];
+  const int64_t k0 = (int64_t)blockIdx.x * TT;
+  const int c0 = blockIdx.y * TT;
+  const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+  for (int i = hi; i < TT; i += 4) {
+    const int64_t k = k0 + i;
+    const int c = c0 + lo;
+    float v = 0.f;
+    if (k < rows && c < cols) {
+      v = (float)X[k * ldx + c];
+      if (s) v *= s[k];
+    }
+    tile[i][lo] = v;
+  }
+  __syncthreads();
+  for (int i = hi; i < TT; i += 4) {
+    const int c = c0 + i;
+    const int64_t k = k0 + lo;
+    if (c >= cols || k >= ldo) continue;
+    uint8_t code = 0;
+    if (k < rows) {
+      float v = tile[lo][i];
+      if (prev) v -= t0[c] * e4m3_to_float(prev[(int64_t)c * ldp + k]);
+      code = e4m3_from_float(v / t[c]);
+    }
+    Xt[(int64_t)c * ldo + k] = code;
   }
 }
 
@@ -651,10 +677,9 @@ hipError_t quant_x(const TX* X, int64_t ldx, int64_t rows, int cols, const float
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(colscale_kernel, dim3(cb), dim3(256), 0, st, tmax, cols, t);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  int64_t grid = cdiv((int64_t)cols * ldo, 256);
-  if (grid > 16384) grid = 16384;
-  hipLaunchKernelGGL(encode_kernel<TX>, dim3((unsigned)grid), dim3(256), 0, st, X, ldx, rows,
-                     cols, s, prev, ldp, t0, t, Xt, ldo);
+  const dim3 grid((unsigned)cdiv(ldo, TT), (unsigned)cdiv(cols, TT));
+  hipLaunchKernelGGL(encode_kernel<TX>, grid, dim3(256), 0, st, X, ldx, rows, cols, s, prev, ldp,
+                     t0, t, Xt, ldo);
   return hipGetLastError();
 }
 
