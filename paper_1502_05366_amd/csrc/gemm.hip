@@ -243,8 +243,9 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 
 // Adds the partial sums of every tile that was split between workgroups.
 // Grid: (tile, chunk of FIX_CHUNK elements); each thread sums its elements
-// over the workgroups that covered the tile, in workgroup order.
-constexpr int FIX_CHUNK = 1024;
+// over the workgroups that covered the tile, in a fixed order (eight
+// interleaved chains, then their pairwise sums).
+constexpr int FIX_CHUNK = 256;
 
 template <typename TC, typename TO, int CBW>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
@@ -266,13 +267,13 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
     const int64_t r = row0 + e / BN;
     const int64_t c = col0 + e % BN;
     if (r >= g.M || c >= g.L) continue;
-    // four independent chains (workgroups w, w+1, w+2, w+3), added in a fixed
-    // order: the loads of four partial tiles are in flight at once
-    TC s[4] = {TC(0), TC(0), TC(0), TC(0)};
+    // eight independent chains (workgroups w .. w+7), added in a fixed order:
+    // the loads of eight partial tiles are in flight at once
+    TC s[8] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
     int64_t w = wf;
-    for (; w + 3 <= wl; w += 4) {
+    for (; w + 7 <= wl; w += 8) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int64_t wu = w + u;
         const bool ok = range_begin(wu, g.U, g.G) != range_begin(wu + 1, g.U, g.G);
         const int64_t slot = 2 * wu + (wu == wf ? 1 : 0);
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
       const int64_t slot = 2 * w + (w == wf ? 1 : 0);
       s[0] += P[slot * (int64_t)(BM * BN) + e];
     }
-    C[r * g.ldc + c] = (TO)((s[0] + s[1]) + (s[2] + s[3]));
+    C[r * g.ldc + c] = (TO)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
   }
 }
 
