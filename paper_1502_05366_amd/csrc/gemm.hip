@@ -242,10 +242,15 @@ __global__ __launch_bounds__(NT) void gemm_sk_kernel(GemmArgs g) {
 }
 
 // Adds the partial sums of every tile that was split between workgroups.
-// Grid: (tile, chunk of FIX_CHUNK elements); each thread sums its elements
+// Grid: (tile, chunk of the tile's elements); each thread sums its elements
 // over the workgroups that covered the tile, in a fixed order (eight
-// interleaved chains, then their pairwise sums).
-constexpr int FIX_CHUNK = 256;
+// interleaved chains, then their pairwise sums).  Chunks of FIX_CHUNK
+// elements, or of FIX_CHUNK_FEW (one element per thread) when there are too
+// few tiles to fill the chip: a reduction over a tall K splits each of a few
+// small output tiles across ~100 workgroups, and its latency then sets the
+// time.
+constexpr int FIX_CHUNK = 1024;
+constexpr int FIX_CHUNK_FEW = 256;
 
 template <typename TC, typename TO, int CBW>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
@@ -261,8 +266,9 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs g) {
   const int64_t col0 = (tile % g.nct) * BN;
   const TC* P = static_cast<const TC*>(g.part);
   TO* C = static_cast<TO*>(g.C);
-  const int e0 = blockIdx.y * FIX_CHUNK;
-  const int e1 = min(e0 + FIX_CHUNK, BM * BN);
+  const int chunk = (BM * BN + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int e0 = blockIdx.y * chunk;
+  const int e1 = min(e0 + chunk, BM * BN);
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t r = row0 + e / BN;
     const int64_t c = col0 + e % BN;
@@ -297,7 +303,8 @@ hipError_t run(const GemmArgs& g, hipStream_t s) {
   // with one workgroup per tile every range is a whole tile: no fix-up
   const int64_t T = g.U / g.KI;
   if (g.G != T) {
-    const unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    unsigned nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK);
+    if (T * nch < 4 * 256) nch = (unsigned)cdiv(BM * 32 * CBW, FIX_CHUNK_FEW);
     hipLaunchKernelGGL((gemm_fixup_kernel<TC, TO, CBW>), dim3((unsigned)T, nch), dim3(256), 0, s,
                        g);
     e = hipGetLastError();

@@ -469,15 +469,51 @@ __global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restri
   V[e] = (in && i == j) ? 1.0 : 0.0;
 }
 
-__global__ __launch_bounds__(JNT) void jacobi_finish_kernel(const double* __restrict__ W,
-                                                            const double* __restrict__ V,
-                                                            int64_t ld, int l, int k,
-                                                            double* __restrict__ S,
-                                                            double* __restrict__ Uh, int64_t lduh,
-                                                            double* __restrict__ Vh,
-                                                            int64_t ldvh) {
-  __shared__ double sig[JACOBI_MAX_L];
-  jacobi_finish<JNT>(W, V, ld, l, k, sig, S, Uh, lduh, Vh, ldvh);
+// The output of the block iteration spread over the chip (one wave per
+// column; the single-workgroup jacobi_finish took ~0.6 ms at l = 576, its
+// row-strided writes of Uh and Vh issued from one compute unit).  First
+// sigma_j = ||w_j|| into sig, then each column's rank among the sigma
+// (descending, ties by index) and, for the k largest, S, Uh and Vh.  The
+// arithmetic is jacobi_finish's.
+constexpr int JOW = 8;   // waves (columns) per workgroup
+
+__global__ __launch_bounds__(64 * JOW) void jacobi_sig_kernel(const double* __restrict__ W,
+                                                              int64_t ld, int l,
+                                                              double* __restrict__ sig) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * JOW + (threadIdx.x >> 6);
+  if (j >= l) return;   // (a whole wave)
+  double s2 = 0.0;
+  for (int i = lane; i < l; i += 64) {
+    const double x = W[j * ld + i];
+    s2 += x * x;
+  }
+  s2 = wave_sum(s2);
+  if (lane == 0) sig[j] = sqrt(s2);
+}
+
+__global__ __launch_bounds__(64 * JOW) void jacobi_out_kernel(
+    const double* __restrict__ W, const double* __restrict__ V, int64_t ld, int l, int k,
+    const double* __restrict__ sig, double* __restrict__ S, double* __restrict__ Uh, int64_t lduh,
+    double* __restrict__ Vh, int64_t ldvh) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * JOW + (threadIdx.x >> 6);
+  if (j >= l) return;   // (a whole wave)
+  const double sj = sig[j];
+  int rank = 0;
+  for (int i = lane; i < l; i += 64) {
+    const double si = sig[i];
+    rank += (si > sj || (si == sj && i < j)) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rank += __shfl_xor(rank, off, 64);
+  if (rank >= k) return;
+  if (lane == 0) S[rank] = sj;
+  const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+  for (int i = lane; i < l; i += 64) {
+    Uh[(int64_t)i * lduh + rank] = W[j * ld + i] * inv;
+    Vh[(int64_t)i * ldvh + rank] = V[j * ld + i];
+  }
 }
 
 }  // namespace
@@ -494,9 +530,9 @@ static int jac_cols(int l) {
 }
 
 size_t jacobi_work_bytes(int l) {
-  // W, V (padded) and the control words of the block iteration
+  // W, V (padded), the control words of the block iteration and the l sigma
   return 2 * (size_t)jac_rows(l) * jac_cols(l) * sizeof(double) +
-         JCTL * FLAG_STRIDE * sizeof(uint32_t) + 256;
+         JCTL * FLAG_STRIDE * sizeof(uint32_t) + (size_t)l * sizeof(double) + 256;
 }
 
 template <int JRPL, int NW>
@@ -551,8 +587,12 @@ hipError_t launch_jacobi(const double* Rh, int64_t ldr, int l, int k, double* wo
   if (e != hipSuccess) return e;
   e = (l <= 256) ? launch_block<16, 8>(a, s) : launch_block<40, 8>(a, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(JNT), 0, s, W, V, ld, l, k, S, Uh,
-                     lduh, Vh, ldvh);
+  double* sig = reinterpret_cast<double*>(ctl + JCTL * FLAG_STRIDE);
+  const unsigned nwg = (unsigned)cdiv(l, JOW);
+  hipLaunchKernelGGL(jacobi_sig_kernel, dim3(nwg), dim3(64 * JOW), 0, s, W, ld, l, sig);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(jacobi_out_kernel, dim3(nwg), dim3(64 * JOW), 0, s, W, V, ld, l, k, sig, S,
+                     Uh, lduh, Vh, ldvh);
   return hipGetLastError();
 }
 
