@@ -38,7 +38,7 @@ PEAK_FP8_TFLOPS = 5000.0
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs of this
 # script, each scaled by counter/bytes of the plain 1 GiB copy kernel timed
 # below; valid only while the pass kernel's sources hash to "sources".
-PASS_TRAFFIC = {"sources": "baf0db1c7f08f848d5380b86553cc21cd9fdf5f7e6d1b92541de1f3d114cecdf",
+PASS_TRAFFIC = {"sources": "fc2a4138c2a8871c57e6d256b627da01351229dcf28ef61f39e02b7dbe4b90c7",
                 "bytes": 4589000000}
 PASS_SOURCES = ("paper_1502_05366_amd/csrc/gemm.hip",)
 

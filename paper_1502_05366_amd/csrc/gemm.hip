@@ -337,8 +337,12 @@ hipError_t dispatch_trans(const GemmArgs& g, bool trans, int cbw, hipStream_t s)
 
 GemmPlan plan_gemm(int64_t M, int64_t K, int64_t L, int ncu, int force_G) {
   GemmPlan p;
+  // the fewest column tiles of at most 256 columns, as even as 32-column
+  // steps allow (l = 576: three tiles of 192, not 256 + 256 + 64 with a
+  // quarter of the products on padding)
   const int64_t ncb = cdiv(L, 16);
-  p.cbw = ncb <= 16 ? (int)cdiv(ncb, 2) : 8;
+  const int64_t nct = cdiv(ncb, 16);
+  p.cbw = (int)cdiv(ncb, 2 * nct);
   if (p.cbw < 1) p.cbw = 1;
   const int64_t BN = 32 * p.cbw;
   p.nrt = cdiv(M, BM);
