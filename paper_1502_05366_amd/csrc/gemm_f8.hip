@@ -18,16 +18,18 @@
 // deterministic partial tiles and a fix-up kernel that applies the scales;
 // BM = 128 rows, BN = 32 * CBW columns (CBW <= 9, so l = 576 takes two column
 // tiles), BK = 128 bytes (one matrix-core depth), 8 waves (4 along M x 2
-// along L), each wave 2 x CBW accumulator tiles (the 256 registers per lane of
-// two waves per SIMD hold 144 accumulators at CBW = 9).
+// along L), each wave 2 x CBW accumulator tiles (72 accumulator registers per
+// lane at CBW = 9, within the 256 of two waves per SIMD).
 //
 // MFMA operand layout (16 x 16 x 128, lane l, g = l / 16, c = l % 16): lane
 // l holds 32 consecutive k of row c of the A operand and the same 32 k of
 // column c of the B operand (k = 32 g .. 32 g + 31); D: lane l element v
 // holds D[4 g + v][c].  Both operands sit in LDS with k contiguous ([row][k]
-// for A, [col][k] for Xt), rows padded to 144 bytes.  A transposed pass (A
-// stored K x M) transposes 4 x 4 byte blocks in registers on the way into
-// LDS.
+// for A, [col][k] for Xt): staged through registers with rows padded to 144
+// bytes, or (Y = A X with K a multiple of 128, gemm_f8_dma_kernel) loaded
+// straight into LDS in unpadded rows with rotated 16-byte chunks.  A
+// transposed pass (A stored K x M) transposes 4 x 4 byte blocks in registers
+// on the way into LDS.
 #include "common.h"
 #include "internal.h"
 
