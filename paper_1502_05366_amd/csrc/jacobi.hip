@@ -102,21 +102,42 @@ struct JacArgs {
   int32_t* sweeps_out;
 };
 
+// spin until workgroup v has completed `target` rounds (bounded: past the cap
+// the wait gives up, raises the abort flag and INFO_BARRIER)
+__device__ void jac_wait_tag(const JacArgs& a, int v, uint32_t target) {
+  uint32_t spins = 0;
+  while (ld_agent_u32(a.tags + v * FLAG_STRIDE) < target + a.wait_bias) {
+    if ((++spins & 63) == 0) {
+      if (ld_agent_u32(a.abort_flag)) break;
+      if (spins > a.spin_cap) {
+        st_agent_u32(a.abort_flag, 1u);
+        info_or(a.info, INFO_BARRIER);
+        break;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 __device__ void jac_wait_all(const JacArgs& a, uint32_t target) {
   const int tid = threadIdx.x;
+  if (tid < a.G) jac_wait_tag(a, tid, target);
+  __syncthreads();
+}
+
+// Before round r + 1 of a sweep, workgroup w needs only its two blocks of
+// that round, written back by the workgroups that held them in round r: it
+// waits for those (so the workgroups drift apart by a few rounds instead of
+// all waiting for the slowest one every round).  A block's owners follow
+// each other round by round, so every block is read after the previous
+// owner's writes and written after its reads.
+__device__ void jac_wait_owners(const JacArgs& a, uint32_t target, int r, int w) {
+  const int tid = threadIdx.x;
   if (tid < a.G) {
-    uint32_t spins = 0;
-    while (ld_agent_u32(a.tags + tid * FLAG_STRIDE) < target + a.wait_bias) {
-      if ((++spins & 63) == 0) {
-        if (ld_agent_u32(a.abort_flag)) break;
-        if (spins > a.spin_cap) {
-          st_agent_u32(a.abort_flag, 1u);
-          info_or(a.info, INFO_BARRIER);
-          break;
-        }
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
+    const int nb = a.nbp;
+    const int b1 = rr_player(w, r + 1, nb), b2 = rr_player(nb - 1 - w, r + 1, nb);
+    const int p1 = rr_player(tid, r, nb), p2 = rr_player(nb - 1 - tid, r, nb);
+    if (p1 == b1 || p1 == b2 || p2 == b1 || p2 == b2) jac_wait_tag(a, tid, target);
   }
   __syncthreads();
 }
@@ -252,11 +273,15 @@ __global__ __launch_bounds__(64 * NW) void jacobi_block_kernel(JacArgs a) {
       {
         double* T = Ts + wave * JJ * TLD;
         d4 axx = Mfma<double>::zero(), axy = Mfma<double>::zero(), ayy = Mfma<double>::zero();
+        // (the area is the wave's own and one wave's LDS accesses complete in
+        // order: a wave barrier keeps the compiler from moving them)
 #pragma unroll
         for (int t = 0; t < RTW; ++t) {
 #pragma unroll
           for (int kk = 0; kk < 8; ++kk) T[(4 * kk + lg) * TLD + li] = wu[t][kk];
-          __syncthreads();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const double x = T[li * TLD + 4 * k + lg], y = T[(BS + li) * TLD + 4 * k + lg];
@@ -264,7 +289,9 @@ __global__ __launch_bounds__(64 * NW) void jacobi_block_kernel(JacArgs a) {
             axy = Mfma<double>::mma(x, y, axy);
             ayy = Mfma<double>::mma(y, y, ayy);
           }
-          __syncthreads();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -435,7 +462,9 @@ __global__ __launch_bounds__(64 * NW) void jacobi_block_kernel(JacArgs a) {
       __syncthreads();
       ++done;
       if (tid == 0) st_agent_u32(a.tags + w * FLAG_STRIDE, done);
-      jac_wait_all(a, done);
+      // the sweep's end needs every workgroup's rotation flag
+      if (last) jac_wait_all(a, done);
+      else jac_wait_owners(a, done, r, w);
     }
     // every workgroup reads the same flags, so all take the same decision
     uint32_t any = 0;
