@@ -598,13 +598,31 @@ __global__ __launch_bounds__(256) void colmax_kernel(const TX* __restrict__ X, i
                                                      int64_t rows, int cols, const float* s,
                                                      const uint8_t* prev, int64_t ldp,
                                                      const float* t0, uint32_t* tmax) {
+  __shared__ float part[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
   const int rg = threadIdx.x >> 6;
-  if (c >= cols) return;
-  float m = 0.f;
-  for (int64_t k = blockIdx.y * 4 + rg; k < rows; k += (int64_t)gridDim.y * 4)
-    m = fmaxf(m, fabsf(xval(X, ldx, s, k, c, prev, ldp, t0)));
-  atomicMax(tmax + c, __float_as_uint(m));
+  // four independent maxima (a maximum does not depend on the order), so
+  // that four loads per thread are in flight
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+  if (c < cols) {
+    const int64_t st = (int64_t)gridDim.y * 4;
+    int64_t k = blockIdx.y * 4 + rg;
+    for (; k + 3 * st < rows; k += 4 * st) {
+      m0 = fmaxf(m0, fabsf(xval(X, ldx, s, k, c, prev, ldp, t0)));
+      m1 = fmaxf(m1, fabsf(xval(X, ldx, s, k + st, c, prev, ldp, t0)));
+      m2 = fmaxf(m2, fabsf(xval(X, ldx, s, k + 2 * st, c, prev, ldp, t0)));
+      m3 = fmaxf(m3, fabsf(xval(X, ldx, s, k + 3 * st, c, prev, ldp, t0)));
+    }
+    for (; k < rows; k += st) m0 = fmaxf(m0, fabsf(xval(X, ldx, s, k, c, prev, ldp, t0)));
+  }
+  part[rg][threadIdx.x & 63] = fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
+  __syncthreads();
+  // one atomic per column and workgroup
+  if (rg == 0 && c < cols) {
+    const int i = threadIdx.x;
+    const float m = fmaxf(fmaxf(part[0][i], part[1][i]), fmaxf(part[2][i], part[3][i]));
+    atomicMax(tmax + c, __float_as_uint(m));
+  }
 }
 
 // t[c] = tmax[c] / 448 (1 for a zero column)
