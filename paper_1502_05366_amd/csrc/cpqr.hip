@@ -423,7 +423,12 @@ __global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__
   const bool cok = col < nrhs;
   const double* bc = Bm + (cok ? col : 0) * b_c;
   double* xc = X + (cok ? col : 0) * x_c;
+  // The loads of a block step are unconditional, from clamped indices, with
+  // a select after them (under a branch each load was waited for at once);
+  // blocks past nb contribute zeros (their X blocks start at zero).
   d4 xt[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) xt[c] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = NB - 1; c >= 0; --c) {
     if (c < nb) {
@@ -431,17 +436,17 @@ __global__ __launch_bounds__(256) void backsub_kernel(const double* __restrict__
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = c * 16 + 4 * v + lk;
-        acc[v] = (cok && i < k) ? bc[i * b_r] : 0.0;
+        const double bv = bc[min(i, k - 1) * b_r];
+        acc[v] = (cok && i < k) ? bv : 0.0;
       }
 #pragma unroll
       for (int b = c + 1; b < NB; ++b) {
-        if (b < nb) {
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int i = c * 16 + li, j = b * 16 + 4 * kk + lk;
-            const double av = (i < k && j < k) ? -S[i * s_r + j * s_c] : 0.0;   // S_cb[li][k]
-            acc = Mfma<double>::mma(av, xt[b][kk], acc);
-          }
+        for (int kk = 0; kk < 4; ++kk) {
+          const int i = c * 16 + li, j = b * 16 + 4 * kk + lk;
+          const double sv = S[min(i, k - 1) * s_r + min(j, k - 1) * s_c];
+          const double av = (i < k && j < k) ? -sv : 0.0;   // S_cb[li][k]
+          acc = Mfma<double>::mma(av, xt[b][kk], acc);
         }
       }
       d4 out = d4{0.0, 0.0, 0.0, 0.0};
