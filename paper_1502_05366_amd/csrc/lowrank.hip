@@ -55,24 +55,32 @@ __global__ __launch_bounds__(LR_NT) void lowrank_kernel(LowRank t, int64_t m, in
   const int kpt = (l + LR_KC - 1) / LR_KC;   // chunks per term
   const int nch = t.count * kpt;
 
+  // Loads are unconditional, from clamped indices; what lies outside the
+  // factors or the matrix is zeroed later, when it is used (a branch around a
+  // load, or a select right after it, makes the compiler wait for the load
+  // there, one load at a time).
   double xv[4], wv[4];
   auto gload = [&](int c) {
     const int term = c / kpt;
     const int k0 = (c - term * kpt) * LR_KC + lq;
     const double* X = t.X[term];
     const double* W = t.W[term];
+    const int64_t xr = xok ? xrow : m - 1, wr_ = wok ? wrow : n - 1;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int k = k0 + i;
-      xv[i] = (xok && k < l) ? X[xrow * t.ldx + k] : 0.0;
-      wv[i] = (wok && k < l) ? W[wrow * t.ldw + k] : 0.0;
+      const int k = min(k0 + i, l - 1);
+      xv[i] = X[xr * t.ldx + k];
+      wv[i] = W[wr_ * t.ldw + k];
     }
   };
-  auto sstore = [&](int b) {
+  auto sstore = [&](int b, int c) {
+    const int term = c / kpt;
+    const int k0 = (c - term * kpt) * LR_KC + lq;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      Xs[b][lr * LR_LD + lq + i] = xv[i];
-      Ws[b][lr * LR_LD + lq + i] = wv[i];
+      const bool kin = k0 + i < l;
+      Xs[b][lr * LR_LD + lq + i] = (xok && kin) ? xv[i] : 0.0;
+      Ws[b][lr * LR_LD + lq + i] = (wok && kin) ? wv[i] : 0.0;
     }
   };
 
@@ -83,11 +91,15 @@ __global__ __launch_bounds__(LR_NT) void lowrank_kernel(LowRank t, int64_t m, in
     for (int ct = 0; ct < 4; ++ct) acc[rb][ct] = d4{0.0, 0.0, 0.0, 0.0};
 
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    const bool more = c + 1 < nch;
-    if (more) gload(c + 1);
+    // the next chunk (the last one again at the end: unconditional, so the
+    // staged registers are not phis); its loads go out before the products
+    // and are waited for at the store after them
+    const int cn = c + 1 < nch ? c + 1 : c;
+    gload(cn);
+    __builtin_amdgcn_sched_barrier(0);
     const double* xs = Xs[c & 1];
     const double* ws = Ws[c & 1];
 #pragma unroll
@@ -102,10 +114,28 @@ __global__ __launch_bounds__(LR_NT) void lowrank_kernel(LowRank t, int64_t m, in
         acc[1][ct] = Mfma<double>::mma(a1, bv, acc[1][ct]);
       }
     }
-    if (more) sstore((c + 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
+    sstore((c + 1) & 1, cn);   // (past the last chunk: a buffer no one reads)
     __syncthreads();
   }
 
+  // the tile's entries of A (for OUT without dres, of out itself, unused),
+  // all loads issued before any is used
+  const bool needA = (MODE != LR_OUT) || (dres != nullptr);
+  const double* Ab = needA ? A : out;
+  const int64_t ldb = needA ? lda : ldo;
+  double av[2][4][4];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int64_t col = min(col0 + wc + ct * 16 + li, n - 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = min(row0 + wr + rb * 16 + drow(lk, v), m - 1);
+        av[rb][ct][v] = Ab[row * ldb + col];
+      }
+    }
   const double alpha = (MODE == LR_OUT && dres) ? 2.0 * dres[0] : 0.0;
   double s = 0.0;
 #pragma unroll
@@ -116,17 +146,15 @@ __global__ __launch_bounds__(LR_NT) void lowrank_kernel(LowRank t, int64_t m, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + wr + rb * 16 + drow(lk, v);
-        if (row < m && col < n) {
-          const double p = acc[rb][ct][v];
-          if (MODE == LR_OUT) {
-            double x = p;
-            if (dres) x = fma(alpha, A[row * lda + col], x);
-            out[row * ldo + col] = x;
-          } else {
-            const double x = A[row * lda + col] - p;
-            if (MODE == LR_SUB) A[row * lda + col] = x;
-            s = fma(x, x, s);
-          }
+        const bool ok = row < m && col < n;
+        const double p = acc[rb][ct][v];
+        if (MODE == LR_OUT) {
+          if (ok) out[row * ldo + col] = dres ? fma(alpha, av[rb][ct][v], p) : p;
+        } else {
+          // (a zero outside the matrix leaves the sum as it is)
+          const double x = ok ? av[rb][ct][v] - p : 0.0;
+          if (MODE == LR_SUB && ok) A[row * lda + col] = x;
+          s = fma(x, x, s);
         }
       }
     }
